@@ -1,0 +1,182 @@
+/* lnocc.h -- C ABI of the MI355X fragment solver for periodic LNO-CCSD(T).
+ *
+ * The library solves the problem that each LNO fragment poses (Ye and
+ * Berkelbach, "Periodic local coupled-cluster theory for insulators and
+ * metals", Sec. II.B): given the local Hamiltonian of an active space, i.e.
+ * the semi-canonical Fock diagonal (Eq. 11 restricted to the active orbitals;
+ * occupied and virtual orbitals are rotated separately, so the Fock matrix is
+ * diagonal with no occupied-virtual block) and real three-index
+ * density-fitting factors B[Q,p,q] with (pq|rs) = sum_Q B[Q,p,q] B[Q,r,s]
+ * (Eq. 27a with the momentum sum folded into Q), it returns the CCSD
+ * amplitudes t_ia, t_iajb, the CCSD correlation energy (Eq. 7) and the
+ * perturbative triples energy (Eq. 16 summed at i = i' with the intermediates
+ * of SI Sec. S1).
+ *
+ * Conventions common to every entry point
+ *  - Orbitals are ordered occupied first; n = nocc + nvir.
+ *  - Arrays are row-major FP64 in device memory unless stated otherwise.
+ *  - t1[i][a] = t_i^a; t2[i][j][a][b] = t_ij^ab (= t_iajb of the paper),
+ *    which satisfies t2[i][j][a][b] = t2[j][i][b][a].
+ *  - The caller owns every buffer.  The library allocates no device memory:
+ *    all scratch comes from the workspace the caller passes in options.
+ *  - Work is enqueued on options.stream (a hipStream_t; NULL = default
+ *    stream).  Every entry point returns after that stream has completed the
+ *    work, so host-side outputs are valid on return.
+ *  - Calls that share one workspace must not overlap.
+ *  - Status codes < 0 are errors (outputs undefined); > 0 are warnings
+ *    (outputs valid).  Argument errors are detected on the host before any
+ *    device work is enqueued.
+ */
+#ifndef LNOCC_H
+#define LNOCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LNOCC_ABI_VERSION 1
+
+typedef enum {
+  LNOCC_OK = 0,
+  LNOCC_NOT_CONVERGED = 1, /* max_iter reached; last iterate returned */
+  LNOCC_EINVAL = -1,       /* bad argument (null pointer, size, gap, tolerance) */
+  LNOCC_ENOMEM = -2,       /* workspace missing or smaller than required */
+  LNOCC_EDEVICE = -3,      /* a HIP call failed */
+  LNOCC_ENUMERIC = -4      /* a non-finite residual or energy appeared */
+} lnocc_status_t;
+
+/* Arithmetic of the two dominant contractions (the particle-particle ladder
+ * of the CCSD residual and the W contraction of (T)).  Energies, denominators,
+ * residual norms and DIIS stay FP64 in every mode. */
+typedef enum {
+  LNOCC_FP64 = 0,
+  LNOCC_FP32 = 1, /* FP32 matrix-core products, FP32 accumulation per tile */
+  LNOCC_BF16 = 2  /* BF16 matrix-core products (round to nearest even), FP32 accumulation */
+} lnocc_precision_t;
+
+typedef enum {
+  LNOCC_GUESS_MP2 = 0,  /* T1 = 0, T2 = MP1 amplitudes (Eq. 21 with i_F over all occupied) */
+  LNOCC_GUESS_USER = 1  /* start from the caller's t1 / t2 buffers (restart) */
+} lnocc_guess_t;
+
+/* One fragment problem and its results. */
+typedef struct lnocc_fragment_t {
+  int32_t nocc, nvir, naux;  /* active occupied, active virtual, auxiliary functions */
+  int32_t reserved0;
+  const double *B;           /* device [naux][n][n]; B[Q][p][q] == B[Q][q][p] is assumed */
+  const double *eps_occ;     /* device [nocc], semi-canonical occupied energies (Hartree) */
+  const double *eps_vir;     /* device [nvir], semi-canonical virtual energies;
+                                every eps_occ must lie below every eps_vir */
+  double conv_tol;           /* > 0; converged when ||t_new - t_old||_2 <= conv_tol over
+                                the whole t1 and t2 arrays (Jacobi step, before DIIS) */
+  double *t1;                /* device [nocc][nvir]: out (in with LNOCC_GUESS_USER) */
+  double *t2;                /* device [nocc][nocc][nvir][nvir]: out (in with LNOCC_GUESS_USER) */
+  /* host-side outputs */
+  double e_mp2;              /* MP2 correlation energy (Eq. 7 at the MP1 amplitudes, T1 = 0) */
+  double e_ccsd;             /* CCSD correlation energy (Eq. 7, tau = t2 + t1 t1) */
+  double e_t;                /* (T) energy; 0 when triples are off */
+  double residual;           /* last ||t_new - t_old||_2 */
+  int32_t n_iter;            /* CCSD iterations taken */
+  int32_t status;            /* lnocc_status_t of this fragment */
+} lnocc_fragment_t;
+
+typedef struct lnocc_options_t {
+  int32_t precision;         /* lnocc_precision_t */
+  int32_t guess;             /* lnocc_guess_t */
+  int32_t do_triples;        /* nonzero: compute E_(T) after CCSD */
+  int32_t max_iter;          /* >= 0; 0 = no CCSD update (energy of the starting amplitudes) */
+  int32_t diis_space;        /* 1..16 stored vectors; 1 disables extrapolation */
+  int32_t diis_start;        /* first iteration that extrapolates (>= 1) */
+  void *stream;              /* hipStream_t */
+  void *workspace;           /* device scratch, >= lnocc_workspace_bytes(...) bytes, 256-byte aligned */
+  size_t workspace_bytes;
+  size_t ladder_chunk_bytes; /* cap on the (ac|bd) block formed at a time; 0 = 8 GiB */
+  int32_t triples_batch;     /* unique (i<=j<=k) triples per (T) pass; 0 = automatic */
+  int32_t reserved1;
+} lnocc_options_t;
+
+/* Fills *opt with defaults: FP64, MP2 guess, triples on, max_iter 100,
+ * DIIS space 8 from iteration 2, default stream, no workspace. */
+void lnocc_default_options(lnocc_options_t *opt);
+
+/* Human-readable name of a status code; never NULL. */
+const char *lnocc_status_string(int status);
+
+/* Workspace bytes needed to solve the nfrag fragments of f (one at a time,
+ * reusing the workspace) with *opt.  Writes 0 and returns LNOCC_EINVAL for bad
+ * sizes; host-only, touches no device memory or pointer inside f. */
+int lnocc_workspace_bytes(const lnocc_fragment_t *f, int32_t nfrag,
+                          const lnocc_options_t *opt, size_t *bytes);
+
+/* Fragment CCSD (Sec. II.B: CCSD with the fragment Hamiltonian) followed by
+ * (T) (Eq. 16 at i = i', SI Sec. S1) when opt->do_triples.  Starts from the
+ * MP1 guess (Eq. 21) or the caller's amplitudes, iterates Jacobi steps with
+ * Pulay DIIS until the residual norm falls to f->conv_tol, writes t1 / t2 and
+ * the host outputs of *f, and returns f->status. */
+int lnocc_fragment_ccsd(lnocc_fragment_t *f, const lnocc_options_t *opt);
+
+/* (T) energy (Eq. 16 at i = i' summed over i; W, V and Delta of SI Sec. S1)
+ * of the amplitudes already in f->t1 / f->t2.  Writes f->e_t and returns the
+ * status. */
+int lnocc_fragment_triples(lnocc_fragment_t *f, const lnocc_options_t *opt);
+
+/* CCSD residuals R1[i][a] = <Phi_i^a| e^{-T} H e^{T} |HF> and
+ * R2[i][j][a][b] = <Phi_{i alpha j beta}^{a alpha b beta}| e^{-T} H e^{T} |HF>
+ * of the fragment Hamiltonian (Eq. 10) at the amplitudes in f->t1 / f->t2,
+ * written to the device arrays r1 [nocc][nvir] and r2 [nocc][nocc][nvir][nvir].
+ * This is the quantity the solver drives to zero. */
+int lnocc_ccsd_residuals(lnocc_fragment_t *f, const lnocc_options_t *opt,
+                         double *r1, double *r2);
+
+/* Solves nfrag independent fragments (the sum over fragments of Eq. 8/13 needs
+ * each one; fragments do not interact) with one workspace sized by
+ * lnocc_workspace_bytes(f, nfrag, opt).  Per-fragment results are written to
+ * f[k]; returns the most severe status (errors before warnings). */
+int lnocc_batch_solve(lnocc_fragment_t *f, int32_t nfrag, const lnocc_options_t *opt);
+
+/* ---- building block -------------------------------------------------------
+ * Batched two-index-mode tensor contraction used for every DF product
+ * (Eq. 27a: sums over the auxiliary index) and amplitude contraction:
+ *   C[m,n] = sum_s scale_s sum_k A_s(m,k) B_s(n,k) + beta C[m,n]
+ * where m = mo*Mi + mi, n = no*Ni + ni, k = ko*Ki + ki and each operand gives
+ * one stride per index.  Batch entry e decodes to (e / nb1, e % nb1, 0) and
+ * moves each base pointer by b0*(e / nb1) + b1*(e % nb1) + bid*e.  All strides
+ * are in elements.  FP64 in and out. */
+typedef struct lnocc_operand_t {
+  const double *p;
+  int64_t s_ro, s_ri, s_ko, s_ki;
+  int64_t b0, b1, bid;
+} lnocc_operand_t;
+
+typedef struct lnocc_contract_t {
+  int32_t M, Mi, N, Ni;
+  int32_t nseg;                  /* 1..4 */
+  int32_t K[4], Ki[4];
+  double scale[4];
+  lnocc_operand_t a[4], b[4];
+  double *c;
+  int64_t c_mo, c_mi, c_no, c_ni, c_b0, c_b1, c_bid;
+  double beta;
+  int32_t batch, nb1;
+} lnocc_contract_t;
+
+int lnocc_contract(const lnocc_contract_t *desc, void *stream);
+
+/* ---- validation mode -------------------------------------------------------
+ * on != 0: every later call runs its host logic and launch sequence without
+ * touching a device.  Each contraction launch is checked to stay inside the
+ * workspace and the caller's arrays (sizes from the fragment shape) and fails
+ * with LNOCC_EDEVICE otherwise; device readbacks read as zeros, so a solve
+ * stops after one iteration and then runs every (T) pass.  The spectrum check
+ * is skipped.  Pointers are never dereferenced in this mode.  Process-wide;
+ * not for use while other threads solve. */
+void lnocc_set_validation_mode(int on);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LNOCC_H */

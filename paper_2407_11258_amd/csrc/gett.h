@@ -1,0 +1,75 @@
+// Generic batched tensor contraction ("GETT") on gfx950 matrix cores.
+//
+// C[m, n] (+)= sum_seg scale_seg * sum_k A_seg(m, k) * B_seg(k, n)
+//
+// Each of the M, N and K modes is a pair of tensor indices: m = m_o * Mi + m_i
+// (likewise n with Ni and k with Ki), and every operand gives one stride per
+// index, so any contraction with at most two indices per mode is expressed
+// without a permuted copy.  Several K segments (different operands, same C)
+// accumulate in registers before the single store.  A batch index is decoded
+// into up to three integers (from a table of int triples or as id / nb1,
+// id % nb1); every base pointer moves by a linear combination of them.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lnocc {
+
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
+
+struct GOperand {
+  const void *p;          // element type given by GemmDesc::in_type
+  int64_t s_ro, s_ri;     // strides of the outer / inner row (m or n) index
+  int64_t s_ko, s_ki;     // strides of the outer / inner contraction index
+  int64_t b0, b1, b2;     // pointer offset per unit of each batch integer
+  int64_t bid;            // pointer offset per unit of the batch entry number
+};
+
+struct GSegment {
+  GOperand a;             // rows = m
+  GOperand b;             // rows = n (the operand is addressed as B(n, k))
+  int K, Ki;              // contraction length and inner extent (k = ko*Ki + ki)
+  double scale;           // multiplies the A operand
+  int a_kfast, b_kfast;   // set by gett(): operand contiguous along k
+};
+
+constexpr int kMaxSeg = 4;
+
+struct GemmDesc {
+  int M, Mi, N, Ni;
+  int nseg;
+  GSegment seg[kMaxSeg];
+  double *c;              // output, always FP64
+  int64_t c_mo, c_mi, c_no, c_ni, c_b0, c_b1, c_b2, c_bid;
+  double beta;            // 0: C is overwritten without being read
+  int batch;              // number of batch entries (>= 1)
+  int nb1;                // id -> (id / nb1, id % nb1, 0) when table == nullptr
+  const int *table;       // device int triples, batch entry id -> (i0, i1, i2)
+  int tmax[3];            // with a table: largest value of each batch integer
+  Prec prec;              // arithmetic of the products (inputs are FP64 in memory)
+};
+
+// Address guard.  While a region list is installed (per host thread), gett()
+// refuses to launch a contraction unless every address it can touch lies
+// inside one listed region.  The solver installs the workspace and the
+// caller's arrays; a descriptor mistake then becomes an error, not a fault.
+struct Region { const void *p; size_t bytes; };
+void install_regions(const Region *r, int n);   // n = 0 removes the list
+
+// Validation mode: launches are checked against the guard and then skipped,
+// copies and synchronizations become no-ops and readbacks return zeros.  Lets
+// the whole launch sequence of a solve run on a host without a GPU.
+bool dry_run();
+void set_dry_run(bool on);
+
+// Enqueue on `stream`.  Returns hipSuccess or the launch error.
+hipError_t gett(const GemmDesc &d, hipStream_t stream);
+
+// Convenience: fill a descriptor for a plain strided matrix product
+// C[m,n] = alpha * sum_k A[m*sam + k*sak] * B[k*sbk + n*sbn] + beta*C[m*scm + n*scn].
+GemmDesc gemm_desc(int M, int N, int K, double alpha,
+                   const double *A, int64_t sam, int64_t sak,
+                   const double *B, int64_t sbk, int64_t sbn,
+                   double beta, double *C, int64_t scm, int64_t scn);
+
+}  // namespace lnocc

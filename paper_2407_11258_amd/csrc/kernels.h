@@ -1,0 +1,53 @@
+// Bandwidth-bound kernels of the fragment solver (splits, amplitude updates,
+// FP64 reductions, DIIS vector algebra, the (T) energy epilogue).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lnocc {
+
+// Fixed grid of every partial-sum kernel: the reduction order (and so every
+// FP64 energy and norm) is independent of timing and bitwise reproducible.
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+hipError_t split_B(const double *B, int64_t X, int64_t o, int64_t v,
+                   double *Boo, double *Bov, double *Bvv, hipStream_t s);
+hipError_t diag_sum(const double *Boo, int64_t X, int64_t o, double *J, hipStream_t s);
+hipError_t add_diag(double *M, int64_t n, int64_t ld, const double *eps, hipStream_t s);
+hipError_t transpose2d(const double *in, int64_t rows, int64_t cols, double *out, hipStream_t s);
+hipError_t make_u(const double *t2, int64_t o, int64_t v, double *u, hipStream_t s);
+hipError_t mp2_guess(const double *Kov, const double *eo, const double *ev, int64_t o,
+                     int64_t v, double *t1, double *t2, hipStream_t s);
+hipError_t build_lov(const double *Kov, int64_t o, int64_t v, double *Lov, hipStream_t s);
+hipError_t sub_oovv_into_dint(const double *Goovv, int64_t o, int64_t v, double *Dint,
+                              hipStream_t s);
+hipError_t combine_r2(double *R2, const double *S, const double *Xc, int64_t o, int64_t v,
+                      hipStream_t s);
+// partials[kRedBlocks] <- pieces of sum (2 (ia|jb) - (ib|ja)) (t2 + t1 t1)
+hipError_t energy_partials(const double *Kov, const double *t1, const double *t2, int64_t o,
+                           int64_t v, double *partials, hipStream_t s);
+// out[0] (+)= sum of partials[0..n) in a fixed order
+hipError_t reduce_partials(const double *partials, int64_t n, double *out, int accumulate,
+                           hipStream_t s);
+// x = t + R / D (Jacobi step) as one concatenated vector [t1 | t2]; e = x - t.
+hipError_t jacobi_step(const double *t1, const double *t2, const double *R1, const double *R2,
+                       const double *eo, const double *ev, int64_t o, int64_t v, double *x,
+                       double *e, hipStream_t s);
+// partials[i * kRedBlocks + b] <- pieces of dot(e_new, e_i), i < m
+hipError_t dot_partials(const double *E, int64_t stride, int m, const double *enew, int64_t N,
+                        double *partials, hipStream_t s);
+hipError_t reduce_rows(const double *partials, int m, double *out, hipStream_t s);
+// t1 | t2 <- sum_i c[i] x_i
+hipError_t lincomb(const double *Xs, int64_t stride, int m, const double *c_host, int64_t o,
+                   int64_t v, double *t1, double *t2, hipStream_t s);
+hipError_t scatter_vec(const double *x, int64_t o, int64_t v, double *t1, double *t2,
+                       hipStream_t s);
+
+// (T) energy of a batch of unique triples whose W tensors sit in W[nb][v][v][v].
+// table holds (i, j, k) per entry, i <= j <= k; partials[nb * tiles] per tile.
+hipError_t triples_energy(const double *W, const int *table, int nb, const double *Kov,
+                          const double *t1, const double *eo, const double *ev, int64_t o,
+                          int64_t v, double *partials, int64_t *nparts, hipStream_t s);
+
+}  // namespace lnocc

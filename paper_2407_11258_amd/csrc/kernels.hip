@@ -1,0 +1,416 @@
+// Bandwidth-bound kernels of the fragment solver.  Every reduction writes one
+// partial per block of a fixed-size grid and is finished by a single block in
+// a fixed order, so FP64 energies and norms are bitwise reproducible.
+#include "kernels.h"
+#include "gett.h"
+
+namespace lnocc {
+namespace {
+
+constexpr int kEwThreads = 256;
+
+inline int ew_blocks(int64_t n) {
+  int64_t b = (n + kEwThreads - 1) / kEwThreads;
+  if (b > 16384) b = 16384;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
+}
+
+// Sum over the block; the result is valid in thread 0.
+__device__ inline double block_sum(double x, double *sm) {
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sm[w] = x;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sm[i];
+  return r;
+}
+
+__global__ void k_split_B(const double *__restrict__ B, int64_t X, int64_t o, int64_t v,
+                          double *Boo, double *Bov, double *Bvv) {
+  const int64_t n = o + v, total = X * n * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t Q = e / (n * n), pq = e % (n * n), p = pq / n, q = pq % n;
+    const double x = B[e];
+    if (p < o && q < o) Boo[(Q * o + p) * o + q] = x;
+    else if (p < o) Bov[(Q * o + p) * v + (q - o)] = x;
+    else if (q >= o) Bvv[(Q * v + (p - o)) * v + (q - o)] = x;
+  }
+}
+
+__global__ void k_diag_sum(const double *__restrict__ Boo, int64_t X, int64_t o, double *J) {
+  for (int64_t Q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; Q < X;
+       Q += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t k = 0; k < o; ++k) s += Boo[(Q * o + k) * o + k];
+    J[Q] = s;
+  }
+}
+
+__global__ void k_add_diag(double *M, int64_t n, int64_t ld, const double *eps) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x)
+    M[p * ld + p] += eps[p];
+}
+
+__global__ void k_transpose2d(const double *__restrict__ in, int64_t rows, int64_t cols,
+                              double *out) {
+  const int64_t total = rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / cols, c = e % cols;
+    out[c * rows + r] = in[e];
+  }
+}
+
+// u[i][j][a][b] = 2 t2[i][j][a][b] - t2[j][i][a][b]
+__global__ void k_make_u(const double *__restrict__ t2, int64_t o, int64_t v, double *u) {
+  const int64_t vv = v * v, total = o * o * vv;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ij = e / vv, ab = e % vv, i = ij / o, j = ij % o;
+    u[e] = 2.0 * t2[e] - t2[(j * o + i) * vv + ab];
+  }
+}
+
+// t2[i][j][a][b] = (ia|jb) / (e_i + e_j - e_a - e_b), t1 = 0
+__global__ void k_mp2_guess(const double *__restrict__ Kov, const double *eo, const double *ev,
+                            int64_t o, int64_t v, double *t1, double *t2) {
+  const int64_t vv = v * v, total = o * o * vv;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ij = e / vv, ab = e % vv, i = ij / o, j = ij % o, a = ab / v, b = ab % v;
+    t2[e] = Kov[((i * v + a) * o + j) * v + b] / (eo[i] + eo[j] - ev[a] - ev[b]);
+    if (e < o * v) t1[e] = 0.0;
+  }
+}
+
+// Lov[l][d][k][c] = 2 (ld|kc) - (lc|kd), Kov[k][c][l][d] = (kc|ld)
+__global__ void k_build_lov(const double *__restrict__ Kov, int64_t o, int64_t v, double *Lov) {
+  const int64_t total = o * v * o * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e % v, k = (e / v) % o, d = (e / (v * o)) % v, l = e / (v * o * v);
+    Lov[e] = 2.0 * Kov[e] - Kov[((l * v + c) * o + k) * v + d];
+  }
+}
+
+// Dint[i][a][k][c] -= Goovv[k][i][a][c]
+__global__ void k_sub_oovv(const double *__restrict__ G, int64_t o, int64_t v, double *Dint) {
+  const int64_t total = o * v * o * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e % v, k = (e / v) % o, a = (e / (v * o)) % v, i = e / (v * o * v);
+    Dint[e] -= G[((k * o + i) * v + a) * v + c];
+  }
+}
+
+// R2 += S + S^P - 1/2 (X + X^P) - (Xs + Xs^P), with Y^P[i][j][a][b] = Y[j][i][b][a]
+// and Xs[i][j][a][b] = X[j][i][a][b].
+__global__ void k_combine_r2(double *R2, const double *__restrict__ S, const double *__restrict__ Xc,
+                             int64_t o, int64_t v) {
+  const int64_t vv = v * v, total = o * o * vv;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ij = e / vv, ab = e % vv, i = ij / o, j = ij % o, a = ab / v, b = ab % v;
+    const int64_t ji_ba = (j * o + i) * vv + b * v + a;
+    const int64_t ji_ab = (j * o + i) * vv + ab;
+    const int64_t ij_ba = ij * vv + b * v + a;
+    R2[e] += S[e] + S[ji_ba] - 0.5 * (Xc[e] + Xc[ji_ba]) - (Xc[ji_ab] + Xc[ij_ba]);
+  }
+}
+
+__global__ void k_energy_partials(const double *__restrict__ Kov, const double *__restrict__ t1,
+                                  const double *__restrict__ t2, int64_t o, int64_t v,
+                                  double *partials) {
+  __shared__ double sm[kRedThreads / 64];
+  const int64_t vv = v * v, total = o * o * vv;
+  double acc = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ij = e / vv, ab = e % vv, i = ij / o, j = ij % o, a = ab / v, b = ab % v;
+    const double tau = t2[e] + t1[i * v + a] * t1[j * v + b];
+    const double L = 2.0 * Kov[((i * v + a) * o + j) * v + b] - Kov[((i * v + b) * o + j) * v + a];
+    acc += L * tau;
+  }
+  const double r = block_sum(acc, sm);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+__global__ void k_reduce(const double *__restrict__ partials, int64_t n, double *out,
+                         int accumulate) {
+  __shared__ double sm[kRedThreads / 64];
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) acc += partials[e];
+  const double r = block_sum(acc, sm);
+  if (threadIdx.x == 0) out[0] = accumulate ? out[0] + r : r;
+}
+
+__global__ void k_jacobi(const double *__restrict__ t1, const double *__restrict__ t2,
+                         const double *__restrict__ R1, const double *__restrict__ R2,
+                         const double *eo, const double *ev, int64_t o, int64_t v, double *x,
+                         double *err) {
+  const int64_t n1 = o * v, vv = v * v, total = n1 + o * o * vv;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double told, xn;
+    if (e < n1) {
+      const int64_t i = e / v, a = e % v;
+      told = t1[e];
+      xn = told + R1[e] / (eo[i] - ev[a]);
+    } else {
+      const int64_t f = e - n1, ij = f / vv, ab = f % vv;
+      const int64_t i = ij / o, j = ij % o, a = ab / v, b = ab % v;
+      told = t2[f];
+      xn = told + R2[f] / (eo[i] + eo[j] - ev[a] - ev[b]);
+    }
+    x[e] = xn;
+    err[e] = xn - told;
+  }
+}
+
+constexpr int kMaxDiis = 16;
+
+__global__ void k_dot_partials(const double *__restrict__ E, int64_t stride, int m,
+                               const double *__restrict__ enew, int64_t N, double *partials) {
+  __shared__ double sm[kRedThreads / 64];
+  double acc[kMaxDiis];
+#pragma unroll
+  for (int i = 0; i < kMaxDiis; ++i) acc[i] = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double x = enew[e];
+#pragma unroll
+    for (int i = 0; i < kMaxDiis; ++i)
+      if (i < m) acc[i] += x * E[i * stride + e];
+  }
+#pragma unroll
+  for (int i = 0; i < kMaxDiis; ++i) {
+    if (i < m) {   // m is uniform over the block
+      const double r = block_sum(acc[i], sm);
+      if (threadIdx.x == 0) partials[i * kRedBlocks + blockIdx.x] = r;
+    }
+  }
+}
+
+__global__ void k_reduce_rows(const double *__restrict__ partials, double *out) {
+  __shared__ double sm[kRedThreads / 64];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < kRedBlocks; e += blockDim.x)
+    acc += partials[blockIdx.x * kRedBlocks + e];
+  const double r = block_sum(acc, sm);
+  if (threadIdx.x == 0) out[blockIdx.x] = r;
+}
+
+struct Coeffs { double c[kMaxDiis]; };
+
+__global__ void k_lincomb(const double *__restrict__ Xs, int64_t stride, int m, Coeffs cf,
+                          int64_t o, int64_t v, double *t1, double *t2) {
+  const int64_t n1 = o * v, total = n1 + o * o * v * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += cf.c[i] * Xs[i * stride + e];
+    if (e < n1) t1[e] = s;
+    else t2[e - n1] = s;
+  }
+}
+
+__global__ void k_scatter(const double *__restrict__ x, int64_t o, int64_t v, double *t1,
+                          double *t2) {
+  const int64_t n1 = o * v, total = n1 + o * o * v * v;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < n1) t1[e] = x[e];
+    else t2[e - n1] = x[e];
+  }
+}
+
+// (T) energy epilogue on cube tiles of the W tensors.
+constexpr int TT = 8;          // tile edge
+constexpr int TP = TT + 1;     // padded innermost extent in LDS
+
+__device__ inline void load_cube(const double *__restrict__ W, int64_t v, int64_t o0, int64_t o1,
+                                 int64_t o2, double *L) {
+  for (int e = threadIdx.x; e < TT * TT * TT; e += blockDim.x) {
+    const int p = e / (TT * TT), q = (e / TT) % TT, r = e % TT;
+    const int64_t x = o0 + p, y = o1 + q, z = o2 + r;
+    L[(p * TT + q) * TP + r] = (x < v && y < v && z < v) ? W[(x * v + y) * v + z] : 0.0;
+  }
+}
+
+__global__ void k_triples_energy(const double *__restrict__ Wall, const int *__restrict__ table,
+                                 const double *__restrict__ Kov, const double *__restrict__ t1,
+                                 const double *__restrict__ eo, const double *__restrict__ ev,
+                                 int64_t o, int64_t v, int tpd, double *partials) {
+  __shared__ double L[6][TT * TT * TP];
+  __shared__ double sm[kRedThreads / 64];
+  const int entry = blockIdx.y;
+  const int i = table[3 * entry], j = table[3 * entry + 1], k = table[3 * entry + 2];
+  const double *W = Wall + (int64_t)entry * v * v * v;
+  const int tile = blockIdx.x;
+  const int64_t a0 = (int64_t)(tile / (tpd * tpd)) * TT;
+  const int64_t b0 = (int64_t)((tile / tpd) % tpd) * TT;
+  const int64_t c0 = (int64_t)(tile % tpd) * TT;
+  load_cube(W, v, a0, b0, c0, L[0]);   // W^abc
+  load_cube(W, v, b0, c0, a0, L[1]);   // W^bca
+  load_cube(W, v, c0, a0, b0, L[2]);   // W^cab
+  load_cube(W, v, a0, c0, b0, L[3]);   // W^acb
+  load_cube(W, v, b0, a0, c0, L[4]);   // W^bac
+  load_cube(W, v, c0, b0, a0, L[5]);   // W^cba
+  __syncthreads();
+  const double eijk = eo[i] + eo[j] + eo[k];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < TT * TT * TT; e += blockDim.x) {
+    const int x = e / (TT * TT), y = (e / TT) % TT, z = e % TT;
+    const int64_t a = a0 + x, b = b0 + y, c = c0 + z;
+    if (a >= v || b >= v || c >= v) continue;
+    const double w = L[0][(x * TT + y) * TP + z];
+    const double wbca = L[1][(y * TT + z) * TP + x];
+    const double wcab = L[2][(z * TT + x) * TP + y];
+    const double wacb = L[3][(x * TT + z) * TP + y];
+    const double wbac = L[4][(y * TT + x) * TP + z];
+    const double wcba = L[5][(z * TT + y) * TP + x];
+    const double V = w + Kov[((i * v + a) * o + j) * v + b] * t1[k * v + c] +
+                     Kov[((i * v + a) * o + k) * v + c] * t1[j * v + b] +
+                     Kov[((j * v + b) * o + k) * v + c] * t1[i * v + a];
+    const double Z = 4.0 * w + wbca + wcab - 2.0 * (wacb + wbac + wcba);
+    acc += V * Z / (eijk - ev[a] - ev[b] - ev[c]);
+  }
+  const double weight = (i < j && j < k) ? 2.0 : 1.0;   // (6 or 3) / 3
+  const double r = block_sum(acc, sm);
+  if (threadIdx.x == 0) partials[(int64_t)entry * gridDim.x + tile] = weight * r;
+}
+
+}  // namespace
+
+hipError_t split_B(const double *B, int64_t X, int64_t o, int64_t v, double *Boo, double *Bov,
+                   double *Bvv, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  const int64_t n = o + v;
+  hipLaunchKernelGGL(k_split_B, dim3(ew_blocks(X * n * n)), dim3(kEwThreads), 0, s, B, X, o, v,
+                     Boo, Bov, Bvv);
+  return hipGetLastError();
+}
+hipError_t diag_sum(const double *Boo, int64_t X, int64_t o, double *J, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_diag_sum, dim3(ew_blocks(X)), dim3(kEwThreads), 0, s, Boo, X, o, J);
+  return hipGetLastError();
+}
+hipError_t add_diag(double *M, int64_t n, int64_t ld, const double *eps, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_add_diag, dim3(ew_blocks(n)), dim3(kEwThreads), 0, s, M, n, ld, eps);
+  return hipGetLastError();
+}
+hipError_t transpose2d(const double *in, int64_t rows, int64_t cols, double *out, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose2d, dim3(ew_blocks(rows * cols)), dim3(kEwThreads), 0, s, in,
+                     rows, cols, out);
+  return hipGetLastError();
+}
+hipError_t make_u(const double *t2, int64_t o, int64_t v, double *u, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_make_u, dim3(ew_blocks(o * o * v * v)), dim3(kEwThreads), 0, s, t2, o, v, u);
+  return hipGetLastError();
+}
+hipError_t mp2_guess(const double *Kov, const double *eo, const double *ev, int64_t o, int64_t v,
+                     double *t1, double *t2, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_mp2_guess, dim3(ew_blocks(o * o * v * v)), dim3(kEwThreads), 0, s, Kov,
+                     eo, ev, o, v, t1, t2);
+  return hipGetLastError();
+}
+hipError_t build_lov(const double *Kov, int64_t o, int64_t v, double *Lov, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_build_lov, dim3(ew_blocks(o * o * v * v)), dim3(kEwThreads), 0, s, Kov,
+                     o, v, Lov);
+  return hipGetLastError();
+}
+hipError_t sub_oovv_into_dint(const double *Goovv, int64_t o, int64_t v, double *Dint,
+                              hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_sub_oovv, dim3(ew_blocks(o * o * v * v)), dim3(kEwThreads), 0, s, Goovv,
+                     o, v, Dint);
+  return hipGetLastError();
+}
+hipError_t combine_r2(double *R2, const double *S, const double *Xc, int64_t o, int64_t v,
+                      hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_combine_r2, dim3(ew_blocks(o * o * v * v)), dim3(kEwThreads), 0, s, R2, S,
+                     Xc, o, v);
+  return hipGetLastError();
+}
+hipError_t energy_partials(const double *Kov, const double *t1, const double *t2, int64_t o,
+                           int64_t v, double *partials, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_energy_partials, dim3(kRedBlocks), dim3(kRedThreads), 0, s, Kov, t1, t2,
+                     o, v, partials);
+  return hipGetLastError();
+}
+hipError_t reduce_partials(const double *partials, int64_t n, double *out, int accumulate,
+                           hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, partials, n, out, accumulate);
+  return hipGetLastError();
+}
+hipError_t jacobi_step(const double *t1, const double *t2, const double *R1, const double *R2,
+                       const double *eo, const double *ev, int64_t o, int64_t v, double *x,
+                       double *e, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_jacobi, dim3(ew_blocks(o * v + o * o * v * v)), dim3(kEwThreads), 0, s,
+                     t1, t2, R1, R2, eo, ev, o, v, x, e);
+  return hipGetLastError();
+}
+hipError_t dot_partials(const double *E, int64_t stride, int m, const double *enew, int64_t N,
+                        double *partials, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  if (m < 1 || m > kMaxDiis) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dot_partials, dim3(kRedBlocks), dim3(kRedThreads), 0, s, E, stride, m,
+                     enew, N, partials);
+  return hipGetLastError();
+}
+hipError_t reduce_rows(const double *partials, int m, double *out, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_rows, dim3(m), dim3(kRedThreads), 0, s, partials, out);
+  return hipGetLastError();
+}
+hipError_t lincomb(const double *Xs, int64_t stride, int m, const double *c_host, int64_t o,
+                   int64_t v, double *t1, double *t2, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  if (m < 1 || m > kMaxDiis) return hipErrorInvalidValue;
+  Coeffs cf{};
+  for (int i = 0; i < m; ++i) cf.c[i] = c_host[i];
+  hipLaunchKernelGGL(k_lincomb, dim3(ew_blocks(o * v + o * o * v * v)), dim3(kEwThreads), 0, s,
+                     Xs, stride, m, cf, o, v, t1, t2);
+  return hipGetLastError();
+}
+hipError_t scatter_vec(const double *x, int64_t o, int64_t v, double *t1, double *t2,
+                       hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3(ew_blocks(o * v + o * o * v * v)), dim3(kEwThreads), 0, s,
+                     x, o, v, t1, t2);
+  return hipGetLastError();
+}
+hipError_t triples_energy(const double *W, const int *table, int nb, const double *Kov,
+                          const double *t1, const double *eo, const double *ev, int64_t o,
+                          int64_t v, double *partials, int64_t *nparts, hipStream_t s) {
+  const int tpd = (int)((v + TT - 1) / TT);
+  const int tiles = tpd * tpd * tpd;
+  *nparts = (int64_t)tiles * nb;
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_triples_energy, dim3(tiles, nb), dim3(kRedThreads), 0, s, W, table, Kov,
+                     t1, eo, ev, o, v, tpd, partials);
+  return hipGetLastError();
+}
+
+}  // namespace lnocc

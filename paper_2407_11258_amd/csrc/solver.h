@@ -1,0 +1,83 @@
+// Internal interface of the fragment solver (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/lnocc.h"
+#include "gett.h"
+
+namespace lnocc {
+
+struct Dims { int64_t o, v, X; };
+
+// Device buffers carved out of the caller's workspace.  The (T) buffers alias
+// the CCSD scratch, which is dead once the amplitudes have converged.
+struct Layout {
+  Dims dm;
+  // common
+  double *Boo, *Bov, *Bvv;          // DF split [X][o][o], [X][o][v], [X][v][v]
+  double *Kov;                      // (kc|ld) as [k][c][l][d]
+  double *t1w, *t2w;                // amplitudes when the caller passes none
+  double *hoo, *hov, *hvo, *hvv;    // bare one-electron operator blocks
+  double *J;                        // [X] occupied trace of B (or B~)
+  double *scal, *partials;          // small scalars, reduction partials
+  // CCSD
+  double *Btoo, *Btai, *Btvv;       // T1-dressed factors; Btai[Q][i][a] = B~[Q][a][i]
+  double *Foo, *Fov, *Fvo, *Fvv, *Foop, *Fvvp;
+  double *Pvv, *Q2, *Lov;           // (ld|kc) [k][l][d][c], (kd|lc) [k][l][c][d], 2(ld|kc)-(lc|kd) [l][d][k][c]
+  double *u, *R1, *R2, *S, *Xc, *Goovv, *Cint, *Dint, *Wkl, *Y1, *Z1;
+  double *chunk;                    // (ac|bd)~ for chunk_a values of a: [a][b][c][d]
+  double *dx, *de;                  // DIIS vectors and errors [m][namp]
+  int64_t chunk_a, namp;
+  int diis_m;
+  // (T)
+  double *Gt, *Jt, *W, *tpart;      // (ai|bd) [i][a][b][d], (ck|jl) [j][k][c][l], W [nb][v][v][v]
+  int *table;
+  int nb;
+  int64_t ntriples;
+  size_t bytes;
+};
+
+struct Inputs {
+  const double *B, *eo, *ev;
+  double *t1, *t2;
+  double conv_tol;
+};
+
+struct Outputs {
+  double e_mp2 = 0, e_ccsd = 0, e_t = 0, residual = 0;
+  int n_iter = 0, status = 0;
+};
+
+// Stream copies and synchronization that become no-ops in validation mode
+// (readbacks then return zeros).
+inline hipError_t dcopy(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  return dry_run() ? hipSuccess : hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+inline hipError_t dzero(void *dst, size_t bytes, hipStream_t s) {
+  return dry_run() ? hipSuccess : hipMemsetAsync(dst, 0, bytes, s);
+}
+inline hipError_t d2h(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  if (dry_run()) {
+    for (size_t i = 0; i < bytes; ++i) ((char *)dst)[i] = 0;
+    return hipSuccess;
+  }
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+}
+inline hipError_t h2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  return dry_run() ? hipSuccess : hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+}
+inline hipError_t dsync(hipStream_t s) { return dry_run() ? hipSuccess : hipStreamSynchronize(s); }
+
+int64_t unique_triples(int64_t o);
+void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout &L);
+int setup_fragment(const Layout &L, const double *B, const double *eo, const double *ev,
+                   bool ccsd_phase, hipStream_t s);
+int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s);
+int energy(const Layout &L, const double *t1, const double *t2, double *dev_out, hipStream_t s);
+int run_ccsd(const Layout &L, const Inputs &in, const lnocc_options_t &opt, Outputs &out,
+             hipStream_t s);
+int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s);
+
+}  // namespace lnocc

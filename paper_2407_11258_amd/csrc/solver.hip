@@ -1,0 +1,581 @@
+// Host driver of the fragment solver: workspace layout, the closed-shell CCSD
+// residual as a sequence of contractions, Jacobi + DIIS iterations and the
+// (T) passes.  Everything here enqueues device work on one stream; the only
+// device-to-host traffic is one small readback per iteration.
+//
+// CCSD equations: closed-shell CCSD written with the T1-similarity-transformed
+// Hamiltonian H~ = exp(-T1) H exp(T1).  Three-index factors are dressed once
+// per iteration (B~ = Lm B Rm^T with Lm = 1 - T, Rm = 1 + T^T, T[a][i] = t_i^a),
+// after which every term is a product of dressed DF factors, T2 and the dressed
+// Fock matrix.  The residual returned is <mu| e^{-T} H e^{T} |HF> for
+// mu = (i alpha -> a alpha) and (i alpha j beta -> a alpha b beta).
+#include "solver.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "gett.h"
+#include "kernels.h"
+
+namespace lnocc {
+
+#define LN_TRY(x)                                                         \
+  do {                                                                    \
+    hipError_t e_ = (x);                                                  \
+    if (e_ != hipSuccess) {                                               \
+      if (std::getenv("LNOCC_DEBUG"))                                     \
+        std::fprintf(stderr, "lnocc: %s failed (%s) at %s:%d\n", #x,      \
+                     hipGetErrorString(e_), __FILE__, __LINE__);         \
+      return LNOCC_EDEVICE;                                               \
+    }                                                                     \
+  } while (0)
+
+namespace {
+
+GOperand OP(const double *p, int64_t ro, int64_t ri, int64_t ko, int64_t ki) {
+  GOperand g{};
+  g.p = p; g.s_ro = ro; g.s_ri = ri; g.s_ko = ko; g.s_ki = ki;
+  return g;
+}
+GOperand OPB(GOperand g, int64_t b0, int64_t b1, int64_t b2) {
+  g.b0 = b0; g.b1 = b1; g.b2 = b2;
+  return g;
+}
+GemmDesc DESC(int64_t M, int64_t Mi, int64_t N, int64_t Ni, double *c, int64_t cmo, int64_t cmi,
+              int64_t cno, int64_t cni, double beta) {
+  GemmDesc d{};
+  d.M = (int)M; d.Mi = (int)Mi; d.N = (int)N; d.Ni = (int)Ni;
+  d.c = c; d.c_mo = cmo; d.c_mi = cmi; d.c_no = cno; d.c_ni = cni;
+  d.beta = beta; d.batch = 1; d.nb1 = 1; d.table = nullptr; d.prec = Prec::F64;
+  return d;
+}
+void SEG(GemmDesc &d, int64_t K, int64_t Ki, double scale, GOperand a, GOperand b) {
+  GSegment &s = d.seg[d.nseg++];
+  s.a = a; s.b = b; s.K = (int)K; s.Ki = (int)Ki; s.scale = scale;
+}
+// batch over the auxiliary index: entry Q moves operands by b0 * Q
+void BATCH_Q(GemmDesc &d, int64_t X, int64_t cstride) {
+  d.batch = (int)X; d.nb1 = 1; d.c_b0 = cstride;
+}
+
+struct Arena {
+  char *base;
+  size_t off = 0;
+  double *d(int64_t n) {
+    off = (off + 255) & ~size_t(255);
+    double *p = base ? (double *)(base + off) : nullptr;
+    off += (size_t)n * sizeof(double);
+    return p;
+  }
+  int *i(int64_t n) {
+    off = (off + 255) & ~size_t(255);
+    int *p = base ? (int *)(base + off) : nullptr;
+    off += (size_t)n * sizeof(int);
+    return p;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- layout
+int64_t unique_triples(int64_t o) {
+  // i <= j <= k with not all equal
+  return o * (o + 1) * (o + 2) / 6 - o;
+}
+
+void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout &L) {
+  const int64_t o = dm.o, v = dm.v, X = dm.X;
+  const int64_t ov = o * v, oo = o * o, vv = v * v, oovv = oo * vv, vvv = vv * v;
+  Arena A{base};
+  L = Layout{};
+  L.dm = dm;
+  // common
+  L.Boo = A.d(X * oo); L.Bov = A.d(X * ov); L.Bvv = A.d(X * vv);
+  L.Kov = A.d(oovv);
+  L.t1w = A.d(ov); L.t2w = A.d(oovv);
+  L.hoo = A.d(oo); L.hov = A.d(ov); L.hvo = A.d(ov); L.hvv = A.d(vv);
+  L.J = A.d(X);
+  L.scal = A.d(64);
+  L.partials = A.d(16 * kRedBlocks);
+  const size_t phase = A.off;
+  // CCSD phase
+  L.diis_m = std::max(1, (int)opt.diis_space);
+  const int64_t N = ov + oovv;
+  L.namp = N;
+  int64_t chunk_bytes = opt.ladder_chunk_bytes ? (int64_t)opt.ladder_chunk_bytes : (int64_t)8 << 30;
+  L.chunk_a = std::max<int64_t>(1, std::min<int64_t>(v, chunk_bytes / (8 * vvv)));
+  L.Btoo = A.d(X * oo); L.Btai = A.d(X * ov); L.Btvv = A.d(X * vv);
+  L.Foo = A.d(oo); L.Fov = A.d(ov); L.Fvo = A.d(ov); L.Fvv = A.d(vv);
+  L.Foop = A.d(oo); L.Fvvp = A.d(vv);
+  L.Pvv = A.d(oovv); L.Q2 = A.d(oovv); L.Lov = A.d(oovv);
+  L.u = A.d(oovv); L.R1 = A.d(ov); L.R2 = A.d(oovv); L.S = A.d(oovv); L.Xc = A.d(oovv);
+  L.Goovv = A.d(oovv); L.Cint = A.d(oovv); L.Dint = A.d(oovv);
+  L.Wkl = A.d(oo * oo); L.Y1 = A.d(X * ov); L.Z1 = A.d(X * ov);
+  L.chunk = A.d(L.chunk_a * vvv);
+  L.dx = A.d(L.diis_m * N); L.de = A.d(L.diis_m * N);
+  const size_t ccsd_end = A.off;
+  // (T) phase (aliases the CCSD scratch)
+  A.off = phase;
+  const int64_t nt = unique_triples(o);
+  int64_t nb = opt.triples_batch;
+  if (nb <= 0) nb = std::max<int64_t>(1, ((int64_t)2 << 30) / (8 * vvv));
+  nb = std::max<int64_t>(1, std::min<int64_t>({nb, std::max<int64_t>(nt, 1), 4096}));
+  L.nb = (int)nb;
+  L.ntriples = nt;
+  L.Gt = A.d(ov * vv); L.Jt = A.d(oo * ov);
+  L.W = A.d(nb * vvv);
+  const int64_t tpd = (v + 7) / 8;
+  L.tpart = A.d(nb * tpd * tpd * tpd);
+  L.table = A.i(3 * std::max<int64_t>(nt, 1));
+  const size_t t_end = A.off;
+  L.bytes = std::max(ccsd_end, t_end) + 256;
+}
+
+// ---------------------------------------------------------------- pieces
+namespace {
+
+// G_pq = sc * 2... : adds sc * sum_Q J_Q B_Qpq + sx * sum_Qk B_Qpk B_Qkq into the
+// four Fock blocks.  Bai[Q][i][a] holds B[Q][a][i].
+int fock_two_electron(const Layout &L, const double *Boo, const double *Bov, const double *Bai,
+                      const double *Bvv, const double *J, double *Goo, double *Gov, double *Gvo,
+                      double *Gvv, double sc, double sx, hipStream_t s) {
+  const int64_t o = L.dm.o, v = L.dm.v, X = L.dm.X, ov = o * v, oo = o * o, vv = v * v;
+  {  // Coulomb
+    GemmDesc d = DESC(oo, 1, 1, 1, Goo, 1, 0, 0, 0, 1.0);
+    SEG(d, X, 1, sc, OP(Boo, 1, 0, oo, 0), OP(J, 0, 0, 1, 0));
+    LN_TRY(gett(d, s));
+    d = DESC(ov, 1, 1, 1, Gov, 1, 0, 0, 0, 1.0);
+    SEG(d, X, 1, sc, OP(Bov, 1, 0, ov, 0), OP(J, 0, 0, 1, 0));
+    LN_TRY(gett(d, s));
+    d = DESC(ov, v, 1, 1, Gvo, 1, o, 0, 0, 1.0);
+    SEG(d, X, 1, sc, OP(Bai, v, 1, ov, 0), OP(J, 0, 0, 1, 0));
+    LN_TRY(gett(d, s));
+    d = DESC(vv, 1, 1, 1, Gvv, 1, 0, 0, 0, 1.0);
+    SEG(d, X, 1, sc, OP(Bvv, 1, 0, vv, 0), OP(J, 0, 0, 1, 0));
+    LN_TRY(gett(d, s));
+  }
+  {  // exchange, contraction over (Q, k)
+    GemmDesc d = DESC(o, 1, o, 1, Goo, o, 0, 1, 0, 1.0);
+    SEG(d, X * o, o, sx, OP(Boo, o, 0, oo, 1), OP(Boo, 1, 0, oo, o));
+    LN_TRY(gett(d, s));
+    d = DESC(o, 1, v, 1, Gov, v, 0, 1, 0, 1.0);
+    SEG(d, X * o, o, sx, OP(Boo, o, 0, oo, 1), OP(Bov, 1, 0, ov, v));
+    LN_TRY(gett(d, s));
+    d = DESC(v, 1, o, 1, Gvo, o, 0, 1, 0, 1.0);
+    SEG(d, X * o, o, sx, OP(Bai, 1, 0, ov, v), OP(Boo, 1, 0, oo, o));
+    LN_TRY(gett(d, s));
+    d = DESC(v, 1, v, 1, Gvv, v, 0, 1, 0, 1.0);
+    SEG(d, X * o, o, sx, OP(Bai, 1, 0, ov, v), OP(Bov, 1, 0, ov, v));
+    LN_TRY(gett(d, s));
+  }
+  return LNOCC_OK;
+}
+
+}  // namespace
+
+// One-off: DF split, bare one-electron operator, (ia|jb) in the layouts used.
+int setup_fragment(const Layout &L, const double *B, const double *eo, const double *ev,
+                   bool ccsd_phase, hipStream_t s) {
+  const int64_t o = L.dm.o, v = L.dm.v, X = L.dm.X, ov = o * v, oo = o * o, vv = v * v;
+  const int64_t ovv = o * vv;
+  LN_TRY(split_B(B, X, o, v, L.Boo, L.Bov, L.Bvv, s));
+  {  // Kov[k][c][l][d] = (kc|ld)
+    GemmDesc d = DESC(ov, 1, ov, 1, L.Kov, ov, 0, 1, 0, 0.0);
+    SEG(d, X, 1, 1.0, OP(L.Bov, 1, 0, ov, 0), OP(L.Bov, 1, 0, ov, 0));
+    LN_TRY(gett(d, s));
+  }
+  if (!ccsd_phase) return LNOCC_OK;
+  // h = diag(eps) - G(B): f = h + G with every occupied orbital of the fragment correlated
+  LN_TRY(dzero(L.hoo, oo * 8, s));
+  LN_TRY(dzero(L.hov, ov * 8, s));
+  LN_TRY(dzero(L.hvo, ov * 8, s));
+  LN_TRY(dzero(L.hvv, vv * 8, s));
+  LN_TRY(diag_sum(L.Boo, X, o, L.J, s));
+  int st = fock_two_electron(L, L.Boo, L.Bov, L.Bov, L.Bvv, L.J, L.hoo, L.hov, L.hvo, L.hvv,
+                             -2.0, 1.0, s);
+  if (st) return st;
+  LN_TRY(add_diag(L.hoo, o, o, eo, s));
+  LN_TRY(add_diag(L.hvv, v, v, ev, s));
+  {  // Pvv[k][l][d][c] = (ld|kc)
+    GemmDesc d = DESC(ov, v, ov, v, L.Pvv, vv, v, ovv, 1, 0.0);
+    SEG(d, X, 1, 1.0, OP(L.Bov, v, 1, ov, 0), OP(L.Bov, v, 1, ov, 0));
+    LN_TRY(gett(d, s));
+  }
+  {  // Q2[k][l][c][d] = (kd|lc)
+    GemmDesc d = DESC(ov, v, ov, v, L.Q2, ovv, 1, vv, v, 0.0);
+    SEG(d, X, 1, 1.0, OP(L.Bov, v, 1, ov, 0), OP(L.Bov, v, 1, ov, 0));
+    LN_TRY(gett(d, s));
+  }
+  LN_TRY(build_lov(L.Kov, o, v, L.Lov, s));
+  return LNOCC_OK;
+}
+
+int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s) {
+  const int64_t o = L.dm.o, v = L.dm.v, X = L.dm.X;
+  const int64_t ov = o * v, oo = o * o, vv = v * v, ovv = o * vv, vvv = vv * v, ooo = oo * o;
+  const size_t B8 = sizeof(double);
+  // --- T1 dressing of the DF factors
+  LN_TRY(dcopy(L.Btoo, L.Boo, X * oo * B8, s));
+  {  // B~_ij = B_ij + sum_b B_ib t_j^b
+    GemmDesc d = DESC(o, 1, o, 1, L.Btoo, o, 0, 1, 0, 1.0);
+    BATCH_Q(d, X, oo);
+    SEG(d, v, 1, 1.0, OPB(OP(L.Bov, v, 0, 1, 0), ov, 0, 0), OP(t1, v, 0, 1, 0));
+    LN_TRY(gett(d, s));
+  }
+  LN_TRY(dcopy(L.Btvv, L.Bvv, X * vv * B8, s));
+  {  // B~_ab = B_ab - sum_k t_k^a B_kb
+    GemmDesc d = DESC(v, 1, v, 1, L.Btvv, v, 0, 1, 0, 1.0);
+    BATCH_Q(d, X, vv);
+    SEG(d, o, 1, -1.0, OP(t1, 1, 0, v, 0), OPB(OP(L.Bov, 1, 0, v, 0), ov, 0, 0));
+    LN_TRY(gett(d, s));
+  }
+  LN_TRY(dcopy(L.Btai, L.Bov, X * ov * B8, s));
+  {  // B~_ai = B_ai + sum_b B_ab t_i^b - sum_k t_k^a B~_ki, stored [Q][i][a]
+    GemmDesc d = DESC(o, 1, v, 1, L.Btai, v, 0, 1, 0, 1.0);
+    BATCH_Q(d, X, ov);
+    SEG(d, v, 1, 1.0, OP(t1, v, 0, 1, 0), OPB(OP(L.Bvv, v, 0, 1, 0), vv, 0, 0));
+    SEG(d, o, 1, -1.0, OPB(OP(L.Btoo, 1, 0, o, 0), oo, 0, 0), OP(t1, 1, 0, v, 0));
+    LN_TRY(gett(d, s));
+  }
+  LN_TRY(diag_sum(L.Btoo, X, o, L.J, s));
+  // --- dressed Fock: F~ = Lm h Rm^T + G(B~)
+  LN_TRY(dcopy(L.Foo, L.hoo, oo * B8, s));
+  {
+    GemmDesc d = DESC(o, 1, o, 1, L.Foo, o, 0, 1, 0, 1.0);
+    SEG(d, v, 1, 1.0, OP(L.hov, v, 0, 1, 0), OP(t1, v, 0, 1, 0));
+    LN_TRY(gett(d, s));
+  }
+  LN_TRY(dcopy(L.Fov, L.hov, ov * B8, s));
+  LN_TRY(dcopy(L.Fvv, L.hvv, vv * B8, s));
+  {
+    GemmDesc d = DESC(v, 1, v, 1, L.Fvv, v, 0, 1, 0, 1.0);
+    SEG(d, o, 1, -1.0, OP(t1, 1, 0, v, 0), OP(L.hov, 1, 0, v, 0));
+    LN_TRY(gett(d, s));
+  }
+  LN_TRY(dcopy(L.Fvo, L.hvo, ov * B8, s));
+  {
+    GemmDesc d = DESC(v, 1, o, 1, L.Fvo, o, 0, 1, 0, 1.0);
+    SEG(d, v, 1, 1.0, OP(L.hvv, v, 0, 1, 0), OP(t1, v, 0, 1, 0));
+    SEG(d, o, 1, -1.0, OP(t1, 1, 0, v, 0), OP(L.Foo, 1, 0, o, 0));
+    LN_TRY(gett(d, s));
+  }
+  int st = fock_two_electron(L, L.Btoo, L.Bov, L.Btai, L.Btvv, L.J, L.Foo, L.Fov, L.Fvo, L.Fvv,
+                             2.0, -1.0, s);
+  if (st) return st;
+  // --- singles residual
+  LN_TRY(transpose2d(L.Fvo, v, o, L.R1, s));   // F~_ai
+  LN_TRY(make_u(t2, o, v, L.u, s));
+  {  // Y[Q][i][d] = sum_kc u_ki^cd B_Q,kc ; R1 += sum_Qd Y[Q][i][d] B~_Q,ad
+    GemmDesc d = DESC(X, 1, ov, v, L.Y1, ov, 0, v, 1, 0.0);
+    SEG(d, ov, v, 1.0, OP(L.Bov, ov, 0, v, 1), OP(L.u, vv, 1, ovv, v));
+    LN_TRY(gett(d, s));
+    d = DESC(o, 1, v, 1, L.R1, v, 0, 1, 0, 1.0);
+    SEG(d, X * v, v, 1.0, OP(L.Y1, v, 0, ov, 1), OP(L.Btvv, v, 0, vv, 1));
+    LN_TRY(gett(d, s));
+  }
+  {  // Z[Q][k][a] = sum_lc u_kl^ac B_Q,lc ; R1 -= sum_Qk B~_Q,ki Z[Q][k][a]
+    GemmDesc d = DESC(X, 1, ov, v, L.Z1, ov, 0, v, 1, 0.0);
+    SEG(d, ov, v, 1.0, OP(L.Bov, ov, 0, v, 1), OP(L.u, ovv, v, vv, 1));
+    LN_TRY(gett(d, s));
+    d = DESC(o, 1, v, 1, L.R1, v, 0, 1, 0, 1.0);
+    SEG(d, X * o, o, -1.0, OP(L.Btoo, 1, 0, oo, o), OP(L.Z1, 1, 0, ov, v));
+    LN_TRY(gett(d, s));
+  }
+  {  // R1 += sum_kc u_ik^ac F~_kc
+    GemmDesc d = DESC(ov, v, 1, 1, L.R1, v, 1, 0, 0, 1.0);
+    SEG(d, ov, v, 1.0, OP(L.u, ovv, v, vv, 1), OP(L.Fov, 0, 0, v, 1));
+    LN_TRY(gett(d, s));
+  }
+  // --- doubles residual: R2 <- (ai|bj)~
+  {
+    GemmDesc d = DESC(ov, v, ov, v, L.R2, ovv, v, vv, 1, 0.0);
+    SEG(d, X, 1, 1.0, OP(L.Btai, v, 1, ov, 0), OP(L.Btai, v, 1, ov, 0));
+    LN_TRY(gett(d, s));
+  }
+  // particle-particle ladder, (ac|bd)~ formed for a block of a at a time
+  for (int64_t a0 = 0; a0 < v; a0 += L.chunk_a) {
+    const int64_t na = std::min<int64_t>(L.chunk_a, v - a0);
+    GemmDesc d = DESC(na * v, v, vv, v, L.chunk, vvv, v, vv, 1, 0.0);
+    SEG(d, X, 1, 1.0, OP(L.Btvv + a0 * v, v, 1, vv, 0), OP(L.Btvv, v, 1, vv, 0));
+    LN_TRY(gett(d, s));
+    d = DESC(oo, 1, na * v, 1, L.R2 + a0 * v, vv, 0, 1, 0, 1.0);
+    SEG(d, vv, 1, 1.0, OP(t2, vv, 0, 1, 0), OP(L.chunk, vv, 0, 1, 0));
+    LN_TRY(gett(d, s));
+  }
+  {  // hole-hole ladder: W_klij = (ki|lj)~ + sum_cd (kc|ld) t_ij^cd ; R2 += sum_kl t_kl^ab W_klij
+    GemmDesc d = DESC(oo, o, oo, o, L.Wkl, ooo, o, oo, 1, 0.0);
+    SEG(d, X, 1, 1.0, OP(L.Btoo, o, 1, oo, 0), OP(L.Btoo, o, 1, oo, 0));
+    LN_TRY(gett(d, s));
+    d = DESC(oo, o, oo, 1, L.Wkl, ooo, oo, 1, 0, 1.0);
+    SEG(d, vv, v, 1.0, OP(L.Kov, ovv, v, ov, 1), OP(t2, vv, 0, v, 1));
+    LN_TRY(gett(d, s));
+    d = DESC(oo, 1, vv, 1, L.R2, vv, 0, 1, 0, 1.0);
+    SEG(d, oo, 1, 1.0, OP(L.Wkl, 1, 0, oo, 0), OP(t2, 1, 0, vv, 0));
+    LN_TRY(gett(d, s));
+  }
+  {  // (ki|ac)~
+    GemmDesc d = DESC(oo, 1, vv, 1, L.Goovv, vv, 0, 1, 0, 0.0);
+    SEG(d, X, 1, 1.0, OP(L.Btoo, 1, 0, oo, 0), OP(L.Btvv, 1, 0, vv, 0));
+    LN_TRY(gett(d, s));
+  }
+  // exchange-type ring: Cint_kiac = (ki|ac)~ - 1/2 sum_ld t_li^ad (kd|lc); X_ijab = sum_kc t_kj^bc Cint_kiac
+  LN_TRY(dcopy(L.Cint, L.Goovv, oo * vv * B8, s));
+  {
+    GemmDesc d = DESC(ov, v, ov, v, L.Cint, vv, v, ovv, 1, 1.0);
+    SEG(d, ov, v, -0.5, OP(t2, vv, v, ovv, 1), OP(L.Q2, ovv, v, vv, 1));
+    LN_TRY(gett(d, s));
+    d = DESC(ov, v, ov, v, L.Xc, ovv, v, vv, 1, 0.0);
+    SEG(d, ov, v, 1.0, OP(L.Cint, vv, v, ovv, 1), OP(t2, vv, v, ovv, 1));
+    LN_TRY(gett(d, s));
+  }
+  // Coulomb-type ring: Dint_iakc = 2 (ai|kc)~ - (ki|ac)~ + 1/2 sum_ld u_il^ad L_ldkc ;
+  // S = 1/2 sum_kc u_jk^bc Dint_iakc
+  {
+    GemmDesc d = DESC(ov, 1, ov, 1, L.Dint, ov, 0, 1, 0, 0.0);
+    SEG(d, X, 1, 2.0, OP(L.Btai, 1, 0, ov, 0), OP(L.Bov, 1, 0, ov, 0));
+    LN_TRY(gett(d, s));
+    LN_TRY(sub_oovv_into_dint(L.Goovv, o, v, L.Dint, s));
+    d = DESC(ov, v, ov, 1, L.Dint, ovv, ov, 1, 0, 1.0);
+    SEG(d, ov, v, 0.5, OP(L.u, ovv, v, vv, 1), OP(L.Lov, 1, 0, ovv, ov));
+    LN_TRY(gett(d, s));
+    d = DESC(ov, v, ov, v, L.S, ovv, v, vv, 1, 0.0);
+    SEG(d, ov, v, 0.5, OP(L.Dint, ovv, ov, v, 1), OP(L.u, ovv, v, vv, 1));
+    LN_TRY(gett(d, s));
+  }
+  // Fock-type terms: F'_bc = F~_bc - sum_kld u_kl^bd (ld|kc), F'_kj = F~_kj + sum_lcd u_lj^cd (kd|lc)
+  LN_TRY(dcopy(L.Fvvp, L.Fvv, vv * B8, s));
+  {
+    GemmDesc d = DESC(v, 1, v, 1, L.Fvvp, v, 0, 1, 0, 1.0);
+    SEG(d, oo * v, v, -1.0, OP(L.u, v, 0, vv, 1), OP(L.Pvv, 1, 0, vv, v));
+    LN_TRY(gett(d, s));
+  }
+  LN_TRY(dcopy(L.Foop, L.Foo, oo * B8, s));
+  {
+    GemmDesc d = DESC(o, 1, o, 1, L.Foop, o, 0, 1, 0, 1.0);
+    SEG(d, o * vv, vv, 1.0, OP(L.Q2, ovv, 0, vv, 1), OP(L.u, vv, 0, ovv, 1));
+    LN_TRY(gett(d, s));
+  }
+  {  // S += sum_c t_ij^ac F'_bc - sum_k t_ik^ab F'_kj
+    GemmDesc d = DESC(oo * v, 1, v, 1, L.S, v, 0, 1, 0, 1.0);
+    SEG(d, v, 1, 1.0, OP(t2, v, 0, 1, 0), OP(L.Fvvp, v, 0, 1, 0));
+    LN_TRY(gett(d, s));
+    d = DESC(o * vv, vv, o, 1, L.S, ovv, 1, vv, 0, 1.0);
+    SEG(d, o, 1, -1.0, OP(t2, ovv, 1, vv, 0), OP(L.Foop, 1, 0, o, 0));
+    LN_TRY(gett(d, s));
+  }
+  LN_TRY(combine_r2(L.R2, L.S, L.Xc, o, v, s));
+  return LNOCC_OK;
+}
+
+int energy(const Layout &L, const double *t1, const double *t2, double *dev_out, hipStream_t s) {
+  LN_TRY(energy_partials(L.Kov, t1, t2, L.dm.o, L.dm.v, L.partials, s));
+  LN_TRY(reduce_partials(L.partials, kRedBlocks, dev_out, 0, s));
+  return LNOCC_OK;
+}
+
+// ---------------------------------------------------------------- DIIS
+namespace {
+// Solves the (m+1) x (m+1) Pulay system for the extrapolation weights.
+bool diis_weights(const std::vector<double> &G, int m, int ld, std::vector<double> &c) {
+  const int n = m + 1;
+  std::vector<double> A(n * n, 0.0), b(n, 0.0);
+  double scale = 0.0;
+  for (int i = 0; i < m; ++i) scale = std::max(scale, std::fabs(G[i * ld + i]));
+  if (!(scale > 0.0) || !std::isfinite(scale)) return false;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) A[i * n + j] = G[i * ld + j] / scale;
+  for (int i = 0; i < m; ++i) { A[i * n + m] = -1.0; A[m * n + i] = -1.0; }
+  b[m] = -1.0;
+  for (int col = 0; col < n; ++col) {   // Gaussian elimination, partial pivoting
+    int p = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(A[r * n + col]) > std::fabs(A[p * n + col])) p = r;
+    if (std::fabs(A[p * n + col]) < 1e-14) return false;
+    if (p != col) {
+      for (int k = 0; k < n; ++k) std::swap(A[p * n + k], A[col * n + k]);
+      std::swap(b[p], b[col]);
+    }
+    for (int r = col + 1; r < n; ++r) {
+      const double f = A[r * n + col] / A[col * n + col];
+      for (int k = col; k < n; ++k) A[r * n + k] -= f * A[col * n + k];
+      b[r] -= f * b[col];
+    }
+  }
+  std::vector<double> x(n);
+  for (int r = n - 1; r >= 0; --r) {
+    double acc = b[r];
+    for (int k = r + 1; k < n; ++k) acc -= A[r * n + k] * x[k];
+    x[r] = acc / A[r * n + r];
+  }
+  c.assign(x.begin(), x.begin() + m);
+  for (double w : c)
+    if (!std::isfinite(w)) return false;
+  return true;
+}
+}  // namespace
+
+int run_ccsd(const Layout &L, const Inputs &in, const lnocc_options_t &opt, Outputs &out,
+             hipStream_t s) {
+  const int64_t o = L.dm.o, v = L.dm.v, N = L.namp;
+  double *t1 = in.t1, *t2 = in.t2;
+  double host[64];
+  // MP2 energy (always from the MP1 amplitudes) and the starting point
+  if (opt.guess == LNOCC_GUESS_MP2) {
+    LN_TRY(mp2_guess(L.Kov, in.eo, in.ev, o, v, t1, t2, s));
+    int st = energy(L, t1, t2, L.scal, s);
+    if (st) return st;
+  } else {
+    LN_TRY(mp2_guess(L.Kov, in.eo, in.ev, o, v, L.R1, L.R2, s));
+    int st = energy(L, L.R1, L.R2, L.scal, s);
+    if (st) return st;
+  }
+  LN_TRY(d2h(host, L.scal, 8, s));
+  LN_TRY(dsync(s));
+  out.e_mp2 = host[0];
+  out.n_iter = 0;
+  out.residual = 0.0;
+  out.status = LNOCC_OK;
+
+  const int m = L.diis_m;
+  std::vector<double> G(m * m, 0.0);
+  int count = 0;         // vectors stored so far
+  bool converged = (opt.max_iter == 0);
+  for (int it = 1; it <= opt.max_iter; ++it) {
+    int st = ccsd_residuals(L, t1, t2, s);
+    if (st) return st;
+    const bool use_diis = (m > 1) && (it >= opt.diis_start);
+    const int slot = use_diis ? (count % m) : 0;
+    double *xs = L.dx + (int64_t)slot * N, *es = L.de + (int64_t)slot * N;
+    LN_TRY(jacobi_step(t1, t2, L.R1, L.R2, in.eo, in.ev, o, v, xs, es, s));
+    const int nvalid = use_diis ? std::min(count + 1, m) : 1;
+    const double *ebase = use_diis ? L.de : es;
+    LN_TRY(dot_partials(ebase, N, nvalid, es, N, L.partials, s));
+    LN_TRY(reduce_rows(L.partials, nvalid, L.scal + 1, s));
+    LN_TRY(d2h(host, L.scal, (1 + nvalid) * 8, s));
+    LN_TRY(dsync(s));
+    const double r2 = host[1 + (use_diis ? slot : 0)];
+    out.residual = std::sqrt(std::max(r2, 0.0));
+    out.n_iter = it;
+    if (!std::isfinite(r2)) return LNOCC_ENUMERIC;
+    if (out.residual <= in.conv_tol) {
+      LN_TRY(scatter_vec(xs, o, v, t1, t2, s));
+      converged = true;
+      break;
+    }
+    bool extrap = false;
+    if (use_diis) {
+      for (int q = 0; q < nvalid; ++q) {
+        G[slot * m + q] = host[1 + q];
+        G[q * m + slot] = host[1 + q];
+      }
+      ++count;
+      if (nvalid >= 2) {
+        std::vector<double> c;
+        if (diis_weights(G, nvalid, m, c)) {
+          LN_TRY(lincomb(L.dx, N, nvalid, c.data(), o, v, t1, t2, s));
+          extrap = true;
+        } else {
+          count = 0;   // ill-conditioned space: restart it from this vector
+          std::fill(G.begin(), G.end(), 0.0);
+          if (slot != 0) {
+            LN_TRY(dcopy(L.dx, xs, N * 8, s));
+            LN_TRY(dcopy(L.de, es, N * 8, s));
+          }
+          G[0] = r2;
+          count = 1;
+        }
+      }
+    }
+    if (!extrap) LN_TRY(scatter_vec(xs, o, v, t1, t2, s));
+  }
+  int st = energy(L, t1, t2, L.scal, s);
+  if (st) return st;
+  LN_TRY(d2h(host, L.scal, 8, s));
+  LN_TRY(dsync(s));
+  out.e_ccsd = host[0];
+  if (!std::isfinite(out.e_ccsd)) return LNOCC_ENUMERIC;
+  out.status = converged ? LNOCC_OK : LNOCC_NOT_CONVERGED;
+  return out.status;
+}
+
+// ---------------------------------------------------------------- (T)
+int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s) {
+  const int64_t o = L.dm.o, v = L.dm.v, X = L.dm.X;
+  const int64_t ov = o * v, oo = o * o, vv = v * v, ovv = o * vv, vvv = vv * v;
+  const int64_t ovo = ov * o, vo = v * o;
+  const double *t1 = in.t1, *t2 = in.t2;
+  double *acc = L.scal + 40;
+  LN_TRY(dzero(acc, 8, s));
+  if (L.ntriples == 0) {
+    out.e_t = 0.0;
+    LN_TRY(dsync(s));
+    return LNOCC_OK;
+  }
+  {  // Gt[i][a][b][d] = (ai|bd)
+    GemmDesc d = DESC(ov, 1, vv, 1, L.Gt, vv, 0, 1, 0, 0.0);
+    SEG(d, X, 1, 1.0, OP(L.Bov, 1, 0, ov, 0), OP(L.Bvv, 1, 0, vv, 0));
+    LN_TRY(gett(d, s));
+  }
+  {  // Jt[j][k][c][l] = (ck|jl)
+    GemmDesc d = DESC(ov, v, oo, o, L.Jt, vo, o, ovo, 1, 0.0);
+    SEG(d, X, 1, 1.0, OP(L.Bov, v, 1, ov, 0), OP(L.Boo, o, 1, oo, 0));
+    LN_TRY(gett(d, s));
+  }
+  std::vector<int> tab;
+  tab.reserve(3 * L.ntriples);
+  for (int i = 0; i < o; ++i)
+    for (int j = i; j < o; ++j)
+      for (int k = j; k < o; ++k)
+        if (!(i == j && j == k)) { tab.push_back(i); tab.push_back(j); tab.push_back(k); }
+  LN_TRY(h2d(L.table, tab.data(), tab.size() * sizeof(int), s));
+  for (int64_t t0 = 0; t0 < L.ntriples; t0 += L.nb) {
+    const int nb = (int)std::min<int64_t>(L.nb, L.ntriples - t0);
+    const int *table = L.table + 3 * t0;
+    auto finish = [&](GemmDesc &d) {
+      d.batch = nb; d.table = table; d.c_bid = vvv;
+      d.tmax[0] = d.tmax[1] = d.tmax[2] = (int)(o - 1);
+    };
+    {  // rows (a,b), column c: P1, P3, H1, H3
+      GemmDesc d = DESC(vv, v, v, 1, L.W, vv, v, 1, 0, 0.0);
+      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), vvv, 0, 0), OPB(OP(t2, v, 0, 1, 0), 0, vv, ovv));
+      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, vvv, 0), OPB(OP(t2, v, 0, 1, 0), vv, 0, ovv));
+      SEG(d, o, 1, -1.0, OPB(OP(t2, v, 1, vv, 0), ovv, 0, 0), OPB(OP(L.Jt, o, 0, 1, 0), 0, ovo, vo));
+      SEG(d, o, 1, -1.0, OPB(OP(t2, 1, v, vv, 0), 0, ovv, 0), OPB(OP(L.Jt, o, 0, 1, 0), ovo, 0, vo));
+      finish(d);
+      LN_TRY(gett(d, s));
+    }
+    {  // rows (a,c), column b: P2, P5, H2, H5
+      GemmDesc d = DESC(vv, v, v, 1, L.W, vv, 1, v, 0, 1.0);
+      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), vvv, 0, 0), OPB(OP(t2, v, 0, 1, 0), 0, ovv, vv));
+      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, 0, vvv), OPB(OP(t2, v, 0, 1, 0), vv, ovv, 0));
+      SEG(d, o, 1, -1.0, OPB(OP(t2, v, 1, vv, 0), ovv, 0, 0), OPB(OP(L.Jt, o, 0, 1, 0), 0, vo, ovo));
+      SEG(d, o, 1, -1.0, OPB(OP(t2, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), ovo, vo, 0));
+      finish(d);
+      LN_TRY(gett(d, s));
+    }
+    {  // rows (b,c), column a: P4, P6, H4, H6
+      GemmDesc d = DESC(vv, v, v, 1, L.W, v, 1, vv, 0, 1.0);
+      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), 0, vvv, 0), OPB(OP(t2, v, 0, 1, 0), ovv, 0, vv));
+      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, 0, vvv), OPB(OP(t2, v, 0, 1, 0), ovv, vv, 0));
+      SEG(d, o, 1, -1.0, OPB(OP(t2, v, 1, vv, 0), 0, ovv, 0), OPB(OP(L.Jt, o, 0, 1, 0), vo, 0, ovo));
+      SEG(d, o, 1, -1.0, OPB(OP(t2, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), vo, ovo, 0));
+      finish(d);
+      LN_TRY(gett(d, s));
+    }
+    int64_t nparts = 0;
+    LN_TRY(triples_energy(L.W, table, nb, L.Kov, t1, in.eo, in.ev, o, v, L.tpart, &nparts, s));
+    LN_TRY(reduce_partials(L.tpart, nparts, acc, 1, s));
+  }
+  double host = 0.0;
+  LN_TRY(d2h(&host, acc, 8, s));
+  LN_TRY(dsync(s));
+  out.e_t = host;
+  if (!std::isfinite(host)) return LNOCC_ENUMERIC;
+  return LNOCC_OK;
+}
+
+}  // namespace lnocc

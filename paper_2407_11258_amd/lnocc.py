@@ -1,0 +1,226 @@
+"""ctypes binding of liblnocc (include/lnocc.h), same names as the C ABI.
+
+Argument marshalling only: every step of the fragment solve runs in the HIP
+library.  PyTorch supplies device memory (tensors, the workspace) and the
+stream.  Importing this module fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import pathlib
+
+_PKG = pathlib.Path(__file__).resolve().parent
+_LIB_PATH = _PKG / "liblnocc.so"
+
+LNOCC_OK = 0
+LNOCC_NOT_CONVERGED = 1
+LNOCC_EINVAL = -1
+LNOCC_ENOMEM = -2
+LNOCC_EDEVICE = -3
+LNOCC_ENUMERIC = -4
+
+LNOCC_FP64, LNOCC_FP32, LNOCC_BF16 = 0, 1, 2
+LNOCC_GUESS_MP2, LNOCC_GUESS_USER = 0, 1
+
+PRECISIONS = {"fp64": LNOCC_FP64, "fp32": LNOCC_FP32, "bf16": LNOCC_BF16}
+
+
+class lnocc_fragment_t(C.Structure):
+    _fields_ = [
+        ("nocc", C.c_int32), ("nvir", C.c_int32), ("naux", C.c_int32), ("reserved0", C.c_int32),
+        ("B", C.c_void_p), ("eps_occ", C.c_void_p), ("eps_vir", C.c_void_p),
+        ("conv_tol", C.c_double),
+        ("t1", C.c_void_p), ("t2", C.c_void_p),
+        ("e_mp2", C.c_double), ("e_ccsd", C.c_double), ("e_t", C.c_double),
+        ("residual", C.c_double),
+        ("n_iter", C.c_int32), ("status", C.c_int32),
+    ]
+
+
+class lnocc_options_t(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32), ("guess", C.c_int32), ("do_triples", C.c_int32),
+        ("max_iter", C.c_int32), ("diis_space", C.c_int32), ("diis_start", C.c_int32),
+        ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+        ("ladder_chunk_bytes", C.c_size_t), ("triples_batch", C.c_int32),
+        ("reserved1", C.c_int32),
+    ]
+
+
+class lnocc_operand_t(C.Structure):
+    _fields_ = [("p", C.c_void_p), ("s_ro", C.c_int64), ("s_ri", C.c_int64),
+                ("s_ko", C.c_int64), ("s_ki", C.c_int64), ("b0", C.c_int64),
+                ("b1", C.c_int64), ("bid", C.c_int64)]
+
+
+class lnocc_contract_t(C.Structure):
+    _fields_ = [
+        ("M", C.c_int32), ("Mi", C.c_int32), ("N", C.c_int32), ("Ni", C.c_int32),
+        ("nseg", C.c_int32), ("K", C.c_int32 * 4), ("Ki", C.c_int32 * 4),
+        ("scale", C.c_double * 4), ("a", lnocc_operand_t * 4), ("b", lnocc_operand_t * 4),
+        ("c", C.c_void_p), ("c_mo", C.c_int64), ("c_mi", C.c_int64), ("c_no", C.c_int64),
+        ("c_ni", C.c_int64), ("c_b0", C.c_int64), ("c_b1", C.c_int64), ("c_bid", C.c_int64),
+        ("beta", C.c_double), ("batch", C.c_int32), ("nb1", C.c_int32),
+    ]
+
+
+EXPORTS = ("lnocc_default_options", "lnocc_status_string", "lnocc_workspace_bytes",
+           "lnocc_fragment_ccsd", "lnocc_fragment_triples", "lnocc_ccsd_residuals",
+           "lnocc_batch_solve", "lnocc_contract")
+
+
+def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
+    p = pathlib.Path(path) if path else _LIB_PATH
+    if not p.exists():
+        raise RuntimeError(f"liblnocc not built ({p}); run paper_2407_11258_amd.build_lib.build()")
+    lib = C.CDLL(str(p))
+    FP, OP = C.POINTER(lnocc_fragment_t), C.POINTER(lnocc_options_t)
+    lib.lnocc_default_options.argtypes = [OP]
+    lib.lnocc_default_options.restype = None
+    lib.lnocc_status_string.argtypes = [C.c_int]
+    lib.lnocc_status_string.restype = C.c_char_p
+    lib.lnocc_workspace_bytes.argtypes = [FP, C.c_int32, OP, C.POINTER(C.c_size_t)]
+    lib.lnocc_workspace_bytes.restype = C.c_int
+    for name in ("lnocc_fragment_ccsd", "lnocc_fragment_triples"):
+        getattr(lib, name).argtypes = [FP, OP]
+        getattr(lib, name).restype = C.c_int
+    lib.lnocc_ccsd_residuals.argtypes = [FP, OP, C.c_void_p, C.c_void_p]
+    lib.lnocc_ccsd_residuals.restype = C.c_int
+    lib.lnocc_batch_solve.argtypes = [FP, C.c_int32, OP]
+    lib.lnocc_batch_solve.restype = C.c_int
+    lib.lnocc_contract.argtypes = [C.POINTER(lnocc_contract_t), C.c_void_p]
+    lib.lnocc_contract.restype = C.c_int
+    return lib
+
+
+_lib = load_library()
+
+
+# ------------------------------------------------------------ same-name wrappers
+def lnocc_default_options() -> lnocc_options_t:
+    opt = lnocc_options_t()
+    _lib.lnocc_default_options(C.byref(opt))
+    return opt
+
+
+def lnocc_status_string(status: int) -> str:
+    return _lib.lnocc_status_string(int(status)).decode()
+
+
+def lnocc_workspace_bytes(frags, opt: lnocc_options_t) -> tuple[int, int]:
+    arr = (lnocc_fragment_t * len(frags))(*frags)
+    out = C.c_size_t(0)
+    st = _lib.lnocc_workspace_bytes(arr, len(frags), C.byref(opt), C.byref(out))
+    return st, out.value
+
+
+def lnocc_fragment_ccsd(frag: lnocc_fragment_t, opt: lnocc_options_t) -> int:
+    return _lib.lnocc_fragment_ccsd(C.byref(frag), C.byref(opt))
+
+
+def lnocc_fragment_triples(frag: lnocc_fragment_t, opt: lnocc_options_t) -> int:
+    return _lib.lnocc_fragment_triples(C.byref(frag), C.byref(opt))
+
+
+def lnocc_ccsd_residuals(frag: lnocc_fragment_t, opt: lnocc_options_t, r1_ptr: int,
+                         r2_ptr: int) -> int:
+    return _lib.lnocc_ccsd_residuals(C.byref(frag), C.byref(opt), r1_ptr, r2_ptr)
+
+
+def lnocc_batch_solve(frags, opt: lnocc_options_t) -> int:
+    """frags: ctypes array of lnocc_fragment_t (results are written into it)."""
+    return _lib.lnocc_batch_solve(frags, len(frags), C.byref(opt))
+
+
+def lnocc_contract(desc: lnocc_contract_t, stream: int = 0) -> int:
+    return _lib.lnocc_contract(C.byref(desc), C.c_void_p(stream))
+
+
+# ------------------------------------------------------------ torch helpers
+@dataclasses.dataclass
+class Result:
+    status: int
+    e_mp2: float
+    e_ccsd: float
+    e_t: float
+    n_iter: int
+    residual: float
+    t1: object
+    t2: object
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(torch):
+    return torch.cuda.current_stream().cuda_stream
+
+
+def make_fragment_struct(B, eps_occ, eps_vir, t1, t2, conv_tol: float) -> lnocc_fragment_t:
+    f = lnocc_fragment_t()
+    f.nocc, f.nvir, f.naux = eps_occ.numel(), eps_vir.numel(), B.shape[0]
+    f.B, f.eps_occ, f.eps_vir = B.data_ptr(), eps_occ.data_ptr(), eps_vir.data_ptr()
+    f.conv_tol = conv_tol
+    f.t1 = t1.data_ptr() if t1 is not None else None
+    f.t2 = t2.data_ptr() if t2 is not None else None
+    return f
+
+
+def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int = 100,
+                 diis_space: int = 8, diis_start: int = 2, guess: int = LNOCC_GUESS_MP2,
+                 ladder_chunk_bytes: int = 0, triples_batch: int = 0) -> lnocc_options_t:
+    opt = lnocc_default_options()
+    opt.precision = PRECISIONS[precision]
+    opt.do_triples = int(do_triples)
+    opt.max_iter = max_iter
+    opt.diis_space = diis_space
+    opt.diis_start = diis_start
+    opt.guess = guess
+    opt.ladder_chunk_bytes = ladder_chunk_bytes
+    opt.triples_batch = triples_batch
+    return opt
+
+
+class Workspace:
+    """A torch-allocated device buffer that grows on demand."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def ensure(self, nbytes: int):
+        torch = _torch()
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+    def attach(self, frags, opt: lnocc_options_t):
+        st, nbytes = lnocc_workspace_bytes(frags, opt)
+        if st != LNOCC_OK:
+            raise ValueError(lnocc_status_string(st))
+        buf = self.ensure(nbytes)
+        opt.workspace = buf.data_ptr()
+        opt.workspace_bytes = buf.numel()
+        opt.stream = _stream_handle(_torch())
+        return opt
+
+
+def solve(B, eps_occ, eps_vir, *, conv_tol=1e-8, t1=None, t2=None, workspace=None, **kw) -> Result:
+    """Fragment CCSD(T) on device tensors (FP64). Returns energies and amplitudes."""
+    torch = _torch()
+    o, v = eps_occ.numel(), eps_vir.numel()
+    if t1 is None:
+        t1 = torch.empty((o, v), dtype=torch.float64, device=B.device)
+    if t2 is None:
+        t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=B.device)
+    opt = make_options(**kw)
+    f = make_fragment_struct(B, eps_occ, eps_vir, t1, t2, conv_tol)
+    ws = workspace or Workspace(B.device)
+    ws.attach([f], opt)
+    st = lnocc_fragment_ccsd(f, opt)
+    return Result(st, f.e_mp2, f.e_ccsd, f.e_t, f.n_iter, f.residual, t1, t2)

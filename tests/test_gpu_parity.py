@@ -1,0 +1,245 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances (FP64 everywhere on this path): residuals and single contractions
+1e-11 absolute on O(1) values (rounding of sums with up to a few thousand
+terms); converged energies 1e-8 Eh and amplitudes 1e-7 (the convergence
+threshold 1e-8 on ||dT||, both sides converge independently); the (T) energy
+of given amplitudes 1e-11 relative.
+"""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_2407_11258_amd import lnocc as L  # noqa: E402
+from oracle import ccsd as occ, triples as otr  # noqa: E402
+from synth import make_fragment  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", file=sys.stderr, flush=True)
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _random_amplitudes(o, v, seed, scale=0.05):
+    rng = np.random.default_rng(seed)
+    t1 = scale * rng.standard_normal((o, v))
+    t2 = scale * rng.standard_normal((o, o, v, v))
+    return t1, t2 + t2.transpose(1, 0, 3, 2)
+
+
+# ------------------------------------------------------------ contraction kernel
+_KEEP = []   # device tensors referenced by raw pointers must outlive the call
+
+
+def _operand(t, ro, ri, ko, ki, b0=0, b1=0, bid=0):
+    _KEEP.append(t)
+    return L.lnocc_operand_t(t.data_ptr(), ro, ri, ko, ki, b0, b1, bid)
+
+
+def _contract(M, Mi, N, Ni, c, cstr, segs, beta=0.0, batch=1, nb1=1, cb=(0, 0, 0)):
+    d = L.lnocc_contract_t()
+    d.M, d.Mi, d.N, d.Ni = M, Mi, N, Ni
+    d.nseg = len(segs)
+    for s, (K, Ki, scale, a, b) in enumerate(segs):
+        d.K[s], d.Ki[s], d.scale[s] = K, Ki, scale
+        d.a[s], d.b[s] = a, b
+    d.c = c.data_ptr()
+    d.c_mo, d.c_mi, d.c_no, d.c_ni = cstr
+    d.c_b0, d.c_b1, d.c_bid = cb
+    d.beta, d.batch, d.nb1 = beta, batch, nb1
+    st = L.lnocc_contract(d, torch.cuda.current_stream().cuda_stream)
+    _KEEP.clear()
+    assert st == L.LNOCC_OK, L.lnocc_status_string(st)
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (130, 70, 37), (257, 129, 200), (64, 300, 5)])
+def test_contract_plain_and_transposed(M, N, K):
+    say(f"contract plain M={M} N={N} K={K}")
+    rng = np.random.default_rng(M + N + K)
+    A = rng.standard_normal((M, K))
+    Bm = rng.standard_normal((N, K))
+    ref = A @ Bm.T
+    c = torch.zeros((M, N), dtype=torch.float64, device=DEV)
+    # operands contiguous along k
+    _contract(M, 1, N, 1, c, (N, 0, 1, 0),
+              [(K, 1, 1.0, _operand(dev(A), K, 0, 1, 0), _operand(dev(Bm), K, 0, 1, 0))])
+    np.testing.assert_allclose(host(c), ref, rtol=0, atol=1e-12 * max(1, K))
+    # operands contiguous along the row index (stored transposed), C transposed
+    At, Bt = dev(A.T.copy()), dev(Bm.T.copy())
+    ct = torch.zeros((N, M), dtype=torch.float64, device=DEV)
+    _contract(M, 1, N, 1, ct, (1, 0, M, 0),
+              [(K, 1, 1.0, _operand(At, 1, 0, M, 0), _operand(Bt, 1, 0, N, 0))])
+    np.testing.assert_allclose(host(ct).T, ref, rtol=0, atol=1e-12 * max(1, K))
+
+
+def test_contract_two_index_modes_segments_and_batch():
+    say("contract two-index modes, segments, batch")
+    o, v, nb0, nb1 = 5, 19, 2, 3
+    rng = np.random.default_rng(3)
+    T = rng.standard_normal((nb0, o, o, v, v))      # T[e0][k][i][a][c]
+    U = rng.standard_normal((nb1, o, o, v, v))      # U[e1][k][j][b][c]
+    P = rng.standard_normal((v, 7))                 # second segment: sum_e P[a, e] Q[b, e]
+    Qm = rng.standard_normal((v, 7))
+    C0 = rng.standard_normal((nb0 * nb1, o, o, v, v))
+    ref = np.einsum("xkiac,ykjbc->xyijab", T, U).reshape(nb0 * nb1, o, o, v, v)
+    ref = ref - 0.5 * np.einsum("ae,be->ab", P, Qm)[None, None, None] + 2.0 * C0
+    c = dev(C0)
+    ovv, vv = o * v * v, v * v
+    # m = (i, a), n = (j, b), k = (k, c); C[e][i][j][a][b]
+    seg1 = (o * v, v, 1.0,
+            _operand(dev(T), vv, v, ovv, 1, b0=o * ovv),
+            _operand(dev(U), vv, v, ovv, 1, b1=o * ovv))
+    # the same C for every (i, j) pair: rows (i, a) with zero stride on i
+    seg2 = (7, 1, -0.5, _operand(dev(P), 0, 7, 1, 0), _operand(dev(Qm), 0, 7, 1, 0))
+    _contract(o * v, v, o * v, v, c, (ovv, v, vv, 1), [seg1, seg2], beta=2.0,
+              batch=nb0 * nb1, nb1=nb1, cb=(0, 0, o * ovv))
+    np.testing.assert_allclose(host(c), ref, rtol=0, atol=1e-11)
+
+
+# ------------------------------------------------------------ solver pieces
+def _fragment_on_device(f, scale=1.0):
+    return dev(scale * f.B), dev(f.eps_occ), dev(f.eps_vir)
+
+
+def _call(fn, f, B, eo, ev, t1, t2, conv_tol=1e-8, **kw):
+    opt = L.make_options(**kw)
+    fs = L.make_fragment_struct(B, eo, ev, t1, t2, conv_tol)
+    ws = L.Workspace(DEV)
+    ws.attach([fs], opt)
+    st = fn(fs, opt)
+    return st, fs
+
+
+@pytest.mark.parametrize("o,v,X,seed", [(3, 13, 40, 21), (2, 37, 61, 22), (5, 9, 17, 23)])
+def test_residuals_match_oracle(o, v, X, seed):
+    say(f"residuals o={o} v={v} X={X}")
+    f = make_fragment(o, v, X, seed)
+    t1, t2 = _random_amplitudes(o, v, seed)
+    R1o, R2o = occ.residuals(2.0 * f.B, f.eps_occ, f.eps_vir, t1, t2)
+    B, eo, ev = _fragment_on_device(f, 2.0)
+    t1d, t2d = dev(t1), dev(t2)
+    r1 = torch.empty((o, v), dtype=torch.float64, device=DEV)
+    r2 = torch.empty((o, o, v, v), dtype=torch.float64, device=DEV)
+    opt = L.make_options()
+    fs = L.make_fragment_struct(B, eo, ev, t1d, t2d, 1e-8)
+    ws = L.Workspace(DEV)
+    ws.attach([fs], opt)
+    st = L.lnocc_ccsd_residuals(fs, opt, r1.data_ptr(), r2.data_ptr())
+    assert st == L.LNOCC_OK, L.lnocc_status_string(st)
+    np.testing.assert_allclose(host(r1), R1o, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(host(r2), R2o, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("o,v,X,seed", [(3, 13, 40, 31), (4, 21, 50, 32), (1, 10, 20, 33)])
+def test_triples_match_oracle(o, v, X, seed):
+    say(f"triples o={o} v={v} X={X}")
+    f = make_fragment(o, v, X, seed)
+    t1, t2 = _random_amplitudes(o, v, seed, scale=0.1)
+    ref = otr.e_triples_restricted(2.0 * f.B, f.eps_occ, f.eps_vir, t1, t2)
+    B, eo, ev = _fragment_on_device(f, 2.0)
+    st, fs = _call(L.lnocc_fragment_triples, f, B, eo, ev, dev(t1), dev(t2), triples_batch=3)
+    assert st == L.LNOCC_OK, L.lnocc_status_string(st)
+    if o == 1:
+        assert fs.e_t == 0.0
+    else:
+        assert abs(fs.e_t - ref) < 1e-11 * max(1.0, abs(ref)), (fs.e_t, ref)
+
+
+@pytest.mark.parametrize("o,v,X,seed,chunk", [(4, 20, 72, 0, 0), (6, 45, 100, 5, 45 ** 3 * 8 * 7),
+                                              (2, 3, 5, 9, 0)])
+def test_full_solve_matches_oracle(o, v, X, seed, chunk):
+    say(f"full solve o={o} v={v} X={X} seed={seed}")
+    f = make_fragment(o, v, X, seed)
+    ref = occ.ccsd(f.B, f.eps_occ, f.eps_vir, conv_tol=1e-10)
+    assert ref.converged
+    ref_t = otr.e_triples_restricted(f.B, f.eps_occ, f.eps_vir, ref.t1, ref.t2)
+    B, eo, ev = _fragment_on_device(f)
+    t1 = torch.empty((o, v), dtype=torch.float64, device=DEV)
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=DEV)
+    st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=1e-10,
+                   ladder_chunk_bytes=chunk)
+    assert st == L.LNOCC_OK, L.lnocc_status_string(st)
+    assert abs(fs.e_mp2 - ref.e_mp2) < 1e-12
+    assert abs(fs.e_ccsd - ref.e_ccsd) < 1e-8
+    assert abs(fs.e_t - ref_t) < 1e-8
+    np.testing.assert_allclose(host(t2), ref.t2, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(host(t1), ref.t1, rtol=0, atol=1e-7)
+    assert fs.residual <= 1e-10
+
+
+def test_solve_is_bitwise_reproducible():
+    say("determinism o=4 v=20")
+    f = make_fragment(4, 20, 72, 0)
+    B, eo, ev = _fragment_on_device(f)
+    out = []
+    for _ in range(2):
+        t1 = torch.empty((4, 20), dtype=torch.float64, device=DEV)
+        t2 = torch.empty((4, 4, 20, 20), dtype=torch.float64, device=DEV)
+        st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2)
+        assert st == L.LNOCC_OK
+        out.append((fs.e_ccsd, fs.e_t, fs.n_iter, host(t2).tobytes()))
+    assert out[0] == out[1]
+
+
+def test_error_paths_on_device():
+    say("error paths")
+    f = make_fragment(3, 8, 20, 4)
+    B, eo, ev = _fragment_on_device(f)
+    t1 = torch.empty((3, 8), dtype=torch.float64, device=DEV)
+    t2 = torch.empty((3, 3, 8, 8), dtype=torch.float64, device=DEV)
+    # overlapping spectrum: rejected before any solve
+    bad = ev.clone()
+    bad[0] = eo.max() + 0.0
+    st, _ = _call(L.lnocc_fragment_ccsd, f, B, eo, bad, t1, t2)
+    assert st == L.LNOCC_EINVAL
+    # non-finite energy
+    nan = eo.clone()
+    nan[1] = float("nan")
+    st, _ = _call(L.lnocc_fragment_ccsd, f, B, nan, ev, t1, t2)
+    assert st == L.LNOCC_EINVAL
+    # workspace too small
+    opt = L.make_options()
+    fs = L.make_fragment_struct(B, eo, ev, t1, t2, 1e-8)
+    ws = L.Workspace(DEV)
+    ws.attach([fs], opt)
+    opt.workspace_bytes -= 4096
+    assert L.lnocc_fragment_ccsd(fs, opt) == L.LNOCC_ENOMEM
+    # iteration limit: warning, last iterate and its energy returned
+    st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, max_iter=1, do_triples=False)
+    assert st == L.LNOCC_NOT_CONVERGED and fs.n_iter == 1 and np.isfinite(fs.e_ccsd)
+    # no iteration: energy of the MP2 guess
+    st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, max_iter=0, do_triples=False)
+    assert st == L.LNOCC_OK and fs.e_ccsd == fs.e_mp2
+
+
+def test_restart_from_converged_amplitudes():
+    say("restart")
+    f = make_fragment(4, 20, 72, 0)
+    B, eo, ev = _fragment_on_device(f)
+    t1 = torch.empty((4, 20), dtype=torch.float64, device=DEV)
+    t2 = torch.empty((4, 4, 20, 20), dtype=torch.float64, device=DEV)
+    st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=1e-10)
+    assert st == L.LNOCC_OK
+    st2, fs2 = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=1e-9,
+                     guess=L.LNOCC_GUESS_USER)
+    assert st2 == L.LNOCC_OK and fs2.n_iter == 1
+    assert abs(fs2.e_ccsd - fs.e_ccsd) < 1e-10 and abs(fs2.e_t - fs.e_t) < 1e-10
