@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Fragment CCSD(T) throughput on one MI355X.
+
+One step = one complete fragment solve through the C ABI
+(lnocc_fragment_ccsd: DF split, MP2 guess, CCSD iterations to the residual
+threshold, then (T)) on the realistic synthetic fragment (nocc=16, nvir=160,
+naux=528, seed 1).  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line with solves/s, the (T) contraction rate, the roofline
+position of the dominant contraction kernel (timed with HIP events on its own
+stream inside the timed region) and the FP64 CPU oracle timed on a bounded
+sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import pathlib
+import sys
+import time
+
+import numpy as np
+
+ROOT = pathlib.Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "fragment CCSD(T) solves/s + (T) TFLOP/s, mixed vs FP64, at |ΔE|≤1e-6 Eh"
+PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+DTYPES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted((ROOT / "paper_2407_11258_amd" / "csrc").glob("*")):
+        h.update(p.read_bytes())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(frag, n_iter: int, budget_triples: int = 4) -> dict:
+    """The oracle as it stands, on a bounded sample of the same fragment:
+    one CCSD residual evaluation and a few unique (T) triples, scaled to one
+    solve (n_iter residual evaluations plus every unique triple)."""
+    from oracle import ccsd as occ, triples as otr
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    o, v = frag.nocc, frag.nvir
+    t2, _ = occ.mp2(frag.B, frag.eps_occ, frag.eps_vir)
+    t1 = np.zeros((o, v))
+    t0 = time.perf_counter()
+    occ.residuals(frag.B, frag.eps_occ, frag.eps_vir, t1, t2)
+    t_res = time.perf_counter() - t0
+    ints = otr.TriplesIntegrals(frag.B, o)
+    triples = [(i, j, k) for i in range(o) for j in range(i, o) for k in range(j, o)
+               if not (i == j == k)]
+    t0 = time.perf_counter()
+    for (i, j, k) in triples[:budget_triples]:
+        otr.w_v(ints, t1, t2, i, j, k)
+    t_trip = (time.perf_counter() - t0) / max(1, min(budget_triples, len(triples)))
+    est = n_iter * t_res + len(triples) * t_trip
+    return {"value": 1.0 / est, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"1 CCSD residual ({t_res:.2f} s) x {n_iter} iterations + "
+                       f"{min(budget_triples, len(triples))} of {len(triples)} unique (T) triples "
+                       f"({t_trip:.2f} s each); estimated {est:.1f} s per solve")}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="single_realistic")
+    ap.add_argument("--precision", default="fp64", choices=sorted(PEAKS_TFLOPS))
+    ap.add_argument("--conv-tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(fragments would be sharded across GPUs with no exchange but the final "
+              "energies); run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2407_11258_amd import lnocc as L
+    from synth import CONFIG_SHAPES, make_fragment
+
+    o, v, X, seed = CONFIG_SHAPES[args.workload]
+    log(f"workload {args.workload}: nocc={o} nvir={v} naux={X} seed={seed}")
+    frag = make_fragment(o, v, X, seed)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    B = torch.tensor(frag.B, device=dev)
+    eo = torch.tensor(frag.eps_occ, device=dev)
+    ev = torch.tensor(frag.eps_vir, device=dev)
+    t1 = torch.empty((o, v), dtype=torch.float64, device=dev)
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=dev)
+    opt = L.make_options(precision=args.precision)
+    fs = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
+    ws = L.Workspace(dev)
+    ws.attach([fs], opt)
+    log(f"workspace {opt.workspace_bytes / 2**30:.2f} GiB")
+
+    def step():
+        st = L.lnocc_fragment_ccsd(fs, opt)
+        if st < 0:
+            raise RuntimeError(L.lnocc_status_string(st))
+        return st
+
+    for w in range(args.warmup):
+        step()
+        log(f"warmup {w + 1}/{args.warmup}: {fs.n_iter} iterations, E_CCSD={fs.e_ccsd:.10f}")
+    torch.cuda.synchronize()
+    L.lnocc_profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    L.lnocc_profile_enable(False)
+    prof = L.lnocc_profile_collect()
+    status = fs.status
+
+    # (T) alone on the converged amplitudes
+    ft = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
+    L.lnocc_fragment_triples(ft, opt)
+    torch.cuda.synchronize()
+    nrep = 2
+    t0 = time.perf_counter()
+    for _ in range(nrep):
+        st = L.lnocc_fragment_triples(ft, opt)
+    torch.cuda.synchronize()
+    t_triples = (time.perf_counter() - t0) / nrep
+    f_t = 2.0 * o ** 3 * v ** 4 + 2.0 * o ** 4 * v ** 3
+    log(f"(T): {t_triples * 1e3:.1f} ms, E_(T)={ft.e_t:.12f}")
+
+    dominant = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dominant]
+    achieved = d["flops"] / d["ms"] / 1e9 if d["ms"] > 0 else 0.0
+    peak = PEAKS_TFLOPS[args.precision]
+    traffic = None
+    tpath = ROOT / "profiles" / "traffic.json"
+    if tpath.exists():
+        tj = json.loads(tpath.read_text())
+        ent = tj.get(f"{args.workload}:{args.precision}:{dominant}")
+        if ent and ent.get("sources") == kernel_sources_hash():
+            traffic = ent.get("bytes_per_launch")
+
+    parity = None
+    gpath = ROOT / "tests" / "golden" / f"{args.workload}.json"
+    if gpath.exists():
+        g = json.loads(gpath.read_text())
+        if g.get("input_sha256") == frag.sha256():
+            parity = {"d_e_ccsd": fs.e_ccsd - g["e_ccsd"], "d_e_t": ft.e_t - g["e_t"]}
+
+    result = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPES[args.precision],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "nocc": o, "nvir": v, "naux": X, "seed": seed,
+                   "precision": args.precision, "conv_tol": args.conv_tol,
+                   "ccsd_iterations": fs.n_iter, "status": status},
+        "triples_tflops": f_t / t_triples / 1e12,
+        "triples_ms": t_triples * 1e3,
+        "e_ccsd": fs.e_ccsd,
+        "e_t": ft.e_t,
+        "parity_vs_oracle": parity,
+        "kernels": {k: {"launches": p["launches"], "ms_total": p["ms"],
+                        "tflops": (p["flops"] / p["ms"] / 1e9) if p["ms"] > 0 else None}
+                    for k, p in prof.items()},
+        "roofline": {"bound": "mfma", "kernel": dominant, "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                     "flops_per_launch": d["flops"] / max(1, d["launches"]),
+                     "avg_launch_ms": d["ms"] / max(1, d["launches"])},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        result["cpu_baseline"] = cpu_baseline(frag, fs.n_iter)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

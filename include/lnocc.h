@@ -165,6 +165,25 @@ typedef struct lnocc_contract_t {
 
 int lnocc_contract(const lnocc_contract_t *desc, void *stream);
 
+/* ---- launch timing ----------------------------------------------------------
+ * While enabled, each contraction launch is bracketed by HIP events recorded on
+ * the stream it runs on.  lnocc_profile_collect waits for the recorded events,
+ * returns per-class totals and clears them.  Classes:
+ *   0 other contractions (intermediates, T1 dressing, Fock, one-off integrals)
+ *   1 (ac|bd) formation for the particle-particle ladder (Eq. 27a over Q)
+ *   2 ladder contraction  sum_cd t_ij^cd (ac|bd)
+ *   3 (T) W contraction   (SI Sec. S1) for batches of unique triples
+ * flops counts 2 M N K per product term (the algorithmic count). */
+typedef struct lnocc_kernel_stats_t {
+  int64_t launches;
+  double ms;
+  double flops;
+} lnocc_kernel_stats_t;
+
+#define LNOCC_KERNEL_CLASSES 4
+void lnocc_profile_enable(int on);
+void lnocc_profile_collect(lnocc_kernel_stats_t out[LNOCC_KERNEL_CLASSES]);
+
 /* ---- validation mode -------------------------------------------------------
  * on != 0: every later call runs its host logic and launch sequence without
  * touching a device.  Each contraction launch is checked to stay inside the

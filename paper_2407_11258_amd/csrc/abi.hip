@@ -223,6 +223,14 @@ int lnocc_batch_solve(lnocc_fragment_t *f, int32_t nfrag, const lnocc_options_t 
 
 void lnocc_set_validation_mode(int on) { set_dry_run(on != 0); }
 
+void lnocc_profile_enable(int on) { profile_enable(on != 0); }
+
+void lnocc_profile_collect(lnocc_kernel_stats_t out[LNOCC_KERNEL_CLASSES]) {
+  KindStats k[(int)Kind::Count];
+  profile_collect(k);
+  for (int i = 0; i < LNOCC_KERNEL_CLASSES; ++i) out[i] = lnocc_kernel_stats_t{k[i].launches, k[i].ms, k[i].flops};
+}
+
 int lnocc_contract(const lnocc_contract_t *c, void *stream) {
   if (!c || !c->c || c->nseg < 1 || c->nseg > 4 || c->M < 0 || c->N < 0 || c->Mi < 1 ||
       c->Ni < 1 || c->batch < 1 || c->nb1 < 1 || c->batch > 65535)

@@ -17,6 +17,16 @@ namespace lnocc {
 
 enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
 
+// What a contraction computes; each class is its own kernel symbol (so
+// profiler statistics separate them) and its own timing bucket.
+enum class Kind : int {
+  Other = 0,          // CCSD intermediates, dressing, Fock, one-off integrals
+  LadderBuild = 1,    // (ac|bd)~ = sum_Q B~_Qac B~_Qbd for a block of a
+  LadderContract = 2, // R2 += sum_cd t_ij^cd (ac|bd)~
+  TriplesW = 3,       // W_ijk^abc for a batch of unique triples
+  Count = 4
+};
+
 struct GOperand {
   const void *p;          // element type given by GemmDesc::in_type
   int64_t s_ro, s_ri;     // strides of the outer / inner row (m or n) index
@@ -47,7 +57,14 @@ struct GemmDesc {
   const int *table;       // device int triples, batch entry id -> (i0, i1, i2)
   int tmax[3];            // with a table: largest value of each batch integer
   Prec prec;              // arithmetic of the products (inputs are FP64 in memory)
+  Kind kind;
 };
+
+// Launch timing: while enabled, every contraction launch is bracketed by HIP
+// events on its stream; collect() waits for them and sums per Kind.
+struct KindStats { int64_t launches; double ms; double flops; };
+void profile_enable(bool on);
+void profile_collect(KindStats out[(int)Kind::Count]);   // also clears
 
 // Address guard.  While a region list is installed (per host thread), gett()
 // refuses to launch a contraction unless every address it can touch lies

@@ -12,6 +12,7 @@
 #include "gett.h"
 
 #include <algorithm>
+#include <vector>
 #include <cstdio>
 #include <cstdlib>
 
@@ -110,6 +111,7 @@ __device__ inline void row_offsets(const GOperand &op, bool kfast, int nrows, in
   }
 }
 
+template <int KIND>
 __global__ __launch_bounds__(kThreads) void gett_f64_kernel(GemmDesc d, int tiles_m) {
   __shared__ double As[BK * LDA];
   __shared__ double Bs[BK * LDB];
@@ -265,6 +267,28 @@ bool descriptor_ok(const GemmDesc &d) {
 }  // namespace
 
 static bool g_dry = false;
+
+struct Record { Kind kind; hipEvent_t start, stop; double flops; };
+static bool g_profile = false;
+static std::vector<Record> g_records;
+
+void profile_enable(bool on) { g_profile = on; }
+
+void profile_collect(KindStats out[(int)Kind::Count]) {
+  for (int k = 0; k < (int)Kind::Count; ++k) out[k] = KindStats{0, 0.0, 0.0};
+  for (const Record &r : g_records) {
+    float ms = 0.f;
+    hipEventSynchronize(r.stop);
+    hipEventElapsedTime(&ms, r.start, r.stop);
+    KindStats &k = out[(int)r.kind];
+    k.launches += 1;
+    k.ms += ms;
+    k.flops += r.flops;
+    hipEventDestroy(r.start);
+    hipEventDestroy(r.stop);
+  }
+  g_records.clear();
+}
 bool dry_run() { return g_dry; }
 void set_dry_run(bool on) { g_dry = on; }
 
@@ -299,8 +323,30 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   const int tiles_m = (d.M + BM - 1) / BM;
   const int tiles_n = (d.N + BN - 1) / BN;
   dim3 grid(tiles_m * tiles_n, d.batch);
-  hipLaunchKernelGGL(gett_f64_kernel, grid, dim3(kThreads), 0, stream, d, tiles_m);
-  return hipGetLastError();
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (g_profile) {
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+      return hipErrorOutOfMemory;
+    hipEventRecord(ev[0], stream);
+  }
+  switch (d.kind) {
+    case Kind::LadderBuild:
+      hipLaunchKernelGGL(gett_f64_kernel<1>, grid, dim3(kThreads), 0, stream, d, tiles_m); break;
+    case Kind::LadderContract:
+      hipLaunchKernelGGL(gett_f64_kernel<2>, grid, dim3(kThreads), 0, stream, d, tiles_m); break;
+    case Kind::TriplesW:
+      hipLaunchKernelGGL(gett_f64_kernel<3>, grid, dim3(kThreads), 0, stream, d, tiles_m); break;
+    default:
+      hipLaunchKernelGGL(gett_f64_kernel<0>, grid, dim3(kThreads), 0, stream, d, tiles_m); break;
+  }
+  const hipError_t err = hipGetLastError();
+  if (g_profile) {
+    hipEventRecord(ev[1], stream);
+    double flops = 0.0;
+    for (int s = 0; s < d.nseg; ++s) flops += 2.0 * d.M * (double)d.N * d.seg[s].K;
+    g_records.push_back(Record{d.kind, ev[0], ev[1], flops * d.batch});
+  }
+  return err;
 }
 
 GemmDesc gemm_desc(int M, int N, int K, double alpha,

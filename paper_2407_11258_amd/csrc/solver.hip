@@ -301,9 +301,11 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     const int64_t na = std::min<int64_t>(L.chunk_a, v - a0);
     GemmDesc d = DESC(na * v, v, vv, v, L.chunk, vvv, v, vv, 1, 0.0);
     SEG(d, X, 1, 1.0, OP(L.Btvv + a0 * v, v, 1, vv, 0), OP(L.Btvv, v, 1, vv, 0));
+    d.kind = Kind::LadderBuild;
     LN_TRY(gett(d, s));
     d = DESC(oo, 1, na * v, 1, L.R2 + a0 * v, vv, 0, 1, 0, 1.0);
     SEG(d, vv, 1, 1.0, OP(t2, vv, 0, 1, 0), OP(L.chunk, vv, 0, 1, 0));
+    d.kind = Kind::LadderContract;
     LN_TRY(gett(d, s));
   }
   {  // hole-hole ladder: W_klij = (ki|lj)~ + sum_cd (kc|ld) t_ij^cd ; R2 += sum_kl t_kl^ab W_klij
@@ -536,7 +538,7 @@ int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s) 
     const int nb = (int)std::min<int64_t>(L.nb, L.ntriples - t0);
     const int *table = L.table + 3 * t0;
     auto finish = [&](GemmDesc &d) {
-      d.batch = nb; d.table = table; d.c_bid = vvv;
+      d.batch = nb; d.table = table; d.c_bid = vvv; d.kind = Kind::TriplesW;
       d.tmax[0] = d.tmax[1] = d.tmax[2] = (int)(o - 1);
     };
     {  // rows (a,b), column c: P1, P3, H1, H3

@@ -66,9 +66,17 @@ class lnocc_contract_t(C.Structure):
     ]
 
 
+class lnocc_kernel_stats_t(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("flops", C.c_double)]
+
+
+LNOCC_KERNEL_CLASSES = 4
+KERNEL_CLASS_NAMES = ("other", "ladder_build", "ladder_contract", "triples_w")
+
 EXPORTS = ("lnocc_default_options", "lnocc_status_string", "lnocc_workspace_bytes",
            "lnocc_fragment_ccsd", "lnocc_fragment_triples", "lnocc_ccsd_residuals",
-           "lnocc_batch_solve", "lnocc_contract")
+           "lnocc_batch_solve", "lnocc_contract", "lnocc_profile_enable",
+           "lnocc_profile_collect", "lnocc_set_validation_mode")
 
 
 def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
@@ -92,6 +100,12 @@ def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
     lib.lnocc_batch_solve.restype = C.c_int
     lib.lnocc_contract.argtypes = [C.POINTER(lnocc_contract_t), C.c_void_p]
     lib.lnocc_contract.restype = C.c_int
+    lib.lnocc_profile_enable.argtypes = [C.c_int]
+    lib.lnocc_profile_enable.restype = None
+    lib.lnocc_profile_collect.argtypes = [C.POINTER(lnocc_kernel_stats_t)]
+    lib.lnocc_profile_collect.restype = None
+    lib.lnocc_set_validation_mode.argtypes = [C.c_int]
+    lib.lnocc_set_validation_mode.restype = None
     return lib
 
 
@@ -136,6 +150,21 @@ def lnocc_batch_solve(frags, opt: lnocc_options_t) -> int:
 
 def lnocc_contract(desc: lnocc_contract_t, stream: int = 0) -> int:
     return _lib.lnocc_contract(C.byref(desc), C.c_void_p(stream))
+
+
+def lnocc_profile_enable(on: bool) -> None:
+    _lib.lnocc_profile_enable(int(bool(on)))
+
+
+def lnocc_profile_collect() -> dict:
+    arr = (lnocc_kernel_stats_t * LNOCC_KERNEL_CLASSES)()
+    _lib.lnocc_profile_collect(arr)
+    return {KERNEL_CLASS_NAMES[k]: {"launches": arr[k].launches, "ms": arr[k].ms,
+                                    "flops": arr[k].flops} for k in range(LNOCC_KERNEL_CLASSES)}
+
+
+def lnocc_set_validation_mode(on: bool) -> None:
+    _lib.lnocc_set_validation_mode(int(bool(on)))
 
 
 # ------------------------------------------------------------ torch helpers

@@ -1,0 +1,59 @@
+"""Writes oracle reference values for the named fragment workloads.
+
+Runs only the FP64 oracle (oracle/) on the seeded synthetic inputs (synth/)
+and stores energies, iteration counts, amplitude norms and a seeded sample of
+amplitude elements as JSON next to this script.  Usage:
+
+    python tests/golden/make_golden.py single_small single_realistic
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import ccsd as occ, triples as otr  # noqa: E402
+from synth import CONFIG_SHAPES, make_fragment  # noqa: E402
+
+CONV_TOL = 1e-10
+NSAMPLE = 256
+
+
+def golden(name: str) -> dict:
+    o, v, X, seed = CONFIG_SHAPES[name]
+    f = make_fragment(o, v, X, seed)
+    t0 = time.time()
+    r = occ.ccsd(f.B, f.eps_occ, f.eps_vir, conv_tol=CONV_TOL, max_iter=200)
+    t_cc = time.time() - t0
+    t0 = time.time()
+    e_t = otr.e_triples_restricted(f.B, f.eps_occ, f.eps_vir, r.t1, r.t2)
+    t_t = time.time() - t0
+    rng = np.random.default_rng(12345)
+    idx2 = np.stack([rng.integers(0, o, NSAMPLE), rng.integers(0, o, NSAMPLE),
+                     rng.integers(0, v, NSAMPLE), rng.integers(0, v, NSAMPLE)], axis=1)
+    idx1 = np.stack([rng.integers(0, o, 64), rng.integers(0, v, 64)], axis=1)
+    return {
+        "workload": name, "nocc": o, "nvir": v, "naux": X, "seed": seed,
+        "input_sha256": f.sha256(), "conv_tol": CONV_TOL,
+        "converged": bool(r.converged), "n_iter": int(r.n_iter), "residual": r.residual,
+        "e_mp2": r.e_mp2, "e_ccsd": r.e_ccsd, "e_t": e_t,
+        "t1_norm": float(np.linalg.norm(r.t1)), "t2_norm": float(np.linalg.norm(r.t2)),
+        "t2_index": idx2.tolist(), "t2_value": [float(r.t2[tuple(i)]) for i in idx2],
+        "t1_index": idx1.tolist(), "t1_value": [float(r.t1[tuple(i)]) for i in idx1],
+        "oracle_seconds": {"ccsd": t_cc, "triples": t_t},
+    }
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:] or ["single_small"]:
+        g = golden(name)
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}.json")
+        with open(path, "w") as fh:
+            json.dump(g, fh, indent=1)
+        print(name, g["e_mp2"], g["e_ccsd"], g["e_t"], g["n_iter"], g["oracle_seconds"], flush=True)
