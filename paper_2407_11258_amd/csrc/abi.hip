@@ -74,7 +74,8 @@ Dims dims_of(const lnocc_fragment_t *f) { return Dims{f->nocc, f->nvir, f->naux}
 // Installs the address guard of the contraction launcher for one call.
 struct Guard {
   Region r[6];
-  Guard(const lnocc_fragment_t *f, const lnocc_options_t *opt) {
+  Guard(const lnocc_fragment_t *f, const lnocc_options_t *opt, const Layout &L) {
+    install_splitk_scratch(L.splitk, (size_t)L.splitk_elems);
     const size_t o = f->nocc, v = f->nvir, X = f->naux, n = o + v;
     int k = 0;
     r[k++] = Region{opt->workspace, opt->workspace_bytes};
@@ -85,7 +86,10 @@ struct Guard {
     r[k++] = Region{f->t2, f->t2 ? o * o * v * v * 8 : 0};
     install_regions(r, k);
   }
-  ~Guard() { install_regions(nullptr, 0); }
+  ~Guard() {
+    install_regions(nullptr, 0);
+    install_splitk_scratch(nullptr, 0);
+  }
 };
 
 int prepare(lnocc_fragment_t *f, const lnocc_options_t *opt, bool need_amplitudes,
@@ -157,7 +161,7 @@ int lnocc_fragment_ccsd(lnocc_fragment_t *f, const lnocc_options_t *opt) {
   int st = prepare(f, opt, opt && opt->guess == LNOCC_GUESS_USER, true, L);
   if (st) return finish(f, st);
   hipStream_t s = (hipStream_t)opt->stream;
-  Guard guard(f, opt);
+  Guard guard(f, opt, L);
   Inputs in{f->B, f->eps_occ, f->eps_vir, f->t1 ? f->t1 : L.t1w, f->t2 ? f->t2 : L.t2w,
             f->conv_tol};
   st = setup_fragment(L, f->B, f->eps_occ, f->eps_vir, true, s);
@@ -181,7 +185,7 @@ int lnocc_fragment_triples(lnocc_fragment_t *f, const lnocc_options_t *opt) {
   int st = prepare(f, opt, true, false, L);
   if (st) return finish(f, st);
   hipStream_t s = (hipStream_t)opt->stream;
-  Guard guard(f, opt);
+  Guard guard(f, opt, L);
   Inputs in{f->B, f->eps_occ, f->eps_vir, f->t1, f->t2, f->conv_tol};
   st = setup_fragment(L, f->B, f->eps_occ, f->eps_vir, false, s);
   Outputs out;
@@ -197,7 +201,7 @@ int lnocc_ccsd_residuals(lnocc_fragment_t *f, const lnocc_options_t *opt, double
   if (!st && (!r1 || !r2)) st = LNOCC_EINVAL;
   if (st) return finish(f, st);
   hipStream_t s = (hipStream_t)opt->stream;
-  Guard guard(f, opt);
+  Guard guard(f, opt, L);
   const int64_t o = f->nocc, v = f->nvir;
   st = setup_fragment(L, f->B, f->eps_occ, f->eps_vir, true, s);
   if (!st) st = ccsd_residuals(L, f->t1, f->t2, s);

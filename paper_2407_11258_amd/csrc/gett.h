@@ -27,6 +27,23 @@ enum class Kind : int {
   Count = 4
 };
 
+// Division by a runtime-invariant divisor via multiply-high (Granlund and
+// Montgomery, PLDI 1994): q = (t + ((n - t) >> s1)) >> s2 with t = mulhi(m, n);
+// exact for all 32-bit n and divisors d >= 1.
+struct FastDiv {
+  uint32_t d, m, s1, s2;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  FastDiv f;
+  f.d = d;
+  f.m = (uint32_t)((((1ull << 32) * ((1ull << l) - d)) / d) + 1);
+  f.s1 = l > 0 ? 1 : 0;
+  f.s2 = l > 0 ? l - 1 : 0;
+  return f;
+}
+
 struct GOperand {
   const void *p;          // element type given by GemmDesc::in_type
   int64_t s_ro, s_ri;     // strides of the outer / inner row (m or n) index
@@ -41,6 +58,7 @@ struct GSegment {
   int K, Ki;              // contraction length and inner extent (k = ko*Ki + ki)
   double scale;           // multiplies the A operand
   int a_kfast, b_kfast;   // set by gett(): operand contiguous along k
+  FastDiv kdiv;           // set by gett(): division by Ki
 };
 
 constexpr int kMaxSeg = 4;
@@ -58,7 +76,12 @@ struct GemmDesc {
   int tmax[3];            // with a table: largest value of each batch integer
   Prec prec;              // arithmetic of the products (inputs are FP64 in memory)
   Kind kind;
+  double *splitk;         // set by gett(): partial-sum scratch when K is split
+  FastDiv mdiv, ndiv;     // set by gett(): division by Mi, Ni
 };
+
+// Scratch for split-K partial sums (per host thread); without it K is never split.
+void install_splitk_scratch(double *p, size_t elems);
 
 // Launch timing: while enabled, every contraction launch is bracketed by HIP
 // events on its stream; collect() waits for them and sums per Kind.

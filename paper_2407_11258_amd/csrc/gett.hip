@@ -1,10 +1,14 @@
 // Generic batched contraction on gfx950 matrix cores (FP64 path).
 //
-// Tile: 128 x 128 outputs per workgroup of 256 threads (4 wave64s in a 2 x 2
-// arrangement, 64 x 64 per wave = 4 x 4 blocks of v_mfma_f64_16x16x4f64).
-// K is staged through LDS in slices of 16, k-major ([k][row]) so that the 16
-// lanes of one MFMA operand row read 128 contiguous bytes.  The next slice is
-// fetched into registers while the current one is multiplied.
+// Tiles: 128 x 128 outputs per workgroup of 8 wave64s (4 x 2, 32 x 64 per wave
+// = 2 x 4 blocks of v_mfma_f64_16x16x4f64; two waves share each SIMD, which
+// the FP64 matrix pipe needs to approach its rate), or 32 x 32 per single-wave
+// workgroup for thin outputs.  K is staged through double-buffered LDS in
+// slices of 16, k-major ([k][row]) so that the 16 lanes of one MFMA operand row
+// read 128 contiguous bytes; the next slice is fetched into registers while the
+// current one is multiplied (one barrier per slice).  Thin outputs with long K
+// are split over K across workgroups; the partial tiles are summed in a fixed
+// order by a second kernel, so results do not depend on scheduling.
 //
 // MFMA 16x16x4 (f64) operand layout, lane l of a wave64:
 //   A: A[l % 16][l / 16]      B: B[l / 16][l % 16]
@@ -19,12 +23,20 @@
 namespace lnocc {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int BM = 128, BN = 128, BK = 16;
-constexpr int LDA = BM + 4;   // padded LDS row (doubles)
-constexpr int LDB = BN + 4;
-constexpr int kPerThreadA = BM * BK / kThreads;   // 8
-constexpr int kPerThreadB = BN * BK / kThreads;   // 8
+constexpr int BK = 16;
+
+// Tile configuration: BM x BN outputs per workgroup, WM x WN waves, each wave
+// owning a (BM/WM) x (BN/WN) block of 16 x 16 MFMA tiles.
+template <int BM_, int BN_, int WM_, int WN_>
+struct Cfg {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
+  static constexpr int T = 64 * WM * WN;
+  static constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
+  static constexpr int LDA = BM + 4, LDB = BN + 4;   // padded LDS rows (doubles)
+  static constexpr int PA = BM * BK / T, PB = BN * BK / T;
+};
+using Big = Cfg<128, 128, 4, 2>;     // 8 waves, 32 x 64 (2 x 4 MFMA blocks) each
+using Small = Cfg<32, 32, 1, 1>;
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
@@ -44,163 +56,221 @@ __device__ inline BatchIdx decode_batch(const GemmDesc &d, int id) {
   return b;
 }
 
-__device__ inline int64_t row_off(const GOperand &op, int r, int Ri) {
-  return (int64_t)(r / Ri) * op.s_ro + (int64_t)(r % Ri) * op.s_ri;
+__device__ inline uint32_t fdiv(const FastDiv &f, uint32_t n) {
+  const uint32_t t = __umulhi(f.m, n);
+  return (t + ((n - t) >> f.s1)) >> f.s2;
 }
-__device__ inline int64_t k_off(const GOperand &op, int k, int Ki) {
-  return (int64_t)(k / Ki) * op.s_ko + (int64_t)(k % Ki) * op.s_ki;
+__device__ inline int64_t two_index_off(const FastDiv &f, uint32_t n, int64_t s_o, int64_t s_i) {
+  const uint32_t q = fdiv(f, n);
+  return (int64_t)q * s_o + (int64_t)(n - q * f.d) * s_i;
 }
 
-// Loads one BK-slice of one operand (rows row0.., k0..) into registers.
-// kfast: consecutive threads walk k (operand contiguous along k); otherwise
-// consecutive threads walk the row index.
-template <int R, int PER>
-__device__ inline void load_slice(const double *__restrict__ base, const GOperand &op,
-                                  bool kfast, int nrows, int Ri, int K, int Ki,
-                                  int row0, int k0, const int64_t *roff,
-                                  const bool *rok, double *reg) {
-  const int t = threadIdx.x;
-  if (kfast) {
-    const int kk = t % BK;
-    const int k = k0 + kk;
-    const bool kok = k < K;
-    const int64_t ko = kok ? k_off(op, k, Ki) : 0;
-#pragma unroll
-    for (int s = 0; s < PER; ++s)
-      reg[s] = (kok && rok[s]) ? base[roff[s] + ko] : 0.0;
-  } else {
+// Per-thread element ownership inside one BK-slice of an R-row operand tile
+// (T threads, PER = R * BK / T elements each).
+//   kfast (operand contiguous along k): element s -> (row t / BK + s T / BK,
+//     k t % BK): one k per thread and slice.
+//   otherwise 16 consecutive threads read 16 consecutive rows at one k: with
+//     g = t / 16 and p = g PER + s, element s -> (row t % 16 + 16 (p % RG),
+//     k p / RG), RG = R / 16 row groups; a thread touches KG = max(1, PER/RG)
+//     values of k per slice.
+template <int R, int T, int PER>
+struct Slice {
+  static constexpr int RG = R / 16;
+  static constexpr int KG = PER >= RG ? PER / RG : 1;
+  static_assert(PER % RG == 0 || RG % PER == 0, "row groups must tile the thread share");
+  int64_t roff[PER];
+  bool rok[PER];
+
+  __device__ static int row_of(bool kfast, int s) {
+    const int t = threadIdx.x;
+    return kfast ? t / BK + s * (T / BK) : t % 16 + 16 * (((t / 16) * PER + s) % RG);
+  }
+  __device__ static int k_of(bool kfast, int s) {
+    const int t = threadIdx.x;
+    return kfast ? t % BK : ((t / 16) * PER + s) / RG;
+  }
+  __device__ void init(const GOperand &op, const FastDiv &rdiv, bool kfast, int nrows, int row0) {
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
-      const int kk = t / R + s * (kThreads / R);
-      const int k = k0 + kk;
-      reg[s] = (k < K && rok[0]) ? base[roff[0] + k_off(op, k, Ki)] : 0.0;
-    }
-  }
-}
-
-template <int R, int LD, int PER>
-__device__ inline void store_slice(double *lds, bool kfast, const double *reg) {
-  const int t = threadIdx.x;
-  if (kfast) {
-    const int kk = t % BK;
-#pragma unroll
-    for (int s = 0; s < PER; ++s) lds[kk * LD + t / BK + s * (kThreads / BK)] = reg[s];
-  } else {
-#pragma unroll
-    for (int s = 0; s < PER; ++s) lds[(t / R + s * (kThreads / R)) * LD + t % R] = reg[s];
-  }
-}
-
-template <int R, int PER>
-__device__ inline void row_offsets(const GOperand &op, bool kfast, int nrows, int Ri,
-                                   int row0, int64_t *roff, bool *rok) {
-  const int t = threadIdx.x;
-  if (kfast) {
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int r = row0 + t / BK + s * (kThreads / BK);
+      const int r = row0 + row_of(kfast, s);
       rok[s] = r < nrows;
-      roff[s] = rok[s] ? row_off(op, r, Ri) : 0;
+      roff[s] = rok[s] ? two_index_off(rdiv, (uint32_t)r, op.s_ro, op.s_ri) : 0;
     }
-  } else {
-    const int r = row0 + t % R;
-    rok[0] = r < nrows;
-    roff[0] = rok[0] ? row_off(op, r, Ri) : 0;
-#pragma unroll
-    for (int s = 1; s < PER; ++s) { rok[s] = rok[0]; roff[s] = roff[0]; }
   }
-}
+  __device__ void load(const double *__restrict__ base, const GOperand &op, const FastDiv &kdiv,
+                       bool kfast, int K, int k0, double scale, double *reg) const {
+    if (kfast) {
+      const int k = k0 + k_of(true, 0);
+      const bool kok = k < K;
+      const int64_t ko = kok ? two_index_off(kdiv, (uint32_t)k, op.s_ko, op.s_ki) : 0;
+#pragma unroll
+      for (int s = 0; s < PER; ++s) {
+        const bool ok = kok && rok[s];
+        const double x = base[ok ? roff[s] + ko : 0];
+        reg[s] = ok ? scale * x : 0.0;
+      }
+    } else {
+      int64_t ko[KG];
+      bool kok[KG];
+#pragma unroll
+      for (int g = 0; g < KG; ++g) {
+        const int k = k0 + k_of(false, g * RG);
+        kok[g] = k < K;
+        ko[g] = kok[g] ? two_index_off(kdiv, (uint32_t)k, op.s_ko, op.s_ki) : 0;
+      }
+#pragma unroll
+      for (int s = 0; s < PER; ++s) {
+        const int g = (KG > 1) ? s / RG : 0;
+        const bool ok = kok[g] && rok[s];
+        const double x = base[ok ? roff[s] + ko[g] : 0];
+        reg[s] = ok ? scale * x : 0.0;
+      }
+    }
+  }
+  template <int LD>
+  __device__ static void store(double *lds, bool kfast, const double *reg) {
+#pragma unroll
+    for (int s = 0; s < PER; ++s) lds[k_of(kfast, s) * LD + row_of(kfast, s)] = reg[s];
+  }
+};
 
-template <int KIND>
-__global__ __launch_bounds__(kThreads) void gett_f64_kernel(GemmDesc d, int tiles_m) {
-  __shared__ double As[BK * LDA];
-  __shared__ double Bs[BK * LDB];
+// k-slices of all segments, numbered consecutively; a split-K share is a
+// contiguous range of them.
+__device__ inline int seg_slices(const GSegment &S) { return (S.K + BK - 1) / BK; }
+
+template <class C, int KIND>
+__global__ __launch_bounds__(C::T) void gett_f64_kernel(GemmDesc d, int tiles_m,
+                                                        int slices_per_split) {
+  __shared__ double As[2][BK * C::LDA];
+  __shared__ double Bs[2][BK * C::LDB];
 
   const int tile = blockIdx.x;
   const int tm = tile % tiles_m, tn = tile / tiles_m;
-  const int m0 = tm * BM, n0 = tn * BN;
+  const int m0 = tm * C::BM, n0 = tn * C::BN;
   const BatchIdx bi = decode_batch(d, blockIdx.y);
+  const int64_t id = blockIdx.y;
+  const int split = blockIdx.z;
+  const int q0 = split * slices_per_split, q1 = q0 + slices_per_split;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / C::WN, wn = wave % C::WN;
 
-  double4_t acc[4][4];
+  double4_t acc[C::MI][C::NI];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < C::MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < C::NI; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
 
+  int qbase = 0;   // global slice number of the current segment's first slice
   for (int sg = 0; sg < d.nseg; ++sg) {
     const GSegment &S = d.seg[sg];
-    const int64_t id = blockIdx.y;
+    const int ns = seg_slices(S);
+    const int lo = max(q0, qbase) - qbase, hi = min(q1, qbase + ns) - qbase;
+    qbase += ns;
+    if (lo >= hi) continue;
     const double *pa = (const double *)S.a.p + bi.i0 * S.a.b0 + bi.i1 * S.a.b1 + bi.i2 * S.a.b2 + id * S.a.bid;
     const double *pb = (const double *)S.b.p + bi.i0 * S.b.b0 + bi.i1 * S.b.b1 + bi.i2 * S.b.b2 + id * S.b.bid;
     const bool akf = S.a_kfast != 0;
     const bool bkf = S.b_kfast != 0;
-    int64_t aoff[kPerThreadA], boff[kPerThreadB];
-    bool aok[kPerThreadA], bok[kPerThreadB];
-    row_offsets<BM, kPerThreadA>(S.a, akf, d.M, d.Mi, m0, aoff, aok);
-    row_offsets<BN, kPerThreadB>(S.b, bkf, d.N, d.Ni, n0, boff, bok);
-    const double scale = S.scale;
+    Slice<C::BM, C::T, C::PA> sa;
+    Slice<C::BN, C::T, C::PB> sb;
+    sa.init(S.a, d.mdiv, akf, d.M, m0);
+    sb.init(S.b, d.ndiv, bkf, d.N, n0);
 
-    double ra[kPerThreadA], rb[kPerThreadB];
-    load_slice<BM, kPerThreadA>(pa, S.a, akf, d.M, d.Mi, S.K, S.Ki, m0, 0, aoff, aok, ra);
-    load_slice<BN, kPerThreadB>(pb, S.b, bkf, d.N, d.Ni, S.K, S.Ki, n0, 0, boff, bok, rb);
-    for (int k0 = 0; k0 < S.K; k0 += BK) {
-#pragma unroll
-      for (int s = 0; s < kPerThreadA; ++s) ra[s] *= scale;
-      __syncthreads();
-      store_slice<BM, LDA, kPerThreadA>(As, akf, ra);
-      store_slice<BN, LDB, kPerThreadB>(Bs, bkf, rb);
-      __syncthreads();
-      if (k0 + BK < S.K) {
-        load_slice<BM, kPerThreadA>(pa, S.a, akf, d.M, d.Mi, S.K, S.Ki, m0, k0 + BK, aoff, aok, ra);
-        load_slice<BN, kPerThreadB>(pb, S.b, bkf, d.N, d.Ni, S.K, S.Ki, n0, k0 + BK, boff, bok, rb);
+    double ra[C::PA], rb[C::PB];
+    sa.load(pa, S.a, S.kdiv, akf, S.K, lo * BK, S.scale, ra);
+    sb.load(pb, S.b, S.kdiv, bkf, S.K, lo * BK, 1.0, rb);
+    __syncthreads();   // previous segment may still read buffer 0
+    Slice<C::BM, C::T, C::PA>::template store<C::LDA>(As[0], akf, ra);
+    Slice<C::BN, C::T, C::PB>::template store<C::LDB>(Bs[0], bkf, rb);
+    __syncthreads();
+    for (int q = lo; q < hi; ++q) {
+      const int buf = (q - lo) & 1;
+      if (q + 1 < hi) {
+        sa.load(pa, S.a, S.kdiv, akf, S.K, (q + 1) * BK, S.scale, ra);
+        sb.load(pb, S.b, S.kdiv, bkf, S.K, (q + 1) * BK, 1.0, rb);
       }
+      const double *Ab = As[buf];
+      const double *Bb = Bs[buf];
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        double af[4], bf[4];
+        double af[C::MI], bf[C::NI];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          af[i] = As[(kk + lane / 16) * LDA + wm * 64 + i * 16 + lane % 16];
+        for (int i = 0; i < C::MI; ++i)
+          af[i] = Ab[(kk + lane / 16) * C::LDA + wm * (C::BM / C::WM) + i * 16 + lane % 16];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          bf[j] = Bs[(kk + lane / 16) * LDB + wn * 64 + j * 16 + lane % 16];
+        for (int j = 0; j < C::NI; ++j)
+          bf[j] = Bb[(kk + lane / 16) * C::LDB + wn * (C::BN / C::WN) + j * 16 + lane % 16];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < C::MI; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < C::NI; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
       }
+      if (q + 1 < hi) {
+        Slice<C::BM, C::T, C::PA>::template store<C::LDA>(As[buf ^ 1], akf, ra);
+        Slice<C::BN, C::T, C::PB>::template store<C::LDB>(Bs[buf ^ 1], bkf, rb);
+      }
+      __syncthreads();
     }
   }
 
   // Epilogue: lane holds rows lane/16 + 4r of each 16x16 block, column lane%16.
-  double *pc = d.c + bi.i0 * d.c_b0 + bi.i1 * d.c_b1 + bi.i2 * d.c_b2 + (int64_t)blockIdx.y * d.c_bid;
-  int64_t coff[4];
-  bool cok[4];
+  if (d.splitk) {   // raw partial sums, row-major [split][M][N]
+    double *pw = d.splitk + (int64_t)split * d.M * d.N;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int n = n0 + wn * 64 + j * 16 + lane % 16;
+    for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * (C::BM / C::WM) + i * 16 + lane / 16 + 4 * r;
+        if (m >= d.M) continue;
+#pragma unroll
+        for (int j = 0; j < C::NI; ++j) {
+          const int n = n0 + wn * (C::BN / C::WN) + j * 16 + lane % 16;
+          if (n < d.N) pw[(int64_t)m * d.N + n] = acc[i][j][r];
+        }
+      }
+    return;
+  }
+  double *pc = d.c + bi.i0 * d.c_b0 + bi.i1 * d.c_b1 + bi.i2 * d.c_b2 + id * d.c_bid;
+  int64_t coff[C::NI];
+  bool cok[C::NI];
+#pragma unroll
+  for (int j = 0; j < C::NI; ++j) {
+    const int n = n0 + wn * (C::BN / C::WN) + j * 16 + lane % 16;
     cok[j] = n < d.N;
-    coff[j] = cok[j] ? (int64_t)(n / d.Ni) * d.c_no + (int64_t)(n % d.Ni) * d.c_ni : 0;
+    coff[j] = cok[j] ? two_index_off(d.ndiv, (uint32_t)n, d.c_no, d.c_ni) : 0;
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < C::MI; ++i) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = m0 + wm * 64 + i * 16 + lane / 16 + 4 * r;
+      const int m = m0 + wm * (C::BM / C::WM) + i * 16 + lane / 16 + 4 * r;
       if (m >= d.M) continue;
-      const int64_t moff = (int64_t)(m / d.Mi) * d.c_mo + (int64_t)(m % d.Mi) * d.c_mi;
+      const int64_t moff = two_index_off(d.mdiv, (uint32_t)m, d.c_mo, d.c_mi);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < C::NI; ++j) {
         if (!cok[j]) continue;
         double *dst = pc + moff + coff[j];
         const double v = acc[i][j][r];
         *dst = (d.beta == 0.0) ? v : v + d.beta * *dst;
       }
     }
+  }
+}
+
+// C[m, n] = sum_s partial[s][m][n] (+ beta C), summed in split order.
+__global__ void splitk_reduce(GemmDesc d, int nsplit) {
+  const int64_t total = (int64_t)d.M * d.N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int s = 0; s < nsplit; ++s) acc += d.splitk[s * total + e];
+    const int m = (int)(e / d.N), n = (int)(e % d.N);
+    double *dst = d.c + (int64_t)(m / d.Mi) * d.c_mo + (int64_t)(m % d.Mi) * d.c_mi +
+                  (int64_t)(n / d.Ni) * d.c_no + (int64_t)(n % d.Ni) * d.c_ni;
+    *dst = (d.beta == 0.0) ? acc : acc + d.beta * *dst;
   }
 }
 
@@ -243,7 +313,7 @@ bool operand_ok(const GemmDesc &d, const GOperand &op, int64_t rows, int64_t Ri,
   return inside(op.p, s, sizeof(double));
 }
 
-bool descriptor_ok(const GemmDesc &d) {
+bool descriptor_ok(const GemmDesc &d, int nsplit) {
   if (!g_regions) return true;
   int64_t bmax[3];
   if (d.table) { bmax[0] = d.tmax[0]; bmax[1] = d.tmax[1]; bmax[2] = d.tmax[2]; }
@@ -262,7 +332,10 @@ bool descriptor_ok(const GemmDesc &d) {
   add_term(c, bmax[1], d.c_b1);
   add_term(c, bmax[2], d.c_b2);
   add_term(c, d.batch - 1, d.c_bid);
-  return inside(d.c, c, sizeof(double));
+  if (!inside(d.c, c, sizeof(double))) return false;
+  if (nsplit > 1 && !inside(d.splitk, Span{0, (int64_t)nsplit * d.M * d.N - 1}, sizeof(double)))
+    return false;
+  return true;
 }
 }  // namespace
 
@@ -301,45 +374,91 @@ static int contiguous_along_k(const GOperand &op, int Ki) {
   return (Ki > 1) ? (op.s_ki == 1) : (op.s_ko == 1);
 }
 
+namespace {
+template <class C>
+void launch(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
+  switch (d.kind) {
+    case Kind::LadderBuild:
+      hipLaunchKernelGGL((gett_f64_kernel<C, 1>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
+    case Kind::LadderContract:
+      hipLaunchKernelGGL((gett_f64_kernel<C, 2>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
+    case Kind::TriplesW:
+      hipLaunchKernelGGL((gett_f64_kernel<C, 3>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
+    default:
+      hipLaunchKernelGGL((gett_f64_kernel<C, 0>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
+  }
+}
+
+thread_local double *g_splitk = nullptr;
+thread_local size_t g_splitk_elems = 0;
+
+}  // namespace
+
+void install_splitk_scratch(double *p, size_t elems) {
+  g_splitk = p;
+  g_splitk_elems = p ? elems : 0;
+}
+
 hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   GemmDesc d = din;
+  d.splitk = nullptr;
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   if (d.Mi <= 0 || d.Ni <= 0 || d.nseg <= 0 || d.nseg > kMaxSeg) return hipErrorInvalidValue;
+  int slices = 0;
   for (int s = 0; s < d.nseg; ++s) {
     if (d.seg[s].K < 0 || d.seg[s].Ki <= 0) return hipErrorInvalidValue;
     d.seg[s].a_kfast = contiguous_along_k(d.seg[s].a, d.seg[s].Ki);
     d.seg[s].b_kfast = contiguous_along_k(d.seg[s].b, d.seg[s].Ki);
+    d.seg[s].kdiv = make_fastdiv((uint32_t)d.seg[s].Ki);
+    slices += (d.seg[s].K + BK - 1) / BK;
   }
   if (d.batch > 65535) return hipErrorInvalidValue;
   if (d.table == nullptr && d.nb1 <= 0) return hipErrorInvalidValue;
-  if (!descriptor_ok(d)) {
+  d.mdiv = make_fastdiv((uint32_t)d.Mi);
+  d.ndiv = make_fastdiv((uint32_t)d.Ni);
+  // Tile shape: the 32 x 32 single-wave tile for thin outputs, else 128 x 128.
+  const bool small = (d.M <= 64 || d.N <= 64);
+  const int BMx = small ? Small::BM : Big::BM, BNx = small ? Small::BN : Big::BN;
+  const int tiles_m = (d.M + BMx - 1) / BMx, tiles_n = (d.N + BNx - 1) / BNx;
+  const int64_t tiles = (int64_t)tiles_m * tiles_n * d.batch;
+  // Split K when the tiles alone cannot occupy the chip and K is long.
+  int nsplit = 1;
+  const int64_t target = small ? 2048 : 512;
+  if (d.batch == 1 && g_splitk && tiles < target && slices >= 8) {
+    int64_t want = (target + tiles - 1) / tiles;
+    want = std::min<int64_t>(want, slices / 4);
+    want = std::min<int64_t>(want, (int64_t)(g_splitk_elems / ((size_t)d.M * d.N)));
+    want = std::min<int64_t>(want, 1024);
+    if (want >= 2) nsplit = (int)want;
+  }
+  const int sps = (slices + nsplit - 1) / nsplit;
+  nsplit = (slices + sps - 1) / sps;
+  if (nsplit > 1) d.splitk = g_splitk;
+  if (!descriptor_ok(d, nsplit)) {
     if (std::getenv("LNOCC_DEBUG"))
       std::fprintf(stderr, "lnocc: contraction M=%d(%d) N=%d(%d) nseg=%d K0=%d(%d) batch=%d "
-                   "leaves its buffers; not launched\n", d.M, d.Mi, d.N, d.Ni, d.nseg,
-                   d.seg[0].K, d.seg[0].Ki, d.batch);
+                   "split=%d leaves its buffers; not launched\n", d.M, d.Mi, d.N, d.Ni, d.nseg,
+                   d.seg[0].K, d.seg[0].Ki, d.batch, nsplit);
     return hipErrorIllegalAddress;
   }
   if (g_dry) return hipSuccess;
-  const int tiles_m = (d.M + BM - 1) / BM;
-  const int tiles_n = (d.N + BN - 1) / BN;
-  dim3 grid(tiles_m * tiles_n, d.batch);
+
   hipEvent_t ev[2] = {nullptr, nullptr};
   if (g_profile) {
     if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
       return hipErrorOutOfMemory;
     hipEventRecord(ev[0], stream);
   }
-  switch (d.kind) {
-    case Kind::LadderBuild:
-      hipLaunchKernelGGL(gett_f64_kernel<1>, grid, dim3(kThreads), 0, stream, d, tiles_m); break;
-    case Kind::LadderContract:
-      hipLaunchKernelGGL(gett_f64_kernel<2>, grid, dim3(kThreads), 0, stream, d, tiles_m); break;
-    case Kind::TriplesW:
-      hipLaunchKernelGGL(gett_f64_kernel<3>, grid, dim3(kThreads), 0, stream, d, tiles_m); break;
-    default:
-      hipLaunchKernelGGL(gett_f64_kernel<0>, grid, dim3(kThreads), 0, stream, d, tiles_m); break;
+  dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)d.batch, (unsigned)nsplit);
+  if (small) launch<Small>(d, grid, tiles_m, sps, stream);
+  else launch<Big>(d, grid, tiles_m, sps, stream);
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess && nsplit > 1) {
+    const int64_t total = (int64_t)d.M * d.N;
+    const int blocks = (int)std::min<int64_t>(4096, (total + 255) / 256);
+    hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, stream, d, nsplit);
+    err = hipGetLastError();
   }
-  const hipError_t err = hipGetLastError();
   if (g_profile) {
     hipEventRecord(ev[1], stream);
     double flops = 0.0;

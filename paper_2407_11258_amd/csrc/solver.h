@@ -22,6 +22,8 @@ struct Layout {
   double *hoo, *hov, *hvo, *hvv;    // bare one-electron operator blocks
   double *J;                        // [X] occupied trace of B (or B~)
   double *scal, *partials;          // small scalars, reduction partials
+  double *splitk;                   // split-K partial sums of thin contractions
+  int64_t splitk_elems;
   // CCSD
   double *Btoo, *Btai, *Btvv;       // T1-dressed factors; Btai[Q][i][a] = B~[Q][a][i]
   double *Foo, *Fov, *Fvo, *Fvv, *Foop, *Fvvp;

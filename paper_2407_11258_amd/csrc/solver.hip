@@ -101,6 +101,8 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.J = A.d(X);
   L.scal = A.d(64);
   L.partials = A.d(16 * kRedBlocks);
+  L.splitk_elems = std::max<int64_t>((int64_t)1 << 22, 64 * vv);
+  L.splitk = A.d(L.splitk_elems);
   const size_t phase = A.off;
   // CCSD phase
   L.diis_m = std::max(1, (int)opt.diis_space);
