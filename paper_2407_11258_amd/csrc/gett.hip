@@ -24,6 +24,7 @@ namespace lnocc {
 namespace {
 
 constexpr int BK = 16;
+constexpr int kCUs = 256;   // compute units of one MI355X
 
 // Tile configuration: BM x BN outputs per workgroup, WM x WN waves, each wave
 // owning a (BM/WM) x (BN/WN) block of 16 x 16 MFMA tiles.
@@ -36,6 +37,8 @@ struct Cfg {
   static constexpr int PA = BM * BK / T, PB = BN * BK / T;
 };
 using Big = Cfg<128, 128, 4, 2>;     // 8 waves, 32 x 64 (2 x 4 MFMA blocks) each
+using Big80 = Cfg<128, 80, 4, 1>;    // 4 waves, 32 x 80 (2 x 5) each: N = 80 q
+using Big64 = Cfg<128, 64, 4, 1>;    // 4 waves, 32 x 64 (2 x 4) each
 using Small = Cfg<32, 32, 1, 1>;
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
@@ -416,20 +419,44 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   if (d.table == nullptr && d.nb1 <= 0) return hipErrorInvalidValue;
   d.mdiv = make_fastdiv((uint32_t)d.Mi);
   d.ndiv = make_fastdiv((uint32_t)d.Ni);
-  // Tile shape: the 32 x 32 single-wave tile for thin outputs, else 128 x 128.
+  // Tile shape: the 32 x 32 single-wave tile for thin outputs; otherwise 128
+  // rows by the N width (128, 80 or 64) that pads N least.
   const bool small = (d.M <= 64 || d.N <= 64);
-  const int BMx = small ? Small::BM : Big::BM, BNx = small ? Small::BN : Big::BN;
+  int BNx = 128;
+  if (!small) {
+    int64_t best = -1;
+    for (int bn : {128, 80, 64}) {
+      const int64_t pad = ((int64_t)(d.N + bn - 1) / bn) * bn - d.N;
+      if (best < 0 || pad < best) { best = pad; BNx = bn; }
+    }
+  }
+  const int BMx = small ? Small::BM : Big::BM;
+  if (small) BNx = Small::BN;
   const int tiles_m = (d.M + BMx - 1) / BMx, tiles_n = (d.N + BNx - 1) / BNx;
   const int64_t tiles = (int64_t)tiles_m * tiles_n * d.batch;
-  // Split K when the tiles alone cannot occupy the chip and K is long.
+  // Split K when the tiles alone leave the chip idle: thin outputs with long K,
+  // or a tile count that fills the last round of workgroups poorly.
   int nsplit = 1;
-  const int64_t target = small ? 2048 : 512;
-  if (d.batch == 1 && g_splitk && tiles < target && slices >= 8) {
-    int64_t want = (target + tiles - 1) / tiles;
-    want = std::min<int64_t>(want, slices / 4);
-    want = std::min<int64_t>(want, (int64_t)(g_splitk_elems / ((size_t)d.M * d.N)));
-    want = std::min<int64_t>(want, 1024);
-    if (want >= 2) nsplit = (int)want;
+  const int64_t cap = g_splitk ? (int64_t)(g_splitk_elems / ((size_t)d.M * d.N)) : 0;
+  if (d.batch == 1 && cap >= 2) {
+    if (small) {
+      const int64_t target = 2048;
+      if (tiles < target && slices >= 8) {
+        int64_t want = (target + tiles - 1) / tiles;
+        want = std::min<int64_t>({want, (int64_t)slices / 4, cap, 1024});
+        if (want >= 2) nsplit = (int)want;
+      }
+    } else if (slices >= 16 && tiles < 4 * kCUs) {
+      // rounds of workgroups x slices per workgroup, plus the partial-sum traffic
+      const double t_slice = 2.0 * BMx * BNx * BK / (45e12 / kCUs);   // s per slice
+      double best = -1.0;
+      for (int ns = 1; ns <= 64 && ns <= cap && ns * 4 <= slices; ++ns) {
+        const int64_t rounds = (tiles * ns + kCUs - 1) / kCUs;
+        const double t = rounds * (double)((slices + ns - 1) / ns) * t_slice +
+                         (ns > 1 ? 16.0 * ns * d.M * (double)d.N / 4e12 : 0.0);
+        if (best < 0 || t < best * 0.98) { best = t; nsplit = ns; }
+      }
+    }
   }
   const int sps = (slices + nsplit - 1) / nsplit;
   nsplit = (slices + sps - 1) / sps;
@@ -451,6 +478,8 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   }
   dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)d.batch, (unsigned)nsplit);
   if (small) launch<Small>(d, grid, tiles_m, sps, stream);
+  else if (BNx == 80) launch<Big80>(d, grid, tiles_m, sps, stream);
+  else if (BNx == 64) launch<Big64>(d, grid, tiles_m, sps, stream);
   else launch<Big>(d, grid, tiles_m, sps, stream);
   hipError_t err = hipGetLastError();
   if (err == hipSuccess && nsplit > 1) {

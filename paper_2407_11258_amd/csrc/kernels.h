@@ -10,6 +10,7 @@ namespace lnocc {
 // FP64 energy and norm) is independent of timing and bitwise reproducible.
 constexpr int kRedBlocks = 512;
 constexpr int kRedThreads = 256;
+constexpr int kTriplesBlocks = 128;   // (T) energy blocks per triple (grid-stride over cube tiles)
 
 hipError_t split_B(const double *B, int64_t X, int64_t o, int64_t v,
                    double *Boo, double *Bov, double *Bvv, hipStream_t s);
@@ -43,6 +44,10 @@ hipError_t lincomb(const double *Xs, int64_t stride, int m, const double *c_host
                    int64_t v, double *t1, double *t2, hipStream_t s);
 hipError_t scatter_vec(const double *x, int64_t o, int64_t v, double *t1, double *t2,
                        hipStream_t s);
+
+// Particle-particle ladder through (ij)-symmetric / antisymmetric rows.
+hipError_t pack_t(const double *t2, int64_t o, int64_t v, double *Tsa, hipStream_t s);
+hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, double *R2, hipStream_t s);
 
 // (T) energy of a batch of unique triples whose W tensors sit in W[nb][v][v][v].
 // table holds (i, j, k) per entry, i <= j <= k; partials[nb * tiles] per tile.

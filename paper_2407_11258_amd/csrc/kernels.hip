@@ -236,6 +236,43 @@ __global__ void k_scatter(const double *__restrict__ x, int64_t o, int64_t v, do
   }
 }
 
+// ---- packed particle-particle ladder --------------------------------------
+// Pairs: tri(h, l) = h (h + 1) / 2 + l for l <= h; stri(h, l) = h (h - 1) / 2 + l for l < h.
+__device__ inline int64_t tri(int64_t h, int64_t l) { return h * (h + 1) / 2 + l; }
+__device__ inline int64_t stri(int64_t h, int64_t l) { return h * (h - 1) / 2 + l; }
+
+// Rows of the ladder contraction: Tsa[tri(j,i)][c][d] = t_ij^cd + t_ij^dc (i <= j)
+// and Tsa[o(o+1)/2 + stri(j,i)][c][d] = t_ij^cd - t_ij^dc (i < j).
+__global__ void k_pack_t(const double *__restrict__ t2, int64_t o, int64_t v, double *Tsa) {
+  const int64_t vv = v * v, total = o * o * vv, op = o * (o + 1) / 2;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ij = e / vv, cd = e % vv, i = ij / o, j = ij % o, c = cd / v, d = cd % v;
+    if (i > j) continue;
+    const double x = t2[e], y = t2[ij * vv + d * v + c];
+    Tsa[tri(j, i) * vv + cd] = x + y;
+    if (i < j) Tsa[(op + stri(j, i)) * vv + cd] = x - y;
+  }
+}
+
+// R2[i][j][a][b] += (S_ij^ab + A_ij^ab) / 2 from SA[r][a][b] (a >= b), where
+// rows r < o(o+1)/2 hold S (symmetric in ij and ab) and the rest A
+// (antisymmetric in both).
+__global__ void k_unpack_ladder(const double *__restrict__ SA, int64_t o, int64_t v, double *R2) {
+  const int64_t vv = v * v, total = o * o * vv, op = o * (o + 1) / 2;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ij = e / vv, ab = e % vv, i = ij / o, j = ij % o, a = ab / v, b = ab % v;
+    const int64_t P = (a >= b) ? a * v + b : b * v + a;
+    double r = SA[((i <= j) ? tri(j, i) : tri(i, j)) * vv + P];
+    if (i != j && a != b) {
+      const double sg = ((i < j) == (a > b)) ? 1.0 : -1.0;
+      r += sg * SA[(op + ((i < j) ? stri(j, i) : stri(i, j))) * vv + P];
+    }
+    R2[e] += 0.5 * r;
+  }
+}
+
 // (T) energy epilogue on cube tiles of the W tensors.
 constexpr int TT = 8;          // tile edge
 constexpr int TP = TT + 1;     // padded innermost extent in LDS
@@ -258,38 +295,41 @@ __global__ void k_triples_energy(const double *__restrict__ Wall, const int *__r
   const int entry = blockIdx.y;
   const int i = table[3 * entry], j = table[3 * entry + 1], k = table[3 * entry + 2];
   const double *W = Wall + (int64_t)entry * v * v * v;
-  const int tile = blockIdx.x;
-  const int64_t a0 = (int64_t)(tile / (tpd * tpd)) * TT;
-  const int64_t b0 = (int64_t)((tile / tpd) % tpd) * TT;
-  const int64_t c0 = (int64_t)(tile % tpd) * TT;
-  load_cube(W, v, a0, b0, c0, L[0]);   // W^abc
-  load_cube(W, v, b0, c0, a0, L[1]);   // W^bca
-  load_cube(W, v, c0, a0, b0, L[2]);   // W^cab
-  load_cube(W, v, a0, c0, b0, L[3]);   // W^acb
-  load_cube(W, v, b0, a0, c0, L[4]);   // W^bac
-  load_cube(W, v, c0, b0, a0, L[5]);   // W^cba
-  __syncthreads();
   const double eijk = eo[i] + eo[j] + eo[k];
+  const int tiles = tpd * tpd * tpd;
   double acc = 0.0;
-  for (int e = threadIdx.x; e < TT * TT * TT; e += blockDim.x) {
-    const int x = e / (TT * TT), y = (e / TT) % TT, z = e % TT;
-    const int64_t a = a0 + x, b = b0 + y, c = c0 + z;
-    if (a >= v || b >= v || c >= v) continue;
-    const double w = L[0][(x * TT + y) * TP + z];
-    const double wbca = L[1][(y * TT + z) * TP + x];
-    const double wcab = L[2][(z * TT + x) * TP + y];
-    const double wacb = L[3][(x * TT + z) * TP + y];
-    const double wbac = L[4][(y * TT + x) * TP + z];
-    const double wcba = L[5][(z * TT + y) * TP + x];
-    const double V = w + Kov[((i * v + a) * o + j) * v + b] * t1[k * v + c] +
-                     Kov[((i * v + a) * o + k) * v + c] * t1[j * v + b] +
-                     Kov[((j * v + b) * o + k) * v + c] * t1[i * v + a];
-    const double Z = 4.0 * w + wbca + wcab - 2.0 * (wacb + wbac + wcba);
-    acc += V * Z / (eijk - ev[a] - ev[b] - ev[c]);
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t a0 = (int64_t)(tile / (tpd * tpd)) * TT;
+    const int64_t b0 = (int64_t)((tile / tpd) % tpd) * TT;
+    const int64_t c0 = (int64_t)(tile % tpd) * TT;
+    __syncthreads();   // the previous tile's reads of L are done
+    load_cube(W, v, a0, b0, c0, L[0]);   // W^abc
+    load_cube(W, v, b0, c0, a0, L[1]);   // W^bca
+    load_cube(W, v, c0, a0, b0, L[2]);   // W^cab
+    load_cube(W, v, a0, c0, b0, L[3]);   // W^acb
+    load_cube(W, v, b0, a0, c0, L[4]);   // W^bac
+    load_cube(W, v, c0, b0, a0, L[5]);   // W^cba
+    __syncthreads();
+    for (int e = threadIdx.x; e < TT * TT * TT; e += blockDim.x) {
+      const int x = e / (TT * TT), y = (e / TT) % TT, z = e % TT;
+      const int64_t a = a0 + x, b = b0 + y, c = c0 + z;
+      if (a >= v || b >= v || c >= v) continue;
+      const double w = L[0][(x * TT + y) * TP + z];
+      const double wbca = L[1][(y * TT + z) * TP + x];
+      const double wcab = L[2][(z * TT + x) * TP + y];
+      const double wacb = L[3][(x * TT + z) * TP + y];
+      const double wbac = L[4][(y * TT + x) * TP + z];
+      const double wcba = L[5][(z * TT + y) * TP + x];
+      const double V = w + Kov[((i * v + a) * o + j) * v + b] * t1[k * v + c] +
+                       Kov[((i * v + a) * o + k) * v + c] * t1[j * v + b] +
+                       Kov[((j * v + b) * o + k) * v + c] * t1[i * v + a];
+      const double Z = 4.0 * w + wbca + wcab - 2.0 * (wacb + wbac + wcba);
+      acc += V * Z / (eijk - ev[a] - ev[b] - ev[c]);
+    }
   }
   const double weight = (i < j && j < k) ? 2.0 : 1.0;   // (6 or 3) / 3
   const double r = block_sum(acc, sm);
-  if (threadIdx.x == 0) partials[(int64_t)entry * gridDim.x + tile] = weight * r;
+  if (threadIdx.x == 0) partials[(int64_t)entry * gridDim.x + blockIdx.x] = weight * r;
 }
 
 }  // namespace
@@ -401,14 +441,26 @@ hipError_t scatter_vec(const double *x, int64_t o, int64_t v, double *t1, double
                      x, o, v, t1, t2);
   return hipGetLastError();
 }
+hipError_t pack_t(const double *t2, int64_t o, int64_t v, double *Tsa, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_t, dim3(ew_blocks(o * o * v * v)), dim3(kEwThreads), 0, s, t2, o, v, Tsa);
+  return hipGetLastError();
+}
+hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, double *R2, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_unpack_ladder, dim3(ew_blocks(o * o * v * v)), dim3(kEwThreads), 0, s, SA,
+                     o, v, R2);
+  return hipGetLastError();
+}
 hipError_t triples_energy(const double *W, const int *table, int nb, const double *Kov,
                           const double *t1, const double *eo, const double *ev, int64_t o,
                           int64_t v, double *partials, int64_t *nparts, hipStream_t s) {
   const int tpd = (int)((v + TT - 1) / TT);
   const int tiles = tpd * tpd * tpd;
-  *nparts = (int64_t)tiles * nb;
+  const int per_entry = tiles < kTriplesBlocks ? tiles : kTriplesBlocks;
+  *nparts = (int64_t)per_entry * nb;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(k_triples_energy, dim3(tiles, nb), dim3(kRedThreads), 0, s, W, table, Kov,
+  hipLaunchKernelGGL(k_triples_energy, dim3(per_entry, nb), dim3(kRedThreads), 0, s, W, table, Kov,
                      t1, eo, ev, o, v, tpd, partials);
   return hipGetLastError();
 }

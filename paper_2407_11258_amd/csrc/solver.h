@@ -30,6 +30,7 @@ struct Layout {
   double *Pvv, *Q2, *Lov;           // (ld|kc) [k][l][d][c], (kd|lc) [k][l][c][d], 2(ld|kc)-(lc|kd) [l][d][k][c]
   double *u, *R1, *R2, *S, *Xc, *Goovv, *Cint, *Dint, *Wkl, *Y1, *Z1;
   double *chunk;                    // (ac|bd)~ for chunk_a values of a: [a][b][c][d]
+  double *Tsa, *SA;                 // ladder rows [t + t^T ; t - t^T] and results [o^2][v][v]
   double *dx, *de;                  // DIIS vectors and errors [m][namp]
   int64_t chunk_a, namp;
   int diis_m;

@@ -101,15 +101,18 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.J = A.d(X);
   L.scal = A.d(64);
   L.partials = A.d(16 * kRedBlocks);
-  L.splitk_elems = std::max<int64_t>((int64_t)1 << 22, 64 * vv);
+  L.splitk_elems = std::max<int64_t>({(int64_t)1 << 22, 64 * vv, 4 * oovv});
   L.splitk = A.d(L.splitk_elems);
   const size_t phase = A.off;
   // CCSD phase
   L.diis_m = std::max(1, (int)opt.diis_space);
   const int64_t N = ov + oovv;
   L.namp = N;
+  // Ladder blocks: a in [a0, a0 + chunk_a) against b < a0 + chunk_a (only b <= a
+  // is used); the (ac|bd) block takes chunk_a v^3 doubles.  About 16 blocks keep
+  // the wasted b > a corner of each rectangle small.
   int64_t chunk_bytes = opt.ladder_chunk_bytes ? (int64_t)opt.ladder_chunk_bytes : (int64_t)8 << 30;
-  L.chunk_a = std::max<int64_t>(1, std::min<int64_t>(v, chunk_bytes / (8 * vvv)));
+  L.chunk_a = std::max<int64_t>(1, std::min<int64_t>((v + 15) / 16, chunk_bytes / (8 * vvv)));
   L.Btoo = A.d(X * oo); L.Btai = A.d(X * ov); L.Btvv = A.d(X * vv);
   L.Foo = A.d(oo); L.Fov = A.d(ov); L.Fvo = A.d(ov); L.Fvv = A.d(vv);
   L.Foop = A.d(oo); L.Fvvp = A.d(vv);
@@ -118,6 +121,7 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.Goovv = A.d(oovv); L.Cint = A.d(oovv); L.Dint = A.d(oovv);
   L.Wkl = A.d(oo * oo); L.Y1 = A.d(X * ov); L.Z1 = A.d(X * ov);
   L.chunk = A.d(L.chunk_a * vvv);
+  L.Tsa = A.d(oovv); L.SA = A.d(oovv);
   L.dx = A.d(L.diis_m * N); L.de = A.d(L.diis_m * N);
   const size_t ccsd_end = A.off;
   // (T) phase (aliases the CCSD scratch)
@@ -130,8 +134,7 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.ntriples = nt;
   L.Gt = A.d(ov * vv); L.Jt = A.d(oo * ov);
   L.W = A.d(nb * vvv);
-  const int64_t tpd = (v + 7) / 8;
-  L.tpart = A.d(nb * tpd * tpd * tpd);
+  L.tpart = A.d(nb * kTriplesBlocks);
   L.table = A.i(3 * std::max<int64_t>(nt, 1));
   const size_t t_end = A.off;
   L.bytes = std::max(ccsd_end, t_end) + 256;
@@ -298,18 +301,25 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     SEG(d, X, 1, 1.0, OP(L.Btai, v, 1, ov, 0), OP(L.Btai, v, 1, ov, 0));
     LN_TRY(gett(d, s));
   }
-  // particle-particle ladder, (ac|bd)~ formed for a block of a at a time
+  // Particle-particle ladder R_ij^ab = sum_cd t_ij^cd (ac|bd)~ through
+  // S = R^ab + R^ba = sum_cd (t^cd + t^dc) (ac|bd) (symmetric in ij and ab) and
+  // A = R^ab - R^ba = sum_cd (t^cd - t^dc) (ac|bd) (antisymmetric in both): the
+  // (ac|bd) block is formed for b <= a only (half of the v^4 build) and
+  // contracted with o^2 rows (i <= j for S, i < j for A) instead of 2 o^2.
+  LN_TRY(pack_t(t2, o, v, L.Tsa, s));
   for (int64_t a0 = 0; a0 < v; a0 += L.chunk_a) {
-    const int64_t na = std::min<int64_t>(L.chunk_a, v - a0);
-    GemmDesc d = DESC(na * v, v, vv, v, L.chunk, vvv, v, vv, 1, 0.0);
+    const int64_t na = std::min<int64_t>(L.chunk_a, v - a0), a1 = a0 + na;
+    GemmDesc d = DESC(na * v, v, a1 * v, v, L.chunk, vvv, v, vv, 1, 0.0);
     SEG(d, X, 1, 1.0, OP(L.Btvv + a0 * v, v, 1, vv, 0), OP(L.Btvv, v, 1, vv, 0));
     d.kind = Kind::LadderBuild;
     LN_TRY(gett(d, s));
-    d = DESC(oo, 1, na * v, 1, L.R2 + a0 * v, vv, 0, 1, 0, 1.0);
-    SEG(d, vv, 1, 1.0, OP(t2, vv, 0, 1, 0), OP(L.chunk, vv, 0, 1, 0));
+    // SA[r][a][b] = sum_cd Tsa[r][cd] g[a][b][cd], rows (a, b < a1) of the block
+    d = DESC(na * a1, a1, oo, 1, L.SA + a0 * v, v, 1, vv, 0, 0.0);
+    SEG(d, vv, 1, 1.0, OP(L.chunk, vvv, vv, 1, 0), OP(L.Tsa, vv, 0, 1, 0));
     d.kind = Kind::LadderContract;
     LN_TRY(gett(d, s));
   }
+  LN_TRY(unpack_ladder(L.SA, o, v, L.R2, s));
   {  // hole-hole ladder: W_klij = (ki|lj)~ + sum_cd (kc|ld) t_ij^cd ; R2 += sum_kl t_kl^ab W_klij
     GemmDesc d = DESC(oo, o, oo, o, L.Wkl, ooo, o, oo, 1, 0.0);
     SEG(d, X, 1, 1.0, OP(L.Btoo, o, 1, oo, 0), OP(L.Btoo, o, 1, oo, 0));
