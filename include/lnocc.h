@@ -144,7 +144,9 @@ int lnocc_batch_solve(lnocc_fragment_t *f, int32_t nfrag, const lnocc_options_t 
  * where m = mo*Mi + mi, n = no*Ni + ni, k = ko*Ki + ki and each operand gives
  * one stride per index.  Batch entry e decodes to (e / nb1, e % nb1, 0) and
  * moves each base pointer by b0*(e / nb1) + b1*(e % nb1) + bid*e.  All strides
- * are in elements.  FP64 in and out. */
+ * are in elements.  precision selects the operand element type and product
+ * arithmetic (LNOCC_FP64: double; LNOCC_FP32: float, FP32 accumulation;
+ * LNOCC_BF16: bf16 bit patterns, FP32 accumulation); C is always FP64. */
 typedef struct lnocc_operand_t {
   const double *p;
   int64_t s_ro, s_ri, s_ko, s_ki;
@@ -161,6 +163,8 @@ typedef struct lnocc_contract_t {
   int64_t c_mo, c_mi, c_no, c_ni, c_b0, c_b1, c_bid;
   double beta;
   int32_t batch, nb1;
+  int32_t precision;             /* lnocc_precision_t of the operands */
+  int32_t reserved;
 } lnocc_contract_t;
 
 int lnocc_contract(const lnocc_contract_t *desc, void *stream);

@@ -98,7 +98,6 @@ int prepare(lnocc_fragment_t *f, const lnocc_options_t *opt, bool need_amplitude
   if (!st) st = check_options(opt);
   if (!st) st = check_pointers(f, need_amplitudes);
   if (!st && need_tol && !(f->conv_tol > 0.0 && std::isfinite(f->conv_tol))) st = LNOCC_EINVAL;
-  if (!st && opt->precision != LNOCC_FP64) st = LNOCC_EINVAL;
   if (st) return st;
   plan_layout(dims_of(f), *opt, (char *)opt->workspace, L);
   st = check_workspace(L, opt);
@@ -256,7 +255,9 @@ int lnocc_contract(const lnocc_contract_t *c, void *stream) {
   d.c_b0 = c->c_b0; d.c_b1 = c->c_b1; d.c_b2 = 0; d.c_bid = c->c_bid;
   d.beta = c->beta;
   d.batch = c->batch; d.nb1 = c->nb1; d.table = nullptr;
-  d.prec = Prec::F64;
+  if (c->precision < 0 || c->precision > 2) return LNOCC_EINVAL;
+  d.prec = (Prec)c->precision;
+  d.c_type = 0;
   hipStream_t s = (hipStream_t)stream;
   if (gett(d, s) != hipSuccess) return LNOCC_EDEVICE;
   if (dsync(s) != hipSuccess) return LNOCC_EDEVICE;

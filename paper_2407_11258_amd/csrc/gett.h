@@ -45,7 +45,7 @@ inline FastDiv make_fastdiv(uint32_t d) {
 }
 
 struct GOperand {
-  const void *p;          // element type given by GemmDesc::in_type
+  const void *p;          // element type given by GemmDesc::prec
   int64_t s_ro, s_ri;     // strides of the outer / inner row (m or n) index
   int64_t s_ko, s_ki;     // strides of the outer / inner contraction index
   int64_t b0, b1, b2;     // pointer offset per unit of each batch integer
@@ -67,14 +67,16 @@ struct GemmDesc {
   int M, Mi, N, Ni;
   int nseg;
   GSegment seg[kMaxSeg];
-  double *c;              // output, always FP64
+  void *c;                // output (element type c_type)
   int64_t c_mo, c_mi, c_no, c_ni, c_b0, c_b1, c_b2, c_bid;
   double beta;            // 0: C is overwritten without being read
   int batch;              // number of batch entries (>= 1)
   int nb1;                // id -> (id / nb1, id % nb1, 0) when table == nullptr
   const int *table;       // device int triples, batch entry id -> (i0, i1, i2)
   int tmax[3];            // with a table: largest value of each batch integer
-  Prec prec;              // arithmetic of the products (inputs are FP64 in memory)
+  Prec prec;              // operand element type in memory and product arithmetic:
+                          // F64 double, F32 float, BF16 bf16 (FP32 accumulation)
+  int c_type;             // output element: 0 double, 1 float, 2 bf16
   Kind kind;
   double *splitk;         // set by gett(): partial-sum scratch when K is split
   FastDiv mdiv, ndiv;     // set by gett(): division by Mi, Ni

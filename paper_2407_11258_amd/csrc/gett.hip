@@ -16,6 +16,7 @@
 #include "gett.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 #include <cstdio>
 #include <cstdlib>
@@ -23,8 +24,46 @@
 namespace lnocc {
 namespace {
 
-constexpr int BK = 16;
 constexpr int kCUs = 256;   // compute units of one MI355X
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
+
+// Arithmetic modes.  T: operand element in memory and LDS; Acc: accumulator
+// fragment of one 16 x 16 block; KS: k per MFMA; BK: k per LDS slice;
+// row(lane, r): output row of accumulator register r.
+struct ModeF64 {
+  using T = double;
+  using Acc = double4_t;
+  static constexpr int KS = 4, BK = 16;
+  static constexpr bool kRowMajor = false;        // LDS tile [k][row]
+  __device__ static int row(int lane, int r) { return lane / 16 + 4 * r; }
+  __device__ static T cvt(double x) { return x; }
+};
+struct ModeF32 {
+  using T = float;
+  using Acc = float4_t;
+  static constexpr int KS = 4, BK = 16;
+  static constexpr bool kRowMajor = false;
+  __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
+  __device__ static T cvt(double x) { return (float)x; }
+};
+struct ModeBF16 {
+  using T = uint16_t;                              // bf16 bit pattern
+  using Acc = float4_t;
+  static constexpr int KS = 32, BK = 32;
+  static constexpr bool kRowMajor = true;         // LDS tile [row][k]: 8 k per lane read at once
+  __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
+
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// round to nearest even (finite inputs)
+__device__ inline uint16_t f32_to_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
 
 // Tile configuration: BM x BN outputs per workgroup, WM x WN waves, each wave
 // owning a (BM/WM) x (BN/WN) block of 16 x 16 MFMA tiles.
@@ -33,15 +72,11 @@ struct Cfg {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
   static constexpr int T = 64 * WM * WN;
   static constexpr int MI = BM / WM / 16, NI = BN / WN / 16;
-  static constexpr int LDA = BM + 4, LDB = BN + 4;   // padded LDS rows (doubles)
-  static constexpr int PA = BM * BK / T, PB = BN * BK / T;
 };
 using Big = Cfg<128, 128, 4, 2>;     // 8 waves, 32 x 64 (2 x 4 MFMA blocks) each
 using Big80 = Cfg<128, 80, 4, 1>;    // 4 waves, 32 x 80 (2 x 5) each: N = 80 q
 using Big64 = Cfg<128, 64, 4, 1>;    // 4 waves, 32 x 64 (2 x 4) each
 using Small = Cfg<32, 32, 1, 1>;
-
-typedef double double4_t __attribute__((ext_vector_type(4)));
 
 struct BatchIdx { int64_t i0, i1, i2; };
 
@@ -68,6 +103,23 @@ __device__ inline int64_t two_index_off(const FastDiv &f, uint32_t n, int64_t s_
   return (int64_t)q * s_o + (int64_t)(n - q * f.d) * s_i;
 }
 
+// Prefetched elements are loaded unconditionally (from a clamped, always
+// valid address) and kept as raw bits until they are written to LDS after the
+// MFMA block; masking and scaling happen only there, so the wait for the loads
+// lands after the arithmetic instead of before it.
+template <typename E> struct BitsOf;
+template <> struct BitsOf<double> { using U = uint64_t; };
+template <> struct BitsOf<float> { using U = uint32_t; };
+template <> struct BitsOf<uint16_t> { using U = uint16_t; };
+
+template <class M> __device__ inline typename M::T scaled(typename M::T x, double s);
+template <> __device__ inline double scaled<ModeF64>(double x, double s) { return s * x; }
+template <> __device__ inline float scaled<ModeF32>(float x, double s) { return (float)s * x; }
+// (scale = 1 for the B operand: the multiply folds away after inlining)
+template <> __device__ inline uint16_t scaled<ModeBF16>(uint16_t x, double s) {
+  return s == 1.0 ? x : f32_to_bf16((float)s * bf16_to_f32(x));
+}
+
 // Per-thread element ownership inside one BK-slice of an R-row operand tile
 // (T threads, PER = R * BK / T elements each).
 //   kfast (operand contiguous along k): element s -> (row t / BK + s T / BK,
@@ -76,11 +128,15 @@ __device__ inline int64_t two_index_off(const FastDiv &f, uint32_t n, int64_t s_
 //     g = t / 16 and p = g PER + s, element s -> (row t % 16 + 16 (p % RG),
 //     k p / RG), RG = R / 16 row groups; a thread touches KG = max(1, PER/RG)
 //     values of k per slice.
-template <int R, int T, int PER>
+template <class M, int R, int T>
 struct Slice {
+  static constexpr int BK = M::BK;
+  static constexpr int PER = R * BK / T;
   static constexpr int RG = R / 16;
   static constexpr int KG = PER >= RG ? PER / RG : 1;
   static_assert(PER % RG == 0 || RG % PER == 0, "row groups must tile the thread share");
+  static_assert(PER <= 32, "in-range flags are kept in one 32-bit mask");
+  using E = typename M::T;
   int64_t roff[PER];
   bool rok[PER];
 
@@ -100,8 +156,10 @@ struct Slice {
       roff[s] = rok[s] ? two_index_off(rdiv, (uint32_t)r, op.s_ro, op.s_ri) : 0;
     }
   }
-  __device__ void load(const double *__restrict__ base, const GOperand &op, const FastDiv &kdiv,
-                       bool kfast, int K, int k0, double scale, double *reg) const {
+  // Issues the loads of one slice: raw bits in reg, in-range flags in okbits.
+  __device__ void load(const E *__restrict__ base, const GOperand &op, const FastDiv &kdiv,
+                       bool kfast, int K, int k0, E *reg, uint32_t &okbits) const {
+    okbits = 0;
     if (kfast) {
       const int k = k0 + k_of(true, 0);
       const bool kok = k < K;
@@ -109,8 +167,8 @@ struct Slice {
 #pragma unroll
       for (int s = 0; s < PER; ++s) {
         const bool ok = kok && rok[s];
-        const double x = base[ok ? roff[s] + ko : 0];
-        reg[s] = ok ? scale * x : 0.0;
+        okbits |= (uint32_t)ok << s;
+        reg[s] = base[ok ? roff[s] + ko : 0];
       }
     } else {
       int64_t ko[KG];
@@ -125,27 +183,102 @@ struct Slice {
       for (int s = 0; s < PER; ++s) {
         const int g = (KG > 1) ? s / RG : 0;
         const bool ok = kok[g] && rok[s];
-        const double x = base[ok ? roff[s] + ko[g] : 0];
-        reg[s] = ok ? scale * x : 0.0;
+        okbits |= (uint32_t)ok << s;
+        reg[s] = base[ok ? roff[s] + ko[g] : 0];
       }
     }
   }
+  // LDS tile: [k][row] with leading dimension LD, or [row][k] (kRowMajor).
   template <int LD>
-  __device__ static void store(double *lds, bool kfast, const double *reg) {
+  __device__ static void store(E *lds, bool kfast, const E *reg, uint32_t okbits, double scale) {
+    using U = typename BitsOf<E>::U;
 #pragma unroll
-    for (int s = 0; s < PER; ++s) lds[k_of(kfast, s) * LD + row_of(kfast, s)] = reg[s];
+    for (int s = 0; s < PER; ++s) {
+      const U m = ((okbits >> s) & 1u) ? (U)~(U)0 : (U)0;
+      const E x = scaled<M>(__builtin_bit_cast(E, (U)(__builtin_bit_cast(U, reg[s]) & m)), scale);
+      if (M::kRowMajor) lds[row_of(kfast, s) * LD + k_of(kfast, s)] = x;
+      else lds[k_of(kfast, s) * LD + row_of(kfast, s)] = x;
+    }
   }
 };
 
+// One LDS slice of MFMA steps.
+template <class M, class C, int LDA, int LDB>
+__device__ inline void mma_slice_impl(const typename M::T *Ab, const typename M::T *Bb, int lane,
+                                      int wm, int wn, typename M::Acc (&acc)[C::MI][C::NI]) {
+  const int mw = wm * (C::BM / C::WM), nw = wn * (C::BN / C::WN);
+  if constexpr (M::kRowMajor) {
+    // bf16: lane reads 8 consecutive k of row (lane % 16) starting at 8 (lane / 16)
+#pragma unroll
+    for (int kk = 0; kk < M::BK; kk += M::KS) {
+      bf16x8_t af[C::MI], bf[C::NI];
+#pragma unroll
+      for (int i = 0; i < C::MI; ++i) {
+        const u16x8_t raw = *(const u16x8_t *)(Ab + (mw + i * 16 + lane % 16) * LDA + kk + 8 * (lane / 16));
+        af[i] = __builtin_bit_cast(bf16x8_t, raw);
+      }
+#pragma unroll
+      for (int j = 0; j < C::NI; ++j) {
+        const u16x8_t raw = *(const u16x8_t *)(Bb + (nw + j * 16 + lane % 16) * LDB + kk + 8 * (lane / 16));
+        bf[j] = __builtin_bit_cast(bf16x8_t, raw);
+      }
+#pragma unroll
+      for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+        for (int j = 0; j < C::NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < M::BK; kk += M::KS) {
+      typename M::T af[C::MI], bf[C::NI];
+#pragma unroll
+      for (int i = 0; i < C::MI; ++i) af[i] = Ab[(kk + lane / 16) * LDA + mw + i * 16 + lane % 16];
+#pragma unroll
+      for (int j = 0; j < C::NI; ++j) bf[j] = Bb[(kk + lane / 16) * LDB + nw + j * 16 + lane % 16];
+#pragma unroll
+      for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+        for (int j = 0; j < C::NI; ++j) {
+          if constexpr (std::is_same<typename M::T, double>::value)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+          else
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+    }
+  }
+}
+
 // k-slices of all segments, numbered consecutively; a split-K share is a
 // contiguous range of them.
+template <int BK>
 __device__ inline int seg_slices(const GSegment &S) { return (S.K + BK - 1) / BK; }
 
-template <class C, int KIND>
-__global__ __launch_bounds__(C::T) void gett_f64_kernel(GemmDesc d, int tiles_m,
-                                                        int slices_per_split) {
-  __shared__ double As[2][BK * C::LDA];
-  __shared__ double Bs[2][BK * C::LDB];
+__device__ inline void store_out(const GemmDesc &d, void *base, int64_t off, double v) {
+  if (d.c_type == 1) {
+    float *p = (float *)base + off;
+    *p = (d.beta == 0.0) ? (float)v : (float)(v + d.beta * (double)*p);
+  } else if (d.c_type == 2) {
+    uint16_t *p = (uint16_t *)base + off;
+    *p = f32_to_bf16((d.beta == 0.0) ? (float)v : (float)(v + d.beta * (double)bf16_to_f32(*p)));
+  } else {
+    double *p = (double *)base + off;
+    *p = (d.beta == 0.0) ? v : v + d.beta * *p;
+  }
+}
+
+template <class M, class C, int KIND>
+__global__ __launch_bounds__(C::T) void gett_kernel(GemmDesc d, int tiles_m, int slices_per_split) {
+  using E = typename M::T;
+  constexpr int BK = M::BK;
+  // [k][row] tiles pad the row (conflict-free 16-lane reads); [row][k] tiles pad
+  // k to keep 16-byte alignment of each lane's 8-element read.
+  constexpr int LDA = M::kRowMajor ? BK + 8 : C::BM + 4;
+  constexpr int LDB = M::kRowMajor ? BK + 8 : C::BN + 4;
+  constexpr int SZA = M::kRowMajor ? C::BM * LDA : BK * LDA;
+  constexpr int SZB = M::kRowMajor ? C::BN * LDB : BK * LDB;
+  __shared__ __attribute__((aligned(16))) E As[2][SZA];
+  __shared__ __attribute__((aligned(16))) E Bs[2][SZB];
 
   const int tile = blockIdx.x;
   const int tm = tile % tiles_m, tn = tile / tiles_m;
@@ -159,84 +292,73 @@ __global__ __launch_bounds__(C::T) void gett_f64_kernel(GemmDesc d, int tiles_m,
   const int wave = threadIdx.x >> 6;
   const int wm = wave / C::WN, wn = wave % C::WN;
 
-  double4_t acc[C::MI][C::NI];
+  typename M::Acc acc[C::MI][C::NI];
 #pragma unroll
   for (int i = 0; i < C::MI; ++i)
 #pragma unroll
-    for (int j = 0; j < C::NI; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < C::NI; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
+  using SA = Slice<M, C::BM, C::T>;
+  using SB = Slice<M, C::BN, C::T>;
   int qbase = 0;   // global slice number of the current segment's first slice
   for (int sg = 0; sg < d.nseg; ++sg) {
     const GSegment &S = d.seg[sg];
-    const int ns = seg_slices(S);
+    const int ns = seg_slices<BK>(S);
     const int lo = max(q0, qbase) - qbase, hi = min(q1, qbase + ns) - qbase;
     qbase += ns;
     if (lo >= hi) continue;
-    const double *pa = (const double *)S.a.p + bi.i0 * S.a.b0 + bi.i1 * S.a.b1 + bi.i2 * S.a.b2 + id * S.a.bid;
-    const double *pb = (const double *)S.b.p + bi.i0 * S.b.b0 + bi.i1 * S.b.b1 + bi.i2 * S.b.b2 + id * S.b.bid;
+    const E *pa = (const E *)S.a.p + bi.i0 * S.a.b0 + bi.i1 * S.a.b1 + bi.i2 * S.a.b2 + id * S.a.bid;
+    const E *pb = (const E *)S.b.p + bi.i0 * S.b.b0 + bi.i1 * S.b.b1 + bi.i2 * S.b.b2 + id * S.b.bid;
     const bool akf = S.a_kfast != 0;
     const bool bkf = S.b_kfast != 0;
-    Slice<C::BM, C::T, C::PA> sa;
-    Slice<C::BN, C::T, C::PB> sb;
+    SA sa;
+    SB sb;
     sa.init(S.a, d.mdiv, akf, d.M, m0);
     sb.init(S.b, d.ndiv, bkf, d.N, n0);
 
-    double ra[C::PA], rb[C::PB];
-    sa.load(pa, S.a, S.kdiv, akf, S.K, lo * BK, S.scale, ra);
-    sb.load(pb, S.b, S.kdiv, bkf, S.K, lo * BK, 1.0, rb);
+    E ra[SA::PER], rb[SB::PER];
+    uint32_t oka, okb;
+    sa.load(pa, S.a, S.kdiv, akf, S.K, lo * BK, ra, oka);
+    sb.load(pb, S.b, S.kdiv, bkf, S.K, lo * BK, rb, okb);
     __syncthreads();   // previous segment may still read buffer 0
-    Slice<C::BM, C::T, C::PA>::template store<C::LDA>(As[0], akf, ra);
-    Slice<C::BN, C::T, C::PB>::template store<C::LDB>(Bs[0], bkf, rb);
+    SA::template store<LDA>(As[0], akf, ra, oka, S.scale);
+    SB::template store<LDB>(Bs[0], bkf, rb, okb, 1.0);
     __syncthreads();
     for (int q = lo; q < hi; ++q) {
       const int buf = (q - lo) & 1;
       if (q + 1 < hi) {
-        sa.load(pa, S.a, S.kdiv, akf, S.K, (q + 1) * BK, S.scale, ra);
-        sb.load(pb, S.b, S.kdiv, bkf, S.K, (q + 1) * BK, 1.0, rb);
+        sa.load(pa, S.a, S.kdiv, akf, S.K, (q + 1) * BK, ra, oka);
+        sb.load(pb, S.b, S.kdiv, bkf, S.K, (q + 1) * BK, rb, okb);
       }
-      const double *Ab = As[buf];
-      const double *Bb = Bs[buf];
-#pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        double af[C::MI], bf[C::NI];
-#pragma unroll
-        for (int i = 0; i < C::MI; ++i)
-          af[i] = Ab[(kk + lane / 16) * C::LDA + wm * (C::BM / C::WM) + i * 16 + lane % 16];
-#pragma unroll
-        for (int j = 0; j < C::NI; ++j)
-          bf[j] = Bb[(kk + lane / 16) * C::LDB + wn * (C::BN / C::WN) + j * 16 + lane % 16];
-#pragma unroll
-        for (int i = 0; i < C::MI; ++i)
-#pragma unroll
-          for (int j = 0; j < C::NI; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-      }
+      mma_slice_impl<M, C, LDA, LDB>(As[buf], Bs[buf], lane, wm, wn, acc);
       if (q + 1 < hi) {
-        Slice<C::BM, C::T, C::PA>::template store<C::LDA>(As[buf ^ 1], akf, ra);
-        Slice<C::BN, C::T, C::PB>::template store<C::LDB>(Bs[buf ^ 1], bkf, rb);
+        SA::template store<LDA>(As[buf ^ 1], akf, ra, oka, S.scale);
+        SB::template store<LDB>(Bs[buf ^ 1], bkf, rb, okb, 1.0);
       }
       __syncthreads();
     }
   }
 
-  // Epilogue: lane holds rows lane/16 + 4r of each 16x16 block, column lane%16.
   if (d.splitk) {   // raw partial sums, row-major [split][M][N]
     double *pw = d.splitk + (int64_t)split * d.M * d.N;
 #pragma unroll
     for (int i = 0; i < C::MI; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * (C::BM / C::WM) + i * 16 + lane / 16 + 4 * r;
+        const int m = m0 + wm * (C::BM / C::WM) + i * 16 + M::row(lane, r);
         if (m >= d.M) continue;
 #pragma unroll
         for (int j = 0; j < C::NI; ++j) {
           const int n = n0 + wn * (C::BN / C::WN) + j * 16 + lane % 16;
-          if (n < d.N) pw[(int64_t)m * d.N + n] = acc[i][j][r];
+          if (n < d.N) pw[(int64_t)m * d.N + n] = (double)acc[i][j][r];
         }
       }
     return;
   }
-  double *pc = d.c + bi.i0 * d.c_b0 + bi.i1 * d.c_b1 + bi.i2 * d.c_b2 + id * d.c_bid;
+  const int esz = d.c_type == 0 ? 8 : (d.c_type == 1 ? 4 : 2);
+  char *pc = (char *)d.c + (bi.i0 * d.c_b0 + bi.i1 * d.c_b1 + bi.i2 * d.c_b2 + id * d.c_bid) * esz;
   int64_t coff[C::NI];
   bool cok[C::NI];
 #pragma unroll
@@ -249,15 +371,13 @@ __global__ __launch_bounds__(C::T) void gett_f64_kernel(GemmDesc d, int tiles_m,
   for (int i = 0; i < C::MI; ++i) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = m0 + wm * (C::BM / C::WM) + i * 16 + lane / 16 + 4 * r;
+      const int m = m0 + wm * (C::BM / C::WM) + i * 16 + M::row(lane, r);
       if (m >= d.M) continue;
       const int64_t moff = two_index_off(d.mdiv, (uint32_t)m, d.c_mo, d.c_mi);
 #pragma unroll
       for (int j = 0; j < C::NI; ++j) {
         if (!cok[j]) continue;
-        double *dst = pc + moff + coff[j];
-        const double v = acc[i][j][r];
-        *dst = (d.beta == 0.0) ? v : v + d.beta * *dst;
+        store_out(d, pc, moff + coff[j], (double)acc[i][j][r]);
       }
     }
   }
@@ -271,9 +391,9 @@ __global__ void splitk_reduce(GemmDesc d, int nsplit) {
     double acc = 0.0;
     for (int s = 0; s < nsplit; ++s) acc += d.splitk[s * total + e];
     const int m = (int)(e / d.N), n = (int)(e % d.N);
-    double *dst = d.c + (int64_t)(m / d.Mi) * d.c_mo + (int64_t)(m % d.Mi) * d.c_mi +
-                  (int64_t)(n / d.Ni) * d.c_no + (int64_t)(n % d.Ni) * d.c_ni;
-    *dst = (d.beta == 0.0) ? acc : acc + d.beta * *dst;
+    const int64_t off = (int64_t)(m / d.Mi) * d.c_mo + (int64_t)(m % d.Mi) * d.c_mi +
+                        (int64_t)(n / d.Ni) * d.c_no + (int64_t)(n % d.Ni) * d.c_ni;
+    store_out(d, d.c, off, acc);
   }
 }
 
@@ -313,7 +433,8 @@ bool operand_ok(const GemmDesc &d, const GOperand &op, int64_t rows, int64_t Ri,
   add_term(s, bmax[1], op.b1);
   add_term(s, bmax[2], op.b2);
   add_term(s, d.batch - 1, op.bid);
-  return inside(op.p, s, sizeof(double));
+  const size_t esz = d.prec == Prec::F64 ? 8 : (d.prec == Prec::F32 ? 4 : 2);
+  return inside(op.p, s, esz);
 }
 
 bool descriptor_ok(const GemmDesc &d, int nsplit) {
@@ -335,7 +456,7 @@ bool descriptor_ok(const GemmDesc &d, int nsplit) {
   add_term(c, bmax[1], d.c_b1);
   add_term(c, bmax[2], d.c_b2);
   add_term(c, d.batch - 1, d.c_bid);
-  if (!inside(d.c, c, sizeof(double))) return false;
+  if (!inside(d.c, c, d.c_type == 0 ? 8 : (d.c_type == 1 ? 4 : 2))) return false;
   if (nsplit > 1 && !inside(d.splitk, Span{0, (int64_t)nsplit * d.M * d.N - 1}, sizeof(double)))
     return false;
   return true;
@@ -378,17 +499,25 @@ static int contiguous_along_k(const GOperand &op, int Ki) {
 }
 
 namespace {
-template <class C>
-void launch(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
+template <class M, class C>
+void launch_kind(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
   switch (d.kind) {
     case Kind::LadderBuild:
-      hipLaunchKernelGGL((gett_f64_kernel<C, 1>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
+      hipLaunchKernelGGL((gett_kernel<M, C, 1>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
     case Kind::LadderContract:
-      hipLaunchKernelGGL((gett_f64_kernel<C, 2>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
+      hipLaunchKernelGGL((gett_kernel<M, C, 2>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
     case Kind::TriplesW:
-      hipLaunchKernelGGL((gett_f64_kernel<C, 3>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
+      hipLaunchKernelGGL((gett_kernel<M, C, 3>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
     default:
-      hipLaunchKernelGGL((gett_f64_kernel<C, 0>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
+      hipLaunchKernelGGL((gett_kernel<M, C, 0>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
+  }
+}
+template <class C>
+void launch(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
+  switch (d.prec) {
+    case Prec::F32: launch_kind<ModeF32, C>(d, grid, tiles_m, sps, stream); break;
+    case Prec::BF16: launch_kind<ModeBF16, C>(d, grid, tiles_m, sps, stream); break;
+    default: launch_kind<ModeF64, C>(d, grid, tiles_m, sps, stream); break;
   }
 }
 
@@ -407,13 +536,14 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   d.splitk = nullptr;
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   if (d.Mi <= 0 || d.Ni <= 0 || d.nseg <= 0 || d.nseg > kMaxSeg) return hipErrorInvalidValue;
+  const int bk = (d.prec == Prec::BF16) ? 32 : 16;   // k per LDS slice of the mode
   int slices = 0;
   for (int s = 0; s < d.nseg; ++s) {
     if (d.seg[s].K < 0 || d.seg[s].Ki <= 0) return hipErrorInvalidValue;
     d.seg[s].a_kfast = contiguous_along_k(d.seg[s].a, d.seg[s].Ki);
     d.seg[s].b_kfast = contiguous_along_k(d.seg[s].b, d.seg[s].Ki);
     d.seg[s].kdiv = make_fastdiv((uint32_t)d.seg[s].Ki);
-    slices += (d.seg[s].K + BK - 1) / BK;
+    slices += (d.seg[s].K + bk - 1) / bk;
   }
   if (d.batch > 65535) return hipErrorInvalidValue;
   if (d.table == nullptr && d.nb1 <= 0) return hipErrorInvalidValue;
@@ -448,7 +578,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
       }
     } else if (slices >= 16 && tiles < 4 * kCUs) {
       // rounds of workgroups x slices per workgroup, plus the partial-sum traffic
-      const double t_slice = 2.0 * BMx * BNx * BK / (45e12 / kCUs);   // s per slice
+      const double t_slice = 2.0 * BMx * BNx * bk / (45e12 / kCUs);   // s per slice
       double best = -1.0;
       for (int ns = 1; ns <= 64 && ns <= cap && ns * 4 <= slices; ++ns) {
         const int64_t rounds = (tiles * ns + kCUs - 1) / kCUs;

@@ -46,12 +46,15 @@ hipError_t scatter_vec(const double *x, int64_t o, int64_t v, double *t1, double
                        hipStream_t s);
 
 // Particle-particle ladder through (ij)-symmetric / antisymmetric rows.
-hipError_t pack_t(const double *t2, int64_t o, int64_t v, double *Tsa, hipStream_t s);
+// type: 0 double, 1 float, 2 bf16 (round to nearest even)
+hipError_t pack_t(const double *t2, int64_t o, int64_t v, void *Tsa, int type, hipStream_t s);
+hipError_t convert(const double *in, int64_t n, void *out, int type, hipStream_t s);
 hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, double *R2, hipStream_t s);
 
 // (T) energy of a batch of unique triples whose W tensors sit in W[nb][v][v][v].
 // table holds (i, j, k) per entry, i <= j <= k; partials[nb * tiles] per tile.
-hipError_t triples_energy(const double *W, const int *table, int nb, const double *Kov,
+// W element type: 0 double, 1 float
+hipError_t triples_energy(const void *W, int wtype, const int *table, int nb, const double *Kov,
                           const double *t1, const double *eo, const double *ev, int64_t o,
                           int64_t v, double *partials, int64_t *nparts, hipStream_t s);
 

@@ -243,15 +243,38 @@ __device__ inline int64_t stri(int64_t h, int64_t l) { return h * (h - 1) / 2 + 
 
 // Rows of the ladder contraction: Tsa[tri(j,i)][c][d] = t_ij^cd + t_ij^dc (i <= j)
 // and Tsa[o(o+1)/2 + stri(j,i)][c][d] = t_ij^cd - t_ij^dc (i < j).
-__global__ void k_pack_t(const double *__restrict__ t2, int64_t o, int64_t v, double *Tsa) {
+__device__ inline float lp_round_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return __uint_as_float(((u + 0x7fffu + ((u >> 16) & 1u)) >> 16) << 16);
+}
+template <typename T> __device__ inline T to_lp(double x);
+template <> __device__ inline double to_lp<double>(double x) { return x; }
+template <> __device__ inline float to_lp<float>(double x) { return (float)x; }
+template <> __device__ inline uint16_t to_lp<uint16_t>(double x) {   // bf16, round to nearest even
+  const uint32_t u = __float_as_uint((float)x);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+template <typename T> __device__ inline double from_lp(T x);
+template <> __device__ inline double from_lp<double>(double x) { return x; }
+template <> __device__ inline double from_lp<float>(float x) { return (double)x; }
+
+template <typename T>
+__global__ void k_convert(const double *__restrict__ in, int64_t n, T *out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = to_lp<T>(in[e]);
+}
+
+template <typename T>
+__global__ void k_pack_t(const double *__restrict__ t2, int64_t o, int64_t v, T *Tsa) {
   const int64_t vv = v * v, total = o * o * vv, op = o * (o + 1) / 2;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t ij = e / vv, cd = e % vv, i = ij / o, j = ij % o, c = cd / v, d = cd % v;
     if (i > j) continue;
     const double x = t2[e], y = t2[ij * vv + d * v + c];
-    Tsa[tri(j, i) * vv + cd] = x + y;
-    if (i < j) Tsa[(op + stri(j, i)) * vv + cd] = x - y;
+    Tsa[tri(j, i) * vv + cd] = to_lp<T>(x + y);
+    if (i < j) Tsa[(op + stri(j, i)) * vv + cd] = to_lp<T>(x - y);
   }
 }
 
@@ -277,16 +300,18 @@ __global__ void k_unpack_ladder(const double *__restrict__ SA, int64_t o, int64_
 constexpr int TT = 8;          // tile edge
 constexpr int TP = TT + 1;     // padded innermost extent in LDS
 
-__device__ inline void load_cube(const double *__restrict__ W, int64_t v, int64_t o0, int64_t o1,
+template <typename TW>
+__device__ inline void load_cube(const TW *__restrict__ W, int64_t v, int64_t o0, int64_t o1,
                                  int64_t o2, double *L) {
   for (int e = threadIdx.x; e < TT * TT * TT; e += blockDim.x) {
     const int p = e / (TT * TT), q = (e / TT) % TT, r = e % TT;
     const int64_t x = o0 + p, y = o1 + q, z = o2 + r;
-    L[(p * TT + q) * TP + r] = (x < v && y < v && z < v) ? W[(x * v + y) * v + z] : 0.0;
+    L[(p * TT + q) * TP + r] = (x < v && y < v && z < v) ? from_lp<TW>(W[(x * v + y) * v + z]) : 0.0;
   }
 }
 
-__global__ void k_triples_energy(const double *__restrict__ Wall, const int *__restrict__ table,
+template <typename TW>
+__global__ void k_triples_energy(const TW *__restrict__ Wall, const int *__restrict__ table,
                                  const double *__restrict__ Kov, const double *__restrict__ t1,
                                  const double *__restrict__ eo, const double *__restrict__ ev,
                                  int64_t o, int64_t v, int tpd, double *partials) {
@@ -294,7 +319,7 @@ __global__ void k_triples_energy(const double *__restrict__ Wall, const int *__r
   __shared__ double sm[kRedThreads / 64];
   const int entry = blockIdx.y;
   const int i = table[3 * entry], j = table[3 * entry + 1], k = table[3 * entry + 2];
-  const double *W = Wall + (int64_t)entry * v * v * v;
+  const TW *W = Wall + (int64_t)entry * v * v * v;
   const double eijk = eo[i] + eo[j] + eo[k];
   const int tiles = tpd * tpd * tpd;
   double acc = 0.0;
@@ -441,9 +466,20 @@ hipError_t scatter_vec(const double *x, int64_t o, int64_t v, double *t1, double
                      x, o, v, t1, t2);
   return hipGetLastError();
 }
-hipError_t pack_t(const double *t2, int64_t o, int64_t v, double *Tsa, hipStream_t s) {
+hipError_t pack_t(const double *t2, int64_t o, int64_t v, void *Tsa, int type, hipStream_t s) {
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(k_pack_t, dim3(ew_blocks(o * o * v * v)), dim3(kEwThreads), 0, s, t2, o, v, Tsa);
+  const dim3 g(ew_blocks(o * o * v * v)), b(kEwThreads);
+  if (type == 1) hipLaunchKernelGGL(k_pack_t<float>, g, b, 0, s, t2, o, v, (float *)Tsa);
+  else if (type == 2) hipLaunchKernelGGL(k_pack_t<uint16_t>, g, b, 0, s, t2, o, v, (uint16_t *)Tsa);
+  else hipLaunchKernelGGL(k_pack_t<double>, g, b, 0, s, t2, o, v, (double *)Tsa);
+  return hipGetLastError();
+}
+hipError_t convert(const double *in, int64_t n, void *out, int type, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  const dim3 g(ew_blocks(n)), b(kEwThreads);
+  if (type == 1) hipLaunchKernelGGL(k_convert<float>, g, b, 0, s, in, n, (float *)out);
+  else if (type == 2) hipLaunchKernelGGL(k_convert<uint16_t>, g, b, 0, s, in, n, (uint16_t *)out);
+  else hipLaunchKernelGGL(k_convert<double>, g, b, 0, s, in, n, (double *)out);
   return hipGetLastError();
 }
 hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, double *R2, hipStream_t s) {
@@ -452,7 +488,7 @@ hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, double *R2, hip
                      o, v, R2);
   return hipGetLastError();
 }
-hipError_t triples_energy(const double *W, const int *table, int nb, const double *Kov,
+hipError_t triples_energy(const void *W, int wtype, const int *table, int nb, const double *Kov,
                           const double *t1, const double *eo, const double *ev, int64_t o,
                           int64_t v, double *partials, int64_t *nparts, hipStream_t s) {
   const int tpd = (int)((v + TT - 1) / TT);
@@ -460,8 +496,12 @@ hipError_t triples_energy(const double *W, const int *table, int nb, const doubl
   const int per_entry = tiles < kTriplesBlocks ? tiles : kTriplesBlocks;
   *nparts = (int64_t)per_entry * nb;
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(k_triples_energy, dim3(per_entry, nb), dim3(kRedThreads), 0, s, W, table, Kov,
-                     t1, eo, ev, o, v, tpd, partials);
+  if (wtype == 1)
+    hipLaunchKernelGGL(k_triples_energy<float>, dim3(per_entry, nb), dim3(kRedThreads), 0, s,
+                       (const float *)W, table, Kov, t1, eo, ev, o, v, tpd, partials);
+  else
+    hipLaunchKernelGGL(k_triples_energy<double>, dim3(per_entry, nb), dim3(kRedThreads), 0, s,
+                       (const double *)W, table, Kov, t1, eo, ev, o, v, tpd, partials);
   return hipGetLastError();
 }
 

@@ -31,6 +31,10 @@ struct Layout {
   double *u, *R1, *R2, *S, *Xc, *Goovv, *Cint, *Dint, *Wkl, *Y1, *Z1;
   double *chunk;                    // (ac|bd)~ for chunk_a values of a: [a][b][c][d]
   double *Tsa, *SA;                 // ladder rows [t + t^T ; t - t^T] and results [o^2][v][v]
+  double *Btvv_lp;                  // B~_vv in the precision of the ladder products
+  double *t2_lp;                    // t2 in the precision of the (T) products
+  Prec lp;                          // precision of the ladder and (T) products
+  int lpt;                          // its element type: 0 double, 1 float, 2 bf16
   double *dx, *de;                  // DIIS vectors and errors [m][namp]
   int64_t chunk_a, namp;
   int diis_m;

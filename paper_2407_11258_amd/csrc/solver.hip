@@ -93,6 +93,8 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   Arena A{base};
   L = Layout{};
   L.dm = dm;
+  L.lp = opt.precision == LNOCC_FP32 ? Prec::F32 : (opt.precision == LNOCC_BF16 ? Prec::BF16 : Prec::F64);
+  L.lpt = (int)L.lp;
   // common
   L.Boo = A.d(X * oo); L.Bov = A.d(X * ov); L.Bvv = A.d(X * vv);
   L.Kov = A.d(oovv);
@@ -122,6 +124,7 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.Wkl = A.d(oo * oo); L.Y1 = A.d(X * ov); L.Z1 = A.d(X * ov);
   L.chunk = A.d(L.chunk_a * vvv);
   L.Tsa = A.d(oovv); L.SA = A.d(oovv);
+  L.Btvv_lp = (L.lp != Prec::F64) ? A.d(X * vv) : nullptr;
   L.dx = A.d(L.diis_m * N); L.de = A.d(L.diis_m * N);
   const size_t ccsd_end = A.off;
   // (T) phase (aliases the CCSD scratch)
@@ -134,6 +137,7 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.ntriples = nt;
   L.Gt = A.d(ov * vv); L.Jt = A.d(oo * ov);
   L.W = A.d(nb * vvv);
+  L.t2_lp = (L.lp != Prec::F64) ? A.d(oovv) : nullptr;
   L.tpart = A.d(nb * kTriplesBlocks);
   L.table = A.i(3 * std::max<int64_t>(nt, 1));
   const size_t t_end = A.off;
@@ -306,17 +310,30 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
   // A = R^ab - R^ba = sum_cd (t^cd - t^dc) (ac|bd) (antisymmetric in both): the
   // (ac|bd) block is formed for b <= a only (half of the v^4 build) and
   // contracted with o^2 rows (i <= j for S, i < j for A) instead of 2 o^2.
-  LN_TRY(pack_t(t2, o, v, L.Tsa, s));
+  // In the FP32 / BF16 modes B~_vv, the (ac|bd) block and the rows are stored in
+  // that precision; products accumulate in FP32 per tile and SA stays FP64.
+  const bool lowp = L.lp != Prec::F64;
+  const size_t esz = L.lp == Prec::F64 ? 8 : (L.lp == Prec::F32 ? 4 : 2);
+  const char *bvv = (const char *)L.Btvv;
+  if (lowp) {
+    LN_TRY(convert(L.Btvv, X * vv, L.Btvv_lp, L.lpt, s));
+    bvv = (const char *)L.Btvv_lp;
+  }
+  LN_TRY(pack_t(t2, o, v, L.Tsa, L.lpt, s));
   for (int64_t a0 = 0; a0 < v; a0 += L.chunk_a) {
     const int64_t na = std::min<int64_t>(L.chunk_a, v - a0), a1 = a0 + na;
     GemmDesc d = DESC(na * v, v, a1 * v, v, L.chunk, vvv, v, vv, 1, 0.0);
-    SEG(d, X, 1, 1.0, OP(L.Btvv + a0 * v, v, 1, vv, 0), OP(L.Btvv, v, 1, vv, 0));
+    SEG(d, X, 1, 1.0, OP((const double *)(bvv + a0 * v * esz), v, 1, vv, 0),
+        OP((const double *)bvv, v, 1, vv, 0));
     d.kind = Kind::LadderBuild;
+    d.prec = L.lp;
+    d.c_type = L.lpt;
     LN_TRY(gett(d, s));
     // SA[r][a][b] = sum_cd Tsa[r][cd] g[a][b][cd], rows (a, b < a1) of the block
     d = DESC(na * a1, a1, oo, 1, L.SA + a0 * v, v, 1, vv, 0, 0.0);
     SEG(d, vv, 1, 1.0, OP(L.chunk, vvv, vv, 1, 0), OP(L.Tsa, vv, 0, 1, 0));
     d.kind = Kind::LadderContract;
+    d.prec = L.lp;
     LN_TRY(gett(d, s));
   }
   LN_TRY(unpack_ladder(L.SA, o, v, L.R2, s));
@@ -529,16 +546,26 @@ int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s) 
     LN_TRY(dsync(s));
     return LNOCC_OK;
   }
+  // In the FP32 / BF16 modes the integrals and amplitudes entering W are
+  // stored in that precision and W itself in FP32; the energy sum is FP64.
   {  // Gt[i][a][b][d] = (ai|bd)
     GemmDesc d = DESC(ov, 1, vv, 1, L.Gt, vv, 0, 1, 0, 0.0);
     SEG(d, X, 1, 1.0, OP(L.Bov, 1, 0, ov, 0), OP(L.Bvv, 1, 0, vv, 0));
+    d.c_type = L.lpt;
     LN_TRY(gett(d, s));
   }
   {  // Jt[j][k][c][l] = (ck|jl)
     GemmDesc d = DESC(ov, v, oo, o, L.Jt, vo, o, ovo, 1, 0.0);
     SEG(d, X, 1, 1.0, OP(L.Bov, v, 1, ov, 0), OP(L.Boo, o, 1, oo, 0));
+    d.c_type = L.lpt;
     LN_TRY(gett(d, s));
   }
+  const double *t2w = t2;
+  if (L.lp != Prec::F64) {
+    LN_TRY(convert(t2, oo * vv, L.t2_lp, L.lpt, s));
+    t2w = L.t2_lp;
+  }
+  const int wtype = L.lp == Prec::F64 ? 0 : 1;
   std::vector<int> tab;
   tab.reserve(3 * L.ntriples);
   for (int i = 0; i < o; ++i)
@@ -551,37 +578,38 @@ int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s) 
     const int *table = L.table + 3 * t0;
     auto finish = [&](GemmDesc &d) {
       d.batch = nb; d.table = table; d.c_bid = vvv; d.kind = Kind::TriplesW;
+      d.prec = L.lp; d.c_type = wtype;
       d.tmax[0] = d.tmax[1] = d.tmax[2] = (int)(o - 1);
     };
     {  // rows (a,b), column c: P1, P3, H1, H3
       GemmDesc d = DESC(vv, v, v, 1, L.W, vv, v, 1, 0, 0.0);
-      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), vvv, 0, 0), OPB(OP(t2, v, 0, 1, 0), 0, vv, ovv));
-      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, vvv, 0), OPB(OP(t2, v, 0, 1, 0), vv, 0, ovv));
-      SEG(d, o, 1, -1.0, OPB(OP(t2, v, 1, vv, 0), ovv, 0, 0), OPB(OP(L.Jt, o, 0, 1, 0), 0, ovo, vo));
-      SEG(d, o, 1, -1.0, OPB(OP(t2, 1, v, vv, 0), 0, ovv, 0), OPB(OP(L.Jt, o, 0, 1, 0), ovo, 0, vo));
+      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), vvv, 0, 0), OPB(OP(t2w, v, 0, 1, 0), 0, vv, ovv));
+      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, vvv, 0), OPB(OP(t2w, v, 0, 1, 0), vv, 0, ovv));
+      SEG(d, o, 1, -1.0, OPB(OP(t2w, v, 1, vv, 0), ovv, 0, 0), OPB(OP(L.Jt, o, 0, 1, 0), 0, ovo, vo));
+      SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, ovv, 0), OPB(OP(L.Jt, o, 0, 1, 0), ovo, 0, vo));
       finish(d);
       LN_TRY(gett(d, s));
     }
     {  // rows (a,c), column b: P2, P5, H2, H5
       GemmDesc d = DESC(vv, v, v, 1, L.W, vv, 1, v, 0, 1.0);
-      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), vvv, 0, 0), OPB(OP(t2, v, 0, 1, 0), 0, ovv, vv));
-      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, 0, vvv), OPB(OP(t2, v, 0, 1, 0), vv, ovv, 0));
-      SEG(d, o, 1, -1.0, OPB(OP(t2, v, 1, vv, 0), ovv, 0, 0), OPB(OP(L.Jt, o, 0, 1, 0), 0, vo, ovo));
-      SEG(d, o, 1, -1.0, OPB(OP(t2, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), ovo, vo, 0));
+      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), vvv, 0, 0), OPB(OP(t2w, v, 0, 1, 0), 0, ovv, vv));
+      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, 0, vvv), OPB(OP(t2w, v, 0, 1, 0), vv, ovv, 0));
+      SEG(d, o, 1, -1.0, OPB(OP(t2w, v, 1, vv, 0), ovv, 0, 0), OPB(OP(L.Jt, o, 0, 1, 0), 0, vo, ovo));
+      SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), ovo, vo, 0));
       finish(d);
       LN_TRY(gett(d, s));
     }
     {  // rows (b,c), column a: P4, P6, H4, H6
       GemmDesc d = DESC(vv, v, v, 1, L.W, v, 1, vv, 0, 1.0);
-      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), 0, vvv, 0), OPB(OP(t2, v, 0, 1, 0), ovv, 0, vv));
-      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, 0, vvv), OPB(OP(t2, v, 0, 1, 0), ovv, vv, 0));
-      SEG(d, o, 1, -1.0, OPB(OP(t2, v, 1, vv, 0), 0, ovv, 0), OPB(OP(L.Jt, o, 0, 1, 0), vo, 0, ovo));
-      SEG(d, o, 1, -1.0, OPB(OP(t2, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), vo, ovo, 0));
+      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), 0, vvv, 0), OPB(OP(t2w, v, 0, 1, 0), ovv, 0, vv));
+      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, 0, vvv), OPB(OP(t2w, v, 0, 1, 0), ovv, vv, 0));
+      SEG(d, o, 1, -1.0, OPB(OP(t2w, v, 1, vv, 0), 0, ovv, 0), OPB(OP(L.Jt, o, 0, 1, 0), vo, 0, ovo));
+      SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), vo, ovo, 0));
       finish(d);
       LN_TRY(gett(d, s));
     }
     int64_t nparts = 0;
-    LN_TRY(triples_energy(L.W, table, nb, L.Kov, t1, in.eo, in.ev, o, v, L.tpart, &nparts, s));
+    LN_TRY(triples_energy(L.W, wtype, table, nb, L.Kov, t1, in.eo, in.ev, o, v, L.tpart, &nparts, s));
     LN_TRY(reduce_partials(L.tpart, nparts, acc, 1, s));
   }
   double host = 0.0;

@@ -55,7 +55,7 @@ def _operand(t, ro, ri, ko, ki, b0=0, b1=0, bid=0):
     return L.lnocc_operand_t(t.data_ptr(), ro, ri, ko, ki, b0, b1, bid)
 
 
-def _contract(M, Mi, N, Ni, c, cstr, segs, beta=0.0, batch=1, nb1=1, cb=(0, 0, 0)):
+def _contract(M, Mi, N, Ni, c, cstr, segs, beta=0.0, batch=1, nb1=1, cb=(0, 0, 0), precision=0):
     d = L.lnocc_contract_t()
     d.M, d.Mi, d.N, d.Ni = M, Mi, N, Ni
     d.nseg = len(segs)
@@ -66,6 +66,7 @@ def _contract(M, Mi, N, Ni, c, cstr, segs, beta=0.0, batch=1, nb1=1, cb=(0, 0, 0
     d.c_mo, d.c_mi, d.c_no, d.c_ni = cstr
     d.c_b0, d.c_b1, d.c_bid = cb
     d.beta, d.batch, d.nb1 = beta, batch, nb1
+    d.precision = precision
     st = L.lnocc_contract(d, torch.cuda.current_stream().cuda_stream)
     _KEEP.clear()
     assert st == L.LNOCC_OK, L.lnocc_status_string(st)
@@ -113,6 +114,45 @@ def test_contract_two_index_modes_segments_and_batch():
     _contract(o * v, v, o * v, v, c, (ovv, v, vv, 1), [seg1, seg2], beta=2.0,
               batch=nb0 * nb1, nb1=nb1, cb=(0, 0, o * ovv))
     np.testing.assert_allclose(host(c), ref, rtol=0, atol=1e-11)
+
+
+def _bf16_round(x):
+    """Round to the nearest bf16 (ties to even) and return (bits, value)."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    bits = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    val = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return bits, val
+
+
+@pytest.mark.parametrize("M,N,K", [(130, 70, 37), (257, 160, 200), (20, 33, 1000)])
+def test_contract_low_precision(M, N, K):
+    say(f"contract fp32/bf16 M={M} N={N} K={K}")
+    rng = np.random.default_rng(7 + M)
+    A = rng.standard_normal((M, K))
+    Bm = rng.standard_normal((N, K))
+    # FP32: operands exactly representable, FP32 accumulation
+    A32, B32 = A.astype(np.float32), Bm.astype(np.float32)
+    ref = A32.astype(np.float64) @ B32.astype(np.float64).T
+    c = torch.zeros((M, N), dtype=torch.float64, device=DEV)
+    a_t = torch.tensor(A32, device=DEV)
+    b_t = torch.tensor(B32, device=DEV)
+    _contract(M, 1, N, 1, c, (N, 0, 1, 0),
+              [(K, 1, 1.0, _operand(a_t, K, 0, 1, 0), _operand(b_t, K, 0, 1, 0))], precision=1)
+    err = np.abs(host(c) - ref).max() / np.abs(ref).max()
+    assert err < 2e-6 * np.sqrt(K), err
+    # BF16: operands rounded to bf16 on the host, FP32 accumulation; also the
+    # row-contiguous (transposed) operand layout
+    abits, aval = _bf16_round(A)
+    bbits, bval = _bf16_round(Bm)
+    ref = aval @ bval.T
+    a_t = torch.tensor(abits.T.copy().view(np.int16), device=DEV)
+    b_t = torch.tensor(bbits.view(np.int16), device=DEV)
+    c.zero_()
+    _contract(M, 1, N, 1, c, (N, 0, 1, 0),
+              [(K, 1, 1.0, _operand(a_t, 1, 0, M, 0), _operand(b_t, K, 0, 1, 0))], precision=2)
+    err = np.abs(host(c) - ref).max() / np.abs(ref).max()
+    assert err < 2e-6 * np.sqrt(K), err
 
 
 # ------------------------------------------------------------ solver pieces
@@ -184,6 +224,29 @@ def test_full_solve_matches_oracle(o, v, X, seed, chunk):
     np.testing.assert_allclose(host(t2), ref.t2, rtol=0, atol=1e-7)
     np.testing.assert_allclose(host(t1), ref.t1, rtol=0, atol=1e-7)
     assert fs.residual <= 1e-10
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-6), ("bf16", 5e-3)])
+def test_mixed_precision_solve(precision, tol):
+    """Ladder and (T) products in FP32 / BF16 (FP32 accumulation), everything
+    else FP64: energies against the FP64 oracle.  FP32 keeps |dE| below the
+    1e-6 Eh target; BF16 operands (8-bit mantissa) do not and are held to a
+    looser bound that documents the size of the error."""
+    say(f"mixed precision solve {precision}")
+    o, v, X, seed = 6, 45, 100, 5
+    f = make_fragment(o, v, X, seed)
+    ref = occ.ccsd(f.B, f.eps_occ, f.eps_vir, conv_tol=1e-10)
+    ref_t = otr.e_triples_restricted(f.B, f.eps_occ, f.eps_vir, ref.t1, ref.t2)
+    B, eo, ev = _fragment_on_device(f)
+    t1 = torch.empty((o, v), dtype=torch.float64, device=DEV)
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=DEV)
+    st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=1e-9,
+                   precision=precision)
+    say(f"  {precision}: dE_ccsd={fs.e_ccsd - ref.e_ccsd:.3e} dE_t={fs.e_t - ref_t:.3e} "
+        f"iters={fs.n_iter} status={st}")
+    assert st in (L.LNOCC_OK, L.LNOCC_NOT_CONVERGED)
+    assert abs(fs.e_ccsd - ref.e_ccsd) < tol * max(1.0, abs(ref.e_ccsd) * 10)
+    assert abs(fs.e_t - ref_t) < tol
 
 
 def test_solve_is_bitwise_reproducible():
