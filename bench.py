@@ -82,6 +82,9 @@ def main() -> int:
     ap.add_argument("--precision", default="fp64", choices=sorted(PEAKS_TFLOPS))
     ap.add_argument("--conv-tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device (a plain copy of known size "
+                         "that scales hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -92,6 +95,15 @@ def main() -> int:
     import torch
     from paper_2407_11258_amd import lnocc as L
     from synth import CONFIG_SHAPES, make_fragment
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration << 20
+        src = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_calibration} MiB done")
+        del src, dst
 
     o, v, X, seed = CONFIG_SHAPES[args.workload]
     log(f"workload {args.workload}: nocc={o} nvir={v} naux={X} seed={seed}")

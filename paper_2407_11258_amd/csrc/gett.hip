@@ -553,7 +553,8 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   // rows by the N width (128, 80 or 64) that pads N least.
   const bool small = (d.M <= 64 || d.N <= 64);
   int BNx = 128;
-  if (!small) {
+  // (the (ac|bd) formation keeps one tile shape so that it is one kernel symbol)
+  if (!small && d.kind != Kind::LadderBuild) {
     int64_t best = -1;
     for (int bn : {128, 80, 64}) {
       const int64_t pad = ((int64_t)(d.N + bn - 1) / bn) * bn - d.N;

@@ -310,6 +310,10 @@ __device__ inline void load_cube(const TW *__restrict__ W, int64_t v, int64_t o0
   }
 }
 
+// The W tensor of one triple is read in six index orders.  Cube tiles are
+// grouped into orbits under permutations of their (a, b, c) block coordinates;
+// a block loads the (up to six) distinct tiles of one orbit once and evaluates
+// the integrand on all of them, so each W element is read from memory once.
 template <typename TW>
 __global__ void k_triples_energy(const TW *__restrict__ Wall, const int *__restrict__ table,
                                  const double *__restrict__ Kov, const double *__restrict__ t1,
@@ -317,39 +321,84 @@ __global__ void k_triples_energy(const TW *__restrict__ Wall, const int *__restr
                                  int64_t o, int64_t v, int tpd, double *partials) {
   __shared__ double L[6][TT * TT * TP];
   __shared__ double sm[kRedThreads / 64];
+  constexpr int P[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
   const int entry = blockIdx.y;
   const int i = table[3 * entry], j = table[3 * entry + 1], k = table[3 * entry + 2];
   const TW *W = Wall + (int64_t)entry * v * v * v;
   const double eijk = eo[i] + eo[j] + eo[k];
-  const int tiles = tpd * tpd * tpd;
+  const int64_t norbits = (int64_t)tpd * (tpd + 1) * (tpd + 2) / 6;
   double acc = 0.0;
-  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-    const int64_t a0 = (int64_t)(tile / (tpd * tpd)) * TT;
-    const int64_t b0 = (int64_t)((tile / tpd) % tpd) * TT;
-    const int64_t c0 = (int64_t)(tile % tpd) * TT;
-    __syncthreads();   // the previous tile's reads of L are done
-    load_cube(W, v, a0, b0, c0, L[0]);   // W^abc
-    load_cube(W, v, b0, c0, a0, L[1]);   // W^bca
-    load_cube(W, v, c0, a0, b0, L[2]);   // W^cab
-    load_cube(W, v, a0, c0, b0, L[3]);   // W^acb
-    load_cube(W, v, b0, a0, c0, L[4]);   // W^bac
-    load_cube(W, v, c0, b0, a0, L[5]);   // W^cba
+  for (int64_t orb = blockIdx.x; orb < norbits; orb += gridDim.x) {
+    // canonical block coordinates c0 <= c1 <= c2 of orbit number orb
+    int c[3];
+    {
+      int64_t r = orb;
+      int A = 0;
+      for (;; ++A) {
+        const int64_t n = (int64_t)(tpd - A) * (tpd - A + 1) / 2;
+        if (r < n) break;
+        r -= n;
+      }
+      int Bc = A;
+      for (;; ++Bc) {
+        const int64_t n = tpd - Bc;
+        if (r < n) break;
+        r -= n;
+      }
+      c[0] = A; c[1] = Bc; c[2] = Bc + (int)r;
+    }
+    // slot[p]: the first permutation with the same tile coordinates as p
+    int slot[6];
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      slot[p] = p;
+      for (int q = 0; q < p; ++q)
+        if (slot[p] == p && c[P[q][0]] == c[P[p][0]] && c[P[q][1]] == c[P[p][1]] &&
+            c[P[q][2]] == c[P[p][2]])
+          slot[p] = q;
+    }
+    __syncthreads();   // the previous orbit's reads of L are done
+#pragma unroll
+    for (int p = 0; p < 6; ++p)
+      if (slot[p] == p)
+        load_cube(W, v, (int64_t)c[P[p][0]] * TT, (int64_t)c[P[p][1]] * TT,
+                  (int64_t)c[P[p][2]] * TT, L[p]);
     __syncthreads();
-    for (int e = threadIdx.x; e < TT * TT * TT; e += blockDim.x) {
-      const int x = e / (TT * TT), y = (e / TT) % TT, z = e % TT;
-      const int64_t a = a0 + x, b = b0 + y, c = c0 + z;
-      if (a >= v || b >= v || c >= v) continue;
-      const double w = L[0][(x * TT + y) * TP + z];
-      const double wbca = L[1][(y * TT + z) * TP + x];
-      const double wcab = L[2][(z * TT + x) * TP + y];
-      const double wacb = L[3][(x * TT + z) * TP + y];
-      const double wbac = L[4][(y * TT + x) * TP + z];
-      const double wcba = L[5][(z * TT + y) * TP + x];
-      const double V = w + Kov[((i * v + a) * o + j) * v + b] * t1[k * v + c] +
-                       Kov[((i * v + a) * o + k) * v + c] * t1[j * v + b] +
-                       Kov[((j * v + b) * o + k) * v + c] * t1[i * v + a];
-      const double Z = 4.0 * w + wbca + wcab - 2.0 * (wacb + wbac + wcba);
-      acc += V * Z / (eijk - ev[a] - ev[b] - ev[c]);
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      if (slot[p] != p) continue;   // every distinct tile once
+      const int s0 = P[p][0], s1 = P[p][1], s2 = P[p][2];
+      // tiles holding W at (b,c,a), (c,a,b), (a,c,b), (b,a,c), (c,b,a) orders
+      auto find = [&](int q0, int q1, int q2) {
+        int r = 0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+          if (P[q][0] == q0 && P[q][1] == q1 && P[q][2] == q2) r = slot[q];
+        return r;
+      };
+      const double *Labc = L[p];
+      const double *Lbca = L[find(s1, s2, s0)];
+      const double *Lcab = L[find(s2, s0, s1)];
+      const double *Lacb = L[find(s0, s2, s1)];
+      const double *Lbac = L[find(s1, s0, s2)];
+      const double *Lcba = L[find(s2, s1, s0)];
+      const int64_t a0 = (int64_t)c[s0] * TT, b0 = (int64_t)c[s1] * TT, c0 = (int64_t)c[s2] * TT;
+      for (int e = threadIdx.x; e < TT * TT * TT; e += blockDim.x) {
+        const int x = e / (TT * TT), y = (e / TT) % TT, z = e % TT;
+        const int64_t a = a0 + x, b = b0 + y, cc = c0 + z;
+        if (a >= v || b >= v || cc >= v) continue;
+        const double w = Labc[(x * TT + y) * TP + z];
+        const double wbca = Lbca[(y * TT + z) * TP + x];
+        const double wcab = Lcab[(z * TT + x) * TP + y];
+        const double wacb = Lacb[(x * TT + z) * TP + y];
+        const double wbac = Lbac[(y * TT + x) * TP + z];
+        const double wcba = Lcba[(z * TT + y) * TP + x];
+        const double V = w + Kov[((i * v + a) * o + j) * v + b] * t1[k * v + cc] +
+                         Kov[((i * v + a) * o + k) * v + cc] * t1[j * v + b] +
+                         Kov[((j * v + b) * o + k) * v + cc] * t1[i * v + a];
+        const double Z = 4.0 * w + wbca + wcab - 2.0 * (wacb + wbac + wcba);
+        acc += V * Z / (eijk - ev[a] - ev[b] - ev[cc]);
+      }
     }
   }
   const double weight = (i < j && j < k) ? 2.0 : 1.0;   // (6 or 3) / 3
@@ -492,8 +541,8 @@ hipError_t triples_energy(const void *W, int wtype, const int *table, int nb, co
                           const double *t1, const double *eo, const double *ev, int64_t o,
                           int64_t v, double *partials, int64_t *nparts, hipStream_t s) {
   const int tpd = (int)((v + TT - 1) / TT);
-  const int tiles = tpd * tpd * tpd;
-  const int per_entry = tiles < kTriplesBlocks ? tiles : kTriplesBlocks;
+  const int64_t orbits = (int64_t)tpd * (tpd + 1) * (tpd + 2) / 6;
+  const int per_entry = orbits < kTriplesBlocks ? (int)orbits : kTriplesBlocks;
   *nparts = (int64_t)per_entry * nb;
   if (dry_run()) return hipSuccess;
   if (wtype == 1)
