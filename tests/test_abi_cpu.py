@@ -1,0 +1,145 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+* the library loads and exports every function include/lnocc.h declares;
+* the ctypes mirrors have the C layout (sizes and offsets from gcc);
+* argument validation answers before any device work;
+* validation mode runs the whole launch sequence of a solve, every
+  contraction checked to stay inside the workspace and the caller's arrays,
+  for the named workloads and precisions (pointers are never dereferenced).
+"""
+import ctypes as C
+import os
+import pathlib
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_2407_11258_amd import lnocc as L
+from synth import CONFIG_SHAPES, batch_shapes
+
+ROOT = pathlib.Path(__file__).resolve().parent.parent
+HEADER = ROOT / "include" / "lnocc.h"
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lnocc_\w+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported():
+    names = declared_functions()
+    assert "lnocc_fragment_ccsd" in names and "lnocc_batch_solve" in names
+    lib = C.CDLL(str(L._LIB_PATH))
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_struct_layouts_match_the_header():
+    structs = {"lnocc_fragment_t": L.lnocc_fragment_t, "lnocc_options_t": L.lnocc_options_t,
+               "lnocc_operand_t": L.lnocc_operand_t, "lnocc_contract_t": L.lnocc_contract_t,
+               "lnocc_kernel_stats_t": L.lnocc_kernel_stats_t}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    with tempfile.TemporaryDirectory() as td:
+        src, exe = os.path.join(td, "l.c"), os.path.join(td, "l")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-std=c11", src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    for line in out.splitlines():
+        cname, what, val = line.split()
+        py = structs[cname]
+        if what == "size":
+            assert C.sizeof(py) == int(val), cname
+        else:
+            assert getattr(py, what).offset == int(val), (cname, what)
+
+
+def test_defaults_and_status_strings():
+    opt = L.lnocc_default_options()
+    assert (opt.precision, opt.guess, opt.do_triples, opt.max_iter, opt.diis_space,
+            opt.diis_start) == (L.LNOCC_FP64, L.LNOCC_GUESS_MP2, 1, 100, 8, 2)
+    for st in (0, 1, -1, -2, -3, -4):
+        assert L.lnocc_status_string(st).startswith("LNOCC")
+    assert "unknown" in L.lnocc_status_string(42)
+
+
+def test_argument_errors_need_no_device():
+    opt = L.lnocc_default_options()
+    f = L.lnocc_fragment_t()
+    assert L.lnocc_workspace_bytes([f], opt) == (L.LNOCC_EINVAL, 0)       # nocc = 0
+    f.nocc, f.nvir, f.naux = 4, 20, 72
+    st, n = L.lnocc_workspace_bytes([f], opt)
+    assert st == L.LNOCC_OK and n > 0
+    assert L._lib.lnocc_fragment_ccsd(None, C.byref(opt)) == L.LNOCC_EINVAL
+    assert L.lnocc_fragment_ccsd(f, opt) == L.LNOCC_EINVAL                  # null B
+    bad = L.lnocc_default_options()
+    bad.diis_space = 0
+    assert L.lnocc_workspace_bytes([f], bad)[0] == L.LNOCC_EINVAL
+    bad = L.lnocc_default_options()
+    bad.precision = 7
+    assert L.lnocc_workspace_bytes([f], bad)[0] == L.LNOCC_EINVAL
+    f.nocc = 2000                                                            # beyond limits
+    assert L.lnocc_workspace_bytes([f], opt)[0] == L.LNOCC_EINVAL
+
+
+def _fake_fragment(o, v, X):
+    """Pointer values in disjoint ranges; never dereferenced in validation mode."""
+    f = L.lnocc_fragment_t()
+    f.nocc, f.nvir, f.naux = o, v, X
+    n = o + v
+    base = 1 << 44
+    f.B = base
+    f.eps_occ = base + X * n * n * 8 + 4096
+    f.eps_vir = f.eps_occ + o * 8 + 4096
+    f.t1 = f.eps_vir + v * 8 + 4096
+    f.t2 = f.t1 + o * v * 8 + 4096
+    f.conv_tol = 1e-8
+    return f
+
+
+@pytest.fixture
+def validation_mode():
+    L.lnocc_set_validation_mode(True)
+    yield
+    L.lnocc_set_validation_mode(False)
+
+
+SHAPES = [v[:3] for v in CONFIG_SHAPES.values()] + [(1, 1, 1), (2, 37, 61), (1, 10, 20),
+                                                    (6, 45, 100)] + [s[:3] for s in batch_shapes()[:6]]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("o,v,X", SHAPES)
+def test_launch_sequence_stays_in_bounds(validation_mode, o, v, X, precision):
+    opt = L.make_options(precision=precision)
+    f = _fake_fragment(o, v, X)
+    st, nbytes = L.lnocc_workspace_bytes([f], opt)
+    assert st == L.LNOCC_OK
+    opt.workspace, opt.workspace_bytes = 1 << 45, nbytes
+    assert L.lnocc_fragment_ccsd(f, opt) == L.LNOCC_OK
+    assert L.lnocc_fragment_triples(f, opt) == L.LNOCC_OK
+    assert L.lnocc_ccsd_residuals(f, opt, 1 << 46, (1 << 46) + (1 << 40)) == L.LNOCC_OK
+    # a workspace one byte short is refused before anything runs
+    opt.workspace_bytes = nbytes - 1
+    assert L.lnocc_fragment_ccsd(f, opt) == L.LNOCC_ENOMEM
+
+
+def test_small_ladder_blocks_and_triple_batches(validation_mode):
+    opt = L.make_options(ladder_chunk_bytes=1 << 20, triples_batch=5)
+    f = _fake_fragment(7, 53, 90)
+    st, nbytes = L.lnocc_workspace_bytes([f], opt)
+    opt.workspace, opt.workspace_bytes = 1 << 45, nbytes
+    assert L.lnocc_fragment_ccsd(f, opt) == L.LNOCC_OK
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(RuntimeError):
+        L.load_library(tmp_path / "nope.so")

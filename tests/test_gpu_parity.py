@@ -249,6 +249,43 @@ def test_mixed_precision_solve(precision, tol):
     assert abs(fs.e_t - ref_t) < tol
 
 
+def _golden(name):
+    import json
+    import pathlib
+    path = pathlib.Path(__file__).resolve().parent / "golden" / f"{name}.json"
+    if not path.exists():
+        pytest.skip(f"{path.name} not generated")
+    return json.loads(path.read_text())
+
+
+@pytest.mark.parametrize("precision,tol_e", [("fp64", 1e-8), ("fp32", 1e-6)])
+def test_realistic_fragment_against_stored_oracle(precision, tol_e):
+    """nocc=16, nvir=160, naux=528 (the benchmark workload, several tiles in
+    every mode and a ragged 160 = 128 + 32 edge) against oracle values stored
+    by tests/golden/make_golden.py."""
+    g = _golden("single_realistic")
+    say(f"realistic fragment {precision}")
+    f = make_fragment(g["nocc"], g["nvir"], g["naux"], g["seed"])
+    assert f.sha256() == g["input_sha256"]
+    o, v = f.nocc, f.nvir
+    B, eo, ev = _fragment_on_device(f)
+    t1 = torch.empty((o, v), dtype=torch.float64, device=DEV)
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=DEV)
+    st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=g["conv_tol"],
+                   precision=precision)
+    say(f"  dE_mp2={fs.e_mp2 - g['e_mp2']:.2e} dE_ccsd={fs.e_ccsd - g['e_ccsd']:.2e} "
+        f"dE_t={fs.e_t - g['e_t']:.2e} iters={fs.n_iter} (oracle {g['n_iter']})")
+    assert st == L.LNOCC_OK
+    assert abs(fs.e_mp2 - g["e_mp2"]) < 1e-10
+    assert abs(fs.e_ccsd - g["e_ccsd"]) < tol_e
+    assert abs(fs.e_t - g["e_t"]) < tol_e
+    T2 = host(t2)
+    idx = np.array(g["t2_index"])
+    got = T2[idx[:, 0], idx[:, 1], idx[:, 2], idx[:, 3]]
+    np.testing.assert_allclose(got, g["t2_value"], rtol=0, atol=1e-7 if precision == "fp64" else 1e-6)
+    assert abs(np.linalg.norm(T2) - g["t2_norm"]) < 1e-7 * g["t2_norm"] * (1 if precision == "fp64" else 10)
+
+
 def test_solve_is_bitwise_reproducible():
     say("determinism o=4 v=20")
     f = make_fragment(4, 20, 72, 0)
