@@ -82,6 +82,11 @@ def main() -> int:
     ap.add_argument("--precision", default="fp64", choices=sorted(PEAKS_TFLOPS))
     ap.add_argument("--conv-tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--level-shift", type=float, default=0.0)
+    ap.add_argument("--diis-start", type=int, default=2)
+    ap.add_argument("--max-iter", type=int, default=100)
+    ap.add_argument("--triples-reps", type=int, default=2,
+                    help="timed repetitions of (T) alone on the converged amplitudes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a plain copy of known size "
                          "that scales hardware byte counters)")
@@ -115,7 +120,8 @@ def main() -> int:
     ev = torch.tensor(frag.eps_vir, device=dev)
     t1 = torch.empty((o, v), dtype=torch.float64, device=dev)
     t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=dev)
-    opt = L.make_options(precision=args.precision)
+    opt = L.make_options(precision=args.precision, level_shift=args.level_shift,
+                         diis_start=args.diis_start, max_iter=args.max_iter)
     fs = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
     ws = L.Workspace(dev)
     ws.attach([fs], opt)
@@ -142,11 +148,9 @@ def main() -> int:
     prof = L.lnocc_profile_collect()
     status = fs.status
 
-    # (T) alone on the converged amplitudes
+    # (T) alone on the converged amplitudes (the solve above already warmed it up)
     ft = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
-    L.lnocc_fragment_triples(ft, opt)
-    torch.cuda.synchronize()
-    nrep = 2
+    nrep = max(1, args.triples_reps)
     t0 = time.perf_counter()
     for _ in range(nrep):
         st = L.lnocc_fragment_triples(ft, opt)
@@ -189,6 +193,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "nocc": o, "nvir": v, "naux": X, "seed": seed,
                    "precision": args.precision, "conv_tol": args.conv_tol,
+                   "level_shift": args.level_shift, "diis_start": args.diis_start,
                    "ccsd_iterations": fs.n_iter, "status": status},
         "triples_tflops": f_t / t_triples / 1e12,
         "triples_ms": t_triples * 1e3,

@@ -96,6 +96,8 @@ typedef struct lnocc_options_t {
   size_t ladder_chunk_bytes; /* cap on the (ac|bd) block formed at a time; 0 = 8 GiB */
   int32_t triples_batch;     /* unique (i<=j<=k) triples per (T) pass; 0 = automatic */
   int32_t reserved1;
+  double level_shift;        /* >= 0 (Hartree): amplitude steps R / (D - level_shift); the
+                                convergence test always uses the unshifted step R / D */
 } lnocc_options_t;
 
 /* Fills *opt with defaults: FP64, MP2 guess, triples on, max_iter 100,
@@ -115,7 +117,9 @@ int lnocc_workspace_bytes(const lnocc_fragment_t *f, int32_t nfrag,
  * (T) (Eq. 16 at i = i', SI Sec. S1) when opt->do_triples.  Starts from the
  * MP1 guess (Eq. 21) or the caller's amplitudes, iterates Jacobi steps with
  * Pulay DIIS until the residual norm falls to f->conv_tol, writes t1 / t2 and
- * the host outputs of *f, and returns f->status. */
+ * the host outputs of *f, and returns f->status.  A residual that grows three
+ * iterations in a row, or rises 1000-fold above the best one, restarts the
+ * DIIS subspace. */
 int lnocc_fragment_ccsd(lnocc_fragment_t *f, const lnocc_options_t *opt);
 
 /* (T) energy (Eq. 16 at i = i' summed over i; W, V and Delta of SI Sec. S1)

@@ -30,7 +30,7 @@ int check_options(const lnocc_options_t *opt) {
     return LNOCC_EINVAL;
   if (opt->guess != LNOCC_GUESS_MP2 && opt->guess != LNOCC_GUESS_USER) return LNOCC_EINVAL;
   if (opt->max_iter < 0 || opt->diis_space < 1 || opt->diis_space > 16 || opt->diis_start < 1 ||
-      opt->triples_batch < 0)
+      opt->triples_batch < 0 || !(opt->level_shift >= 0.0) || !std::isfinite(opt->level_shift))
     return LNOCC_EINVAL;
   return LNOCC_OK;
 }

@@ -31,10 +31,11 @@ hipError_t energy_partials(const double *Kov, const double *t1, const double *t2
 // out[0] (+)= sum of partials[0..n) in a fixed order
 hipError_t reduce_partials(const double *partials, int64_t n, double *out, int accumulate,
                            hipStream_t s);
-// x = t + R / D (Jacobi step) as one concatenated vector [t1 | t2]; e = x - t.
+// x = t + R / (D - shift) (level-shifted Jacobi step) as one concatenated vector
+// [t1 | t2]; e = x - t; partials[kRedBlocks] <- pieces of ||R / D||^2.
 hipError_t jacobi_step(const double *t1, const double *t2, const double *R1, const double *R2,
-                       const double *eo, const double *ev, int64_t o, int64_t v, double *x,
-                       double *e, hipStream_t s);
+                       const double *eo, const double *ev, int64_t o, int64_t v, double shift,
+                       double *x, double *e, double *partials, hipStream_t s);
 // partials[i * kRedBlocks + b] <- pieces of dot(e_new, e_i), i < m
 hipError_t dot_partials(const double *E, int64_t stride, int m, const double *enew, int64_t N,
                         double *partials, hipStream_t s);

@@ -156,27 +156,38 @@ __global__ void k_reduce(const double *__restrict__ partials, int64_t n, double 
   if (threadIdx.x == 0) out[0] = accumulate ? out[0] + r : r;
 }
 
+// x = t + R / (D - shift) (Jacobi step with a level shift; D < 0), e = x - t,
+// and partials of sum (R / D)^2, the squared norm of the unshifted step.
 __global__ void k_jacobi(const double *__restrict__ t1, const double *__restrict__ t2,
                          const double *__restrict__ R1, const double *__restrict__ R2,
-                         const double *eo, const double *ev, int64_t o, int64_t v, double *x,
-                         double *err) {
+                         const double *eo, const double *ev, int64_t o, int64_t v, double shift,
+                         double *x, double *err, double *partials) {
+  __shared__ double sm[kRedThreads / 64];
   const int64_t n1 = o * v, vv = v * v, total = n1 + o * o * vv;
+  double acc = 0.0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    double told, xn;
+    double told, r, d;
     if (e < n1) {
       const int64_t i = e / v, a = e % v;
       told = t1[e];
-      xn = told + R1[e] / (eo[i] - ev[a]);
+      r = R1[e];
+      d = eo[i] - ev[a];
     } else {
       const int64_t f = e - n1, ij = f / vv, ab = f % vv;
       const int64_t i = ij / o, j = ij % o, a = ab / v, b = ab % v;
       told = t2[f];
-      xn = told + R2[f] / (eo[i] + eo[j] - ev[a] - ev[b]);
+      r = R2[f];
+      d = eo[i] + eo[j] - ev[a] - ev[b];
     }
+    const double xn = told + r / (d - shift);
     x[e] = xn;
     err[e] = xn - told;
+    const double u = r / d;
+    acc += u * u;
   }
+  const double rr = block_sum(acc, sm);
+  if (threadIdx.x == 0) partials[blockIdx.x] = rr;
 }
 
 constexpr int kMaxDiis = 16;
@@ -478,11 +489,11 @@ hipError_t reduce_partials(const double *partials, int64_t n, double *out, int a
   return hipGetLastError();
 }
 hipError_t jacobi_step(const double *t1, const double *t2, const double *R1, const double *R2,
-                       const double *eo, const double *ev, int64_t o, int64_t v, double *x,
-                       double *e, hipStream_t s) {
+                       const double *eo, const double *ev, int64_t o, int64_t v, double shift,
+                       double *x, double *e, double *partials, hipStream_t s) {
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(k_jacobi, dim3(ew_blocks(o * v + o * o * v * v)), dim3(kEwThreads), 0, s,
-                     t1, t2, R1, R2, eo, ev, o, v, x, e);
+  hipLaunchKernelGGL(k_jacobi, dim3(kRedBlocks), dim3(kRedThreads), 0, s, t1, t2, R1, R2, eo, ev,
+                     o, v, shift, x, e, partials);
   return hipGetLastError();
 }
 hipError_t dot_partials(const double *E, int64_t stride, int m, const double *enew, int64_t N,

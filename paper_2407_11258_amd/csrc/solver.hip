@@ -36,6 +36,15 @@ namespace lnocc {
 
 namespace {
 
+// LNOCC_LOG=1: one line per CCSD iteration and per (T) pass on stderr.
+bool log_enabled() {
+  static const bool on = [] {
+    const char *e = std::getenv("LNOCC_LOG");
+    return e && e[0] && e[0] != '0';
+  }();
+  return on;
+}
+
 GOperand OP(const double *p, int64_t ro, int64_t ri, int64_t ko, int64_t ki) {
   GOperand g{};
   g.p = p; g.s_ro = ro; g.s_ri = ri; g.s_ko = ko; g.s_ki = ki;
@@ -101,8 +110,8 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.t1w = A.d(ov); L.t2w = A.d(oovv);
   L.hoo = A.d(oo); L.hov = A.d(ov); L.hvo = A.d(ov); L.hvv = A.d(vv);
   L.J = A.d(X);
-  L.scal = A.d(64);
-  L.partials = A.d(16 * kRedBlocks);
+  L.scal = A.d(64);   // [0] energy, [1..16] Gram row, [32] ||R/D||^2, [40] (T) sum
+  L.partials = A.d(17 * kRedBlocks);   // 16 Gram-row slices + the step norm
   L.splitk_elems = std::max<int64_t>({(int64_t)1 << 22, 64 * vv, 4 * oovv});
   L.splitk = A.d(L.splitk_elems);
   const size_t phase = A.off;
@@ -474,54 +483,85 @@ int run_ccsd(const Layout &L, const Inputs &in, const lnocc_options_t &opt, Outp
   const int m = L.diis_m;
   std::vector<double> G(m * m, 0.0);
   int count = 0;         // vectors stored so far
+  int growth = 0;        // consecutive iterations with a growing residual
+  double prev = INFINITY, best = INFINITY;
   bool converged = (opt.max_iter == 0);
+  double *rnorm = L.scal + 32;   // ||R / D||^2 of the current iterate
   for (int it = 1; it <= opt.max_iter; ++it) {
     int st = ccsd_residuals(L, t1, t2, s);
     if (st) return st;
     const bool use_diis = (m > 1) && (it >= opt.diis_start);
     const int slot = use_diis ? (count % m) : 0;
     double *xs = L.dx + (int64_t)slot * N, *es = L.de + (int64_t)slot * N;
-    LN_TRY(jacobi_step(t1, t2, L.R1, L.R2, in.eo, in.ev, o, v, xs, es, s));
+    LN_TRY(jacobi_step(t1, t2, L.R1, L.R2, in.eo, in.ev, o, v, opt.level_shift, xs, es,
+                       L.partials + 16 * kRedBlocks, s));
+    LN_TRY(reduce_partials(L.partials + 16 * kRedBlocks, kRedBlocks, rnorm, 0, s));
     const int nvalid = use_diis ? std::min(count + 1, m) : 1;
     const double *ebase = use_diis ? L.de : es;
     LN_TRY(dot_partials(ebase, N, nvalid, es, N, L.partials, s));
     LN_TRY(reduce_rows(L.partials, nvalid, L.scal + 1, s));
-    LN_TRY(d2h(host, L.scal, (1 + nvalid) * 8, s));
+    LN_TRY(d2h(host, L.scal, 40 * 8, s));
     LN_TRY(dsync(s));
-    const double r2 = host[1 + (use_diis ? slot : 0)];
+    const double r2 = host[32];
     out.residual = std::sqrt(std::max(r2, 0.0));
     out.n_iter = it;
-    if (!std::isfinite(r2)) return LNOCC_ENUMERIC;
+    if (log_enabled()) {
+      std::fprintf(stderr, "lnocc: iteration %d residual %.3e energy %.12f\n", it, out.residual,
+                   it > 1 ? host[0] : out.e_mp2);
+      std::fflush(stderr);
+    }
+    if (!std::isfinite(r2) || !std::isfinite(host[1 + (use_diis ? slot : 0)])) return LNOCC_ENUMERIC;
     if (out.residual <= in.conv_tol) {
       LN_TRY(scatter_vec(xs, o, v, t1, t2, s));
       converged = true;
       break;
     }
+    // DIIS safeguard: a residual that grows three iterations in a row, or far
+    // above the best one seen, restarts the subspace from the current vector.
+    growth = (out.residual > prev) ? growth + 1 : 0;
+    prev = out.residual;
+    best = std::min(best, out.residual);
+    const bool restart = use_diis && count > 0 && (growth >= 3 || out.residual > 1e3 * best);
+    if (restart) growth = 0;
     bool extrap = false;
     if (use_diis) {
-      for (int q = 0; q < nvalid; ++q) {
-        G[slot * m + q] = host[1 + q];
-        G[q * m + slot] = host[1 + q];
-      }
-      ++count;
-      if (nvalid >= 2) {
-        std::vector<double> c;
-        if (diis_weights(G, nvalid, m, c)) {
-          LN_TRY(lincomb(L.dx, N, nvalid, c.data(), o, v, t1, t2, s));
-          extrap = true;
-        } else {
-          count = 0;   // ill-conditioned space: restart it from this vector
-          std::fill(G.begin(), G.end(), 0.0);
-          if (slot != 0) {
-            LN_TRY(dcopy(L.dx, xs, N * 8, s));
-            LN_TRY(dcopy(L.de, es, N * 8, s));
+      if (restart) {
+        count = 0;
+        std::fill(G.begin(), G.end(), 0.0);
+        if (slot != 0) {
+          LN_TRY(dcopy(L.dx, xs, N * 8, s));
+          LN_TRY(dcopy(L.de, es, N * 8, s));
+        }
+        G[0] = host[1 + slot];
+        count = 1;
+      } else {
+        for (int q = 0; q < nvalid; ++q) {
+          G[slot * m + q] = host[1 + q];
+          G[q * m + slot] = host[1 + q];
+        }
+        ++count;
+        if (nvalid >= 2) {
+          std::vector<double> c;
+          if (diis_weights(G, nvalid, m, c)) {
+            LN_TRY(lincomb(L.dx, N, nvalid, c.data(), o, v, t1, t2, s));
+            extrap = true;
+          } else {
+            std::fill(G.begin(), G.end(), 0.0);   // ill-conditioned: restart from this vector
+            if (slot != 0) {
+              LN_TRY(dcopy(L.dx, xs, N * 8, s));
+              LN_TRY(dcopy(L.de, es, N * 8, s));
+            }
+            G[0] = host[1 + slot];
+            count = 1;
           }
-          G[0] = r2;
-          count = 1;
         }
       }
     }
     if (!extrap) LN_TRY(scatter_vec(xs, o, v, t1, t2, s));
+    if (log_enabled()) {   // energy of the new iterate, read back with the next Gram row
+      const int st2 = energy(L, t1, t2, L.scal, s);
+      if (st2) return st2;
+    }
   }
   int st = energy(L, t1, t2, L.scal, s);
   if (st) return st;
@@ -607,6 +647,11 @@ int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s) 
       SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), vo, ovo, 0));
       finish(d);
       LN_TRY(gett(d, s));
+    }
+    if (log_enabled() && (t0 / L.nb) % 8 == 0) {
+      std::fprintf(stderr, "lnocc: (T) triples %lld..%lld of %lld\n", (long long)t0,
+                   (long long)(t0 + nb), (long long)L.ntriples);
+      std::fflush(stderr);
     }
     int64_t nparts = 0;
     LN_TRY(triples_energy(L.W, wtype, table, nb, L.Kov, t1, in.eo, in.ev, o, v, L.tpart, &nparts, s));

@@ -45,7 +45,7 @@ class lnocc_options_t(C.Structure):
         ("max_iter", C.c_int32), ("diis_space", C.c_int32), ("diis_start", C.c_int32),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("ladder_chunk_bytes", C.c_size_t), ("triples_batch", C.c_int32),
-        ("reserved1", C.c_int32),
+        ("reserved1", C.c_int32), ("level_shift", C.c_double),
     ]
 
 
@@ -202,7 +202,8 @@ def make_fragment_struct(B, eps_occ, eps_vir, t1, t2, conv_tol: float) -> lnocc_
 
 def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int = 100,
                  diis_space: int = 8, diis_start: int = 2, guess: int = LNOCC_GUESS_MP2,
-                 ladder_chunk_bytes: int = 0, triples_batch: int = 0) -> lnocc_options_t:
+                 ladder_chunk_bytes: int = 0, triples_batch: int = 0,
+                 level_shift: float = 0.0) -> lnocc_options_t:
     opt = lnocc_default_options()
     opt.precision = PRECISIONS[precision]
     opt.do_triples = int(do_triples)
@@ -212,6 +213,7 @@ def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int
     opt.guess = guess
     opt.ladder_chunk_bytes = ladder_chunk_bytes
     opt.triples_batch = triples_batch
+    opt.level_shift = level_shift
     return opt
 
 
