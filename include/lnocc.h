@@ -95,9 +95,15 @@ typedef struct lnocc_options_t {
   size_t workspace_bytes;
   size_t ladder_chunk_bytes; /* cap on the (ac|bd) block formed at a time; 0 = 8 GiB */
   int32_t triples_batch;     /* unique (i<=j<=k) triples per (T) pass; 0 = automatic */
-  int32_t reserved1;
+  int32_t batch_slots;       /* lnocc_batch_solve: fragments in flight at once, each with its
+                                own workspace slice; 0 = 4 */
   double level_shift;        /* >= 0 (Hartree): amplitude steps R / (D - level_shift); the
                                 convergence test always uses the unshifted step R / D */
+  int32_t batch_streams;     /* lnocc_batch_solve: 0 = every fragment on opt->stream; n > 0 =
+                                spread the fragments in flight over n streams of default
+                                priority created for the call, so that small fragments run
+                                concurrently */
+  int32_t reserved2;
 } lnocc_options_t;
 
 /* Fills *opt with defaults: FP64, MP2 guess, triples on, max_iter 100,
@@ -107,9 +113,17 @@ void lnocc_default_options(lnocc_options_t *opt);
 /* Human-readable name of a status code; never NULL. */
 const char *lnocc_status_string(int status);
 
-/* Workspace bytes needed to solve the nfrag fragments of f (one at a time,
- * reusing the workspace) with *opt.  Writes 0 and returns LNOCC_EINVAL for bad
- * sizes; host-only, touches no device memory or pointer inside f. */
+/* What failed in the last call on this host thread that returned an error
+ * (the runtime call or check and its message); "" when the last call
+ * succeeded.  Never NULL; valid until the next call on this thread. */
+const char *lnocc_last_error(void);
+
+/* Workspace bytes for *opt.  nfrag == 1: what lnocc_fragment_ccsd needs for
+ * f[0].  nfrag > 1: what lnocc_batch_solve needs to keep min(nfrag,
+ * batch_slots) fragments of f in flight, i.e. that many slices each as large
+ * as the largest fragment's need (also enough for lnocc_fragment_ccsd on any
+ * of them).  Writes 0 and returns LNOCC_EINVAL for bad sizes; host-only,
+ * touches no device memory or pointer inside f. */
 int lnocc_workspace_bytes(const lnocc_fragment_t *f, int32_t nfrag,
                           const lnocc_options_t *opt, size_t *bytes);
 
@@ -136,9 +150,19 @@ int lnocc_ccsd_residuals(lnocc_fragment_t *f, const lnocc_options_t *opt,
                          double *r1, double *r2);
 
 /* Solves nfrag independent fragments (the sum over fragments of Eq. 8/13 needs
- * each one; fragments do not interact) with one workspace sized by
- * lnocc_workspace_bytes(f, nfrag, opt).  Per-fragment results are written to
- * f[k]; returns the most severe status (errors before warnings). */
+ * each one; fragments do not interact), each exactly as lnocc_fragment_ccsd
+ * would.  Fragments are taken largest first and up to batch_slots of them are
+ * in flight at once, each on its own slice of the workspace: the host advances
+ * whichever fragment's per-iteration readback has landed while the work
+ * already queued for the others keeps the device busy, so no device time is
+ * lost to host round trips.  With batch_streams = 0 all of it runs on
+ * opt->stream; otherwise slot q runs on stream q mod batch_streams of a set
+ * created for the call, whose work starts after what opt->stream holds at the
+ * call and which opt->stream waits for before the call returns.  Fewer fragments are in
+ * flight when the workspace holds fewer slices; none fits: LNOCC_ENOMEM.  A fragment that fails the host checks gets its status
+ * and is skipped.  Per-fragment results and statuses are written to f[k];
+ * returns the most severe status (errors before warnings).  Returns when all
+ * fragments are done. */
 int lnocc_batch_solve(lnocc_fragment_t *f, int32_t nfrag, const lnocc_options_t *opt);
 
 /* ---- building block -------------------------------------------------------

@@ -2,7 +2,13 @@
 // the solver of solver.hip on the caller's stream and workspace.
 #include <cmath>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <memory>
+#include <numeric>
+#include <thread>
 #include <vector>
 
 #include "../../include/lnocc.h"
@@ -30,7 +36,8 @@ int check_options(const lnocc_options_t *opt) {
     return LNOCC_EINVAL;
   if (opt->guess != LNOCC_GUESS_MP2 && opt->guess != LNOCC_GUESS_USER) return LNOCC_EINVAL;
   if (opt->max_iter < 0 || opt->diis_space < 1 || opt->diis_space > 16 || opt->diis_start < 1 ||
-      opt->triples_batch < 0 || !(opt->level_shift >= 0.0) || !std::isfinite(opt->level_shift))
+      opt->triples_batch < 0 || opt->batch_slots < 0 || opt->batch_streams < 0 ||
+      opt->batch_streams > 64 || !(opt->level_shift >= 0.0) || !std::isfinite(opt->level_shift))
     return LNOCC_EINVAL;
   return LNOCC_OK;
 }
@@ -110,6 +117,79 @@ int finish(lnocc_fragment_t *f, int st) {
   return st;
 }
 
+// ------------------------------------------------------------------ batch
+constexpr int kDefaultBatchSlots = 4;
+
+int batch_slots(int nfrag, const lnocc_options_t *opt) {
+  const int want = opt->batch_slots > 0 ? opt->batch_slots : kDefaultBatchSlots;
+  return std::max(1, std::min(nfrag, want));
+}
+
+size_t round_up(size_t n, size_t a) { return (n + a - 1) / a * a; }
+
+// Work of one fragment used to order the batch (largest first): the ladder of
+// about twenty iterations plus (T).
+double fragment_cost(const lnocc_fragment_t *f) {
+  const double o = f->nocc, v = f->nvir, X = f->naux;
+  return 20.0 * (X * v * v * v * v + o * o * v * v * v * v) + 2.0 * o * o * o * v * v * v * v;
+}
+
+int worse(int a, int b) {
+  if (a < 0 || b < 0) return std::min(a, b);
+  return std::max(a, b);
+}
+
+// One fragment in flight: its slice of the workspace, its readback buffer
+// and the state machine of its solve.
+struct Slot {
+  enum class Stage { Empty, Begin, Iterate, Final, Triples };
+  Stage stage = Stage::Empty;
+  int frag = -1;
+  hipStream_t s = nullptr;
+  char *base = nullptr;
+  Layout L;
+  Readback rb;
+  std::unique_ptr<CcsdRun> run;
+};
+
+// Advances the solve in slot q after its last readback landed.  Returns a
+// status < 0 on failure, 1 when the fragment is finished, 0 when more device
+// work was enqueued.
+int advance(Slot &q, const lnocc_options_t *opt) {
+  CcsdRun &r = *q.run;
+  int st = LNOCC_OK;
+  switch (q.stage) {
+    case Slot::Stage::Begin:
+      r.after_begin();
+      if (r.phase == CcsdRun::Phase::Converged) {
+        st = r.enqueue_final();
+        q.stage = Slot::Stage::Final;
+      } else {
+        st = r.enqueue_iteration();
+        q.stage = Slot::Stage::Iterate;
+      }
+      return st;
+    case Slot::Stage::Iterate:
+      st = r.after_iteration();
+      if (st) return st;
+      if (r.phase == CcsdRun::Phase::Converged || r.phase == CcsdRun::Phase::Exhausted) {
+        q.stage = Slot::Stage::Final;
+        return r.enqueue_final();
+      }
+      return r.enqueue_iteration();
+    case Slot::Stage::Final:
+      st = r.after_final();
+      if (st < 0 || !opt->do_triples) return st < 0 ? st : 1;
+      q.stage = Slot::Stage::Triples;
+      return r.enqueue_t();
+    case Slot::Stage::Triples:
+      st = r.after_t();
+      return st < 0 ? st : 1;
+    default:
+      return LNOCC_EINVAL;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -151,11 +231,12 @@ int lnocc_workspace_bytes(const lnocc_fragment_t *f, int32_t nfrag, const lnocc_
     plan_layout(dims_of(&f[k]), *opt, nullptr, L);
     need = std::max(need, L.bytes);
   }
-  *bytes = need;
+  *bytes = (nfrag == 1) ? need : round_up(need, 256) * batch_slots(nfrag, opt);
   return LNOCC_OK;
 }
 
 int lnocc_fragment_ccsd(lnocc_fragment_t *f, const lnocc_options_t *opt) {
+  clear_error();
   Layout L;
   int st = prepare(f, opt, opt && opt->guess == LNOCC_GUESS_USER, true, L);
   if (st) return finish(f, st);
@@ -163,9 +244,8 @@ int lnocc_fragment_ccsd(lnocc_fragment_t *f, const lnocc_options_t *opt) {
   Guard guard(f, opt, L);
   Inputs in{f->B, f->eps_occ, f->eps_vir, f->t1 ? f->t1 : L.t1w, f->t2 ? f->t2 : L.t2w,
             f->conv_tol};
-  st = setup_fragment(L, f->B, f->eps_occ, f->eps_vir, true, s);
   Outputs out;
-  if (!st) st = run_ccsd(L, in, *opt, out, s);
+  st = run_ccsd(L, in, *opt, out, s);
   if (st >= 0 && opt->do_triples) {
     const int st2 = run_triples(L, in, out, s);
     if (st2 < 0) st = st2;
@@ -180,6 +260,7 @@ int lnocc_fragment_ccsd(lnocc_fragment_t *f, const lnocc_options_t *opt) {
 }
 
 int lnocc_fragment_triples(lnocc_fragment_t *f, const lnocc_options_t *opt) {
+  clear_error();
   Layout L;
   int st = prepare(f, opt, true, false, L);
   if (st) return finish(f, st);
@@ -195,6 +276,7 @@ int lnocc_fragment_triples(lnocc_fragment_t *f, const lnocc_options_t *opt) {
 }
 
 int lnocc_ccsd_residuals(lnocc_fragment_t *f, const lnocc_options_t *opt, double *r1, double *r2) {
+  clear_error();
   Layout L;
   int st = prepare(f, opt, true, false, L);
   if (!st && (!r1 || !r2)) st = LNOCC_EINVAL;
@@ -214,15 +296,151 @@ int lnocc_ccsd_residuals(lnocc_fragment_t *f, const lnocc_options_t *opt, double
 }
 
 int lnocc_batch_solve(lnocc_fragment_t *f, int32_t nfrag, const lnocc_options_t *opt) {
+  clear_error();
   if (!f || nfrag <= 0) return LNOCC_EINVAL;
+  int st = check_options(opt);
+  if (st) return st;
+  hipStream_t caller = (hipStream_t)opt->stream;
+  // host-side checks of every fragment; a rejected fragment keeps its status
+  size_t slot_bytes = 0;
+  std::vector<int> order;
   int worst = LNOCC_OK;
   for (int k = 0; k < nfrag; ++k) {
-    const int st = lnocc_fragment_ccsd(&f[k], opt);
-    if (st < 0) worst = (worst < 0) ? std::min(worst, st) : st;
-    else if (worst >= 0) worst = std::max(worst, st);
+    lnocc_fragment_t *g = &f[k];
+    st = check_sizes(g);
+    if (!st) st = check_pointers(g, opt->guess == LNOCC_GUESS_USER);
+    if (!st && !(g->conv_tol > 0.0 && std::isfinite(g->conv_tol))) st = LNOCC_EINVAL;
+    if (!st) st = check_spectrum(g, caller);
+    if (st) {
+      worst = worse(worst, finish(g, st));
+      continue;
+    }
+    Layout L;
+    plan_layout(dims_of(g), *opt, nullptr, L);
+    slot_bytes = std::max(slot_bytes, round_up(L.bytes, 256));
+    order.push_back(k);
+  }
+  if (order.empty()) return worst;
+  if (!opt->workspace) return LNOCC_ENOMEM;
+  if (((uintptr_t)opt->workspace) % 256) return LNOCC_EINVAL;
+  const int nslots = (int)std::min<size_t>(batch_slots((int)order.size(), opt),
+                                           opt->workspace_bytes / slot_bytes);
+  if (nslots < 1) {
+    for (int k : order) worst = worse(worst, finish(&f[k], LNOCC_ENOMEM));
+    return worst;
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return fragment_cost(&f[a]) > fragment_cost(&f[b]); });
+
+  // address guard over the workspace and every fragment's arrays
+  std::vector<Region> regions{Region{opt->workspace, opt->workspace_bytes}};
+  for (int k : order) {
+    const size_t o = f[k].nocc, v = f[k].nvir, X = f[k].naux, n = o + v;
+    regions.push_back(Region{f[k].B, X * n * n * 8});
+    regions.push_back(Region{f[k].eps_occ, o * 8});
+    regions.push_back(Region{f[k].eps_vir, v * 8});
+    regions.push_back(Region{f[k].t1, f[k].t1 ? o * v * 8 : 0});
+    regions.push_back(Region{f[k].t2, f[k].t2 ? o * o * v * v * 8 : 0});
+  }
+  install_regions(regions.data(), (int)regions.size());
+
+  // Streams: the caller's, or a set created here (default priority) that
+  // starts after the caller's stream and is joined back into it at the end.
+  const int nstreams = std::min(opt->batch_streams, nslots);
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> joins;
+  bool dev_ok = true;
+  auto rt = [&](hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+      note_error("%s failed (%s)", what, hipGetErrorString(e));
+      dev_ok = false;
+    }
+    return e == hipSuccess;
+  };
+  if (nstreams > 0 && !dry_run()) {
+    for (int i = 0; i < nstreams && dev_ok; ++i) {
+      hipEvent_t e = nullptr;
+      if (rt(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate")) joins.push_back(e);
+    }
+    for (int i = 0; i < nstreams && dev_ok; ++i) {
+      hipStream_t h = nullptr;
+      if (rt(hipStreamCreateWithFlags(&h, hipStreamNonBlocking), "hipStreamCreate")) streams.push_back(h);
+    }
+    if (dev_ok && rt(hipEventRecord(joins[0], caller), "hipEventRecord"))
+      for (hipStream_t h : streams)
+        if (!rt(hipStreamWaitEvent(h, joins[0], 0), "hipStreamWaitEvent")) break;
+  }
+  std::vector<Slot> slots(nslots);
+  for (int q = 0; q < nslots; ++q) {
+    slots[q].base = (char *)opt->workspace + (size_t)q * slot_bytes;
+    slots[q].s = streams.empty() ? caller : streams[q % streams.size()];
+    dev_ok = dev_ok && slots[q].rb.ok();
+  }
+  size_t next = 0;
+  int active = 0;
+  auto retire = [&](Slot &q, int status) {
+    lnocc_fragment_t *g = &f[q.frag];
+    if (status < 0 && !dry_run()) (void)hipStreamSynchronize(q.s);
+    const Outputs &out = q.run->out;
+    g->e_mp2 = out.e_mp2;
+    g->e_ccsd = out.e_ccsd;
+    g->e_t = opt->do_triples ? out.e_t : 0.0;
+    g->residual = out.residual;
+    g->n_iter = out.n_iter;
+    if (status == 1) status = out.status;
+    worst = worse(worst, finish(g, status));
+    q.run.reset();
+    q.frag = -1;
+    q.stage = Slot::Stage::Empty;
+    --active;
+  };
+  while (dev_ok && (next < order.size() || active > 0)) {
+    bool progressed = false;
+    for (Slot &q : slots) {
+      if (q.stage == Slot::Stage::Empty) {
+        if (next >= order.size()) continue;
+        const int k = order[next++];
+        lnocc_fragment_t *g = &f[k];
+        plan_layout(dims_of(g), *opt, q.base, q.L);
+        Inputs in{g->B, g->eps_occ, g->eps_vir, g->t1 ? g->t1 : q.L.t1w,
+                  g->t2 ? g->t2 : q.L.t2w, g->conv_tol};
+        q.frag = k;
+        q.run.reset(new CcsdRun(q.L, in, *opt, q.s, q.rb));
+        ++active;
+        progressed = true;
+        st = q.run->begin();
+        if (st) retire(q, st);
+        else q.stage = Slot::Stage::Begin;
+        continue;
+      }
+      st = q.run->poll();
+      if (st == 0) continue;
+      progressed = true;
+      st = (st < 0) ? st : advance(q, opt);
+      if (st != 0) retire(q, st);
+    }
+    if (!progressed) std::this_thread::yield();
+  }
+  // join the created streams back into the caller's, then release them
+  for (size_t i = 0; i < streams.size(); ++i) {
+    if (i < joins.size() && hipEventRecord(joins[i], streams[i]) == hipSuccess)
+      (void)hipStreamWaitEvent(caller, joins[i], 0);
+  }
+  for (hipStream_t h : streams) {
+    (void)hipStreamSynchronize(h);
+    (void)hipStreamDestroy(h);
+  }
+  if (!joins.empty()) (void)hipStreamSynchronize(caller);
+  for (hipEvent_t e : joins) (void)hipEventDestroy(e);
+  install_regions(nullptr, 0);
+  install_splitk_scratch(nullptr, 0);
+  if (!dev_ok) {   // a stream, event or readback buffer could not be created: nothing ran
+    for (int k : order) worst = worse(worst, finish(&f[k], LNOCC_EDEVICE));
   }
   return worst;
 }
+
+const char *lnocc_last_error(void) { return last_error(); }
 
 void lnocc_set_validation_mode(int on) { set_dry_run(on != 0); }
 
@@ -235,6 +453,7 @@ void lnocc_profile_collect(lnocc_kernel_stats_t out[LNOCC_KERNEL_CLASSES]) {
 }
 
 int lnocc_contract(const lnocc_contract_t *c, void *stream) {
+  clear_error();
   if (!c || !c->c || c->nseg < 1 || c->nseg > 4 || c->M < 0 || c->N < 0 || c->Mi < 1 ||
       c->Ni < 1 || c->batch < 1 || c->nb1 < 1 || c->batch > 65535)
     return LNOCC_EINVAL;
@@ -259,8 +478,16 @@ int lnocc_contract(const lnocc_contract_t *c, void *stream) {
   d.prec = (Prec)c->precision;
   d.c_type = 0;
   hipStream_t s = (hipStream_t)stream;
-  if (gett(d, s) != hipSuccess) return LNOCC_EDEVICE;
-  if (dsync(s) != hipSuccess) return LNOCC_EDEVICE;
+  hipError_t e = gett(d, s);
+  if (e != hipSuccess) {
+    if (!last_error()[0]) note_error("contraction launch failed (%s)", hipGetErrorString(e));
+    return LNOCC_EDEVICE;
+  }
+  e = dsync(s);
+  if (e != hipSuccess) {
+    note_error("stream synchronization after the contraction failed (%s)", hipGetErrorString(e));
+    return LNOCC_EDEVICE;
+  }
   return LNOCC_OK;
 }
 

@@ -104,6 +104,14 @@ void install_regions(const Region *r, int n);   // n = 0 removes the list
 bool dry_run();
 void set_dry_run(bool on);
 
+// Description of the last failure noted on this host thread ("" when none
+// since clear_error()); printed to stderr as well when LNOCC_DEBUG is set.
+// clear_error() also clears the runtime's last-error state, which launch
+// checks read.
+void note_error(const char *fmt, ...);
+const char *last_error();
+void clear_error();
+
 // Enqueue on `stream`.  Returns hipSuccess or the launch error.
 hipError_t gett(const GemmDesc &d, hipStream_t stream);
 

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <type_traits>
 #include <vector>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 
@@ -475,14 +476,14 @@ void profile_collect(KindStats out[(int)Kind::Count]) {
   for (int k = 0; k < (int)Kind::Count; ++k) out[k] = KindStats{0, 0.0, 0.0};
   for (const Record &r : g_records) {
     float ms = 0.f;
-    hipEventSynchronize(r.stop);
-    hipEventElapsedTime(&ms, r.start, r.stop);
+    (void)hipEventSynchronize(r.stop);
+    (void)hipEventElapsedTime(&ms, r.start, r.stop);
     KindStats &k = out[(int)r.kind];
     k.launches += 1;
     k.ms += ms;
     k.flops += r.flops;
-    hipEventDestroy(r.start);
-    hipEventDestroy(r.stop);
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
   }
   g_records.clear();
 }
@@ -523,8 +524,25 @@ void launch(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stre
 
 thread_local double *g_splitk = nullptr;
 thread_local size_t g_splitk_elems = 0;
+thread_local char g_error[512] = "";
 
 }  // namespace
+
+void note_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_error, sizeof(g_error), fmt, ap);
+  va_end(ap);
+  if (std::getenv("LNOCC_DEBUG")) std::fprintf(stderr, "lnocc: %s\n", g_error);
+}
+const char *last_error() { return g_error; }
+void clear_error() {
+  g_error[0] = 0;
+  // The launch wrappers read hipGetLastError(), which also holds the error of
+  // any earlier runtime call of the process (say, an allocation failure that
+  // the caller recovered from); start every entry point with it cleared.
+  if (!g_dry) (void)hipGetLastError();
+}
 
 void install_splitk_scratch(double *p, size_t elems) {
   g_splitk = p;
@@ -593,10 +611,9 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   nsplit = (slices + sps - 1) / sps;
   if (nsplit > 1) d.splitk = g_splitk;
   if (!descriptor_ok(d, nsplit)) {
-    if (std::getenv("LNOCC_DEBUG"))
-      std::fprintf(stderr, "lnocc: contraction M=%d(%d) N=%d(%d) nseg=%d K0=%d(%d) batch=%d "
-                   "split=%d leaves its buffers; not launched\n", d.M, d.Mi, d.N, d.Ni, d.nseg,
-                   d.seg[0].K, d.seg[0].Ki, d.batch, nsplit);
+    note_error("contraction M=%d(%d) N=%d(%d) nseg=%d K0=%d(%d) batch=%d split=%d leaves its "
+               "buffers; not launched", d.M, d.Mi, d.N, d.Ni, d.nseg, d.seg[0].K, d.seg[0].Ki,
+               d.batch, nsplit);
     return hipErrorIllegalAddress;
   }
   if (g_dry) return hipSuccess;
@@ -605,7 +622,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   if (g_profile) {
     if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
       return hipErrorOutOfMemory;
-    hipEventRecord(ev[0], stream);
+    (void)hipEventRecord(ev[0], stream);
   }
   dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)d.batch, (unsigned)nsplit);
   if (small) launch<Small>(d, grid, tiles_m, sps, stream);
@@ -620,7 +637,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
     err = hipGetLastError();
   }
   if (g_profile) {
-    hipEventRecord(ev[1], stream);
+    (void)hipEventRecord(ev[1], stream);
     double flops = 0.0;
     for (int s = 0; s < d.nseg; ++s) flops += 2.0 * d.M * (double)d.N * d.seg[s].K;
     g_records.push_back(Record{d.kind, ev[0], ev[1], flops * d.batch});

@@ -52,6 +52,10 @@ hipError_t pack_t(const double *t2, int64_t o, int64_t v, void *Tsa, int type, h
 hipError_t convert(const double *in, int64_t n, void *out, int type, hipStream_t s);
 hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, double *R2, hipStream_t s);
 
+// table[3 n + {0,1,2}] <- (i, j, k) of the n-th unique triple i <= j <= k, not
+// all equal, in lexicographic order (o (o + 1) (o + 2) / 6 - o entries).
+hipError_t triples_table(int *table, int64_t o, hipStream_t s);
+
 // (T) energy of a batch of unique triples whose W tensors sit in W[nb][v][v][v].
 // table holds (i, j, k) per entry, i <= j <= k; partials[nb * tiles] per tile.
 // W element type: 0 double, 1 float

@@ -548,6 +548,26 @@ hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, double *R2, hip
                      o, v, R2);
   return hipGetLastError();
 }
+// Unique triples i <= j <= k (not all equal) in lexicographic order; one
+// thread, once per (T) computation.
+__global__ void k_triples_table(int *table, int o) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t n = 0;
+  for (int i = 0; i < o; ++i)
+    for (int j = i; j < o; ++j)
+      for (int k = j; k < o; ++k)
+        if (!(i == j && j == k)) {
+          table[3 * n] = i;
+          table[3 * n + 1] = j;
+          table[3 * n + 2] = k;
+          ++n;
+        }
+}
+hipError_t triples_table(int *table, int64_t o, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  hipLaunchKernelGGL(k_triples_table, dim3(1), dim3(64), 0, s, table, (int)o);
+  return hipGetLastError();
+}
 hipError_t triples_energy(const void *W, int wtype, const int *table, int nb, const double *Kov,
                           const double *t1, const double *eo, const double *ev, int64_t o,
                           int64_t v, double *partials, int64_t *nparts, hipStream_t s) {

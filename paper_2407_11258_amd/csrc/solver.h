@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <cmath>
+#include <vector>
 
 #include "../../include/lnocc.h"
 #include "gett.h"
@@ -86,5 +88,57 @@ int energy(const Layout &L, const double *t1, const double *t2, double *dev_out,
 int run_ccsd(const Layout &L, const Inputs &in, const lnocc_options_t &opt, Outputs &out,
              hipStream_t s);
 int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s);
+int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s);
+
+// Pinned host buffer for the small readbacks of one solve ([0] energy,
+// [1..16] DIIS overlaps, [32] step norm, [40] (T) energy) and the event that
+// marks their arrival.  Owned by the caller of CcsdRun; reused across solves.
+struct Readback {
+  double *host = nullptr;
+  hipEvent_t ev = nullptr;
+  Readback();
+  ~Readback();
+  Readback(const Readback &) = delete;
+  Readback &operator=(const Readback &) = delete;
+  bool ok() const;
+};
+
+// CCSD of one fragment as a resumable state machine: each enqueue_* call
+// queues device work and one readback, poll() reports whether that readback
+// has landed, and after_* consumes it.  The batch driver interleaves several
+// of these on one stream, so the host round trip of one fragment overlaps the
+// device work of the others.
+struct CcsdRun {
+  enum class Phase { Idle, Started, Iterating, Converged, Exhausted };
+  const Layout *L;
+  Inputs in;
+  lnocc_options_t opt;
+  hipStream_t s;
+  Readback *rb;
+  double *host;
+  Outputs out;
+  Phase phase = Phase::Idle;
+  std::vector<double> G;       // DIIS Gram matrix (host, FP64)
+  int it = 0, count = 0, growth = 0, slot = 0, nvalid = 1;
+  bool use_diis = false;
+  double prev = INFINITY, best = INFINITY;
+  mutable int polls = 0;
+
+  CcsdRun(const Layout &L, const Inputs &in, const lnocc_options_t &opt, hipStream_t s,
+          Readback &rb);
+  int poll() const;            // 1 landed, 0 pending, < 0 error
+  hipError_t wait() const;
+  int begin();
+  int after_begin();
+  int enqueue_iteration();
+  int after_iteration();
+  int enqueue_final();
+  int after_final();
+  int enqueue_t();             // (T) on the converged amplitudes, E_(T) read back
+  int after_t();
+
+ private:
+  hipError_t mark();
+};
 
 }  // namespace lnocc

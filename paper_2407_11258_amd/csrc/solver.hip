@@ -27,9 +27,8 @@ namespace lnocc {
   do {                                                                    \
     hipError_t e_ = (x);                                                  \
     if (e_ != hipSuccess) {                                               \
-      if (std::getenv("LNOCC_DEBUG"))                                     \
-        std::fprintf(stderr, "lnocc: %s failed (%s) at %s:%d\n", #x,      \
-                     hipGetErrorString(e_), __FILE__, __LINE__);         \
+      note_error("%s failed (%s) at %s:%d", #x, hipGetErrorString(e_),    \
+                 __FILE__, __LINE__);                                     \
       return LNOCC_EDEVICE;                                               \
     }                                                                     \
   } while (0)
@@ -458,134 +457,248 @@ bool diis_weights(const std::vector<double> &G, int m, int ld, std::vector<doubl
 }
 }  // namespace
 
-int run_ccsd(const Layout &L, const Inputs &in, const lnocc_options_t &opt, Outputs &out,
-             hipStream_t s) {
-  const int64_t o = L.dm.o, v = L.dm.v, N = L.namp;
-  double *t1 = in.t1, *t2 = in.t2;
-  double host[64];
+// ---------------------------------------------------------------- CCSD driver
+// The readback buffer is pinned so that copies stay asynchronous and the host
+// can work on other fragments while one is in flight.
+Readback::Readback() {
+  if (dry_run()) {
+    host = (double *)std::calloc(64, sizeof(double));
+    return;
+  }
+  if (hipHostMalloc((void **)&host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    note_error("hipHostMalloc of a readback buffer failed");
+    host = nullptr;
+  }
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    note_error("hipEventCreate failed");
+    ev = nullptr;
+  }
+}
+
+Readback::~Readback() {
+  if (dry_run()) {
+    std::free(host);
+    return;
+  }
+  if (host) (void)hipHostFree(host);
+  if (ev) (void)hipEventDestroy(ev);
+}
+
+bool Readback::ok() const { return host != nullptr && (dry_run() || ev != nullptr); }
+
+CcsdRun::CcsdRun(const Layout &L_, const Inputs &in_, const lnocc_options_t &opt_, hipStream_t s_,
+                 Readback &rb_)
+    : L(&L_), in(in_), opt(opt_), s(s_), rb(&rb_), host(rb_.host),
+      G((size_t)L_.diis_m * L_.diis_m, 0.0) {}
+
+hipError_t CcsdRun::mark() { return dry_run() ? hipSuccess : hipEventRecord(rb->ev, s); }
+
+int CcsdRun::poll() const {
+  if (dry_run()) return (++polls % 3 == 0) ? 1 : 0;   // exercises the pending state
+  const hipError_t e = hipEventQuery(rb->ev);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  note_error("hipEventQuery failed (%s)", hipGetErrorString(e));
+  return LNOCC_EDEVICE;
+}
+
+hipError_t CcsdRun::wait() const { return dry_run() ? hipSuccess : hipEventSynchronize(rb->ev); }
+
+int CcsdRun::begin() {
+  install_splitk_scratch(L->splitk, (size_t)L->splitk_elems);
+  const int64_t o = L->dm.o, v = L->dm.v;
+  int st = setup_fragment(*L, in.B, in.eo, in.ev, true, s);
+  if (st) return st;
   // MP2 energy (always from the MP1 amplitudes) and the starting point
   if (opt.guess == LNOCC_GUESS_MP2) {
-    LN_TRY(mp2_guess(L.Kov, in.eo, in.ev, o, v, t1, t2, s));
-    int st = energy(L, t1, t2, L.scal, s);
-    if (st) return st;
+    LN_TRY(mp2_guess(L->Kov, in.eo, in.ev, o, v, in.t1, in.t2, s));
+    st = energy(*L, in.t1, in.t2, L->scal, s);
   } else {
-    LN_TRY(mp2_guess(L.Kov, in.eo, in.ev, o, v, L.R1, L.R2, s));
-    int st = energy(L, L.R1, L.R2, L.scal, s);
-    if (st) return st;
+    LN_TRY(mp2_guess(L->Kov, in.eo, in.ev, o, v, L->R1, L->R2, s));
+    st = energy(*L, L->R1, L->R2, L->scal, s);
   }
-  LN_TRY(d2h(host, L.scal, 8, s));
-  LN_TRY(dsync(s));
+  if (st) return st;
+  LN_TRY(d2h(host, L->scal, 8, s));
+  LN_TRY(mark());
+  phase = Phase::Started;
+  return LNOCC_OK;
+}
+
+int CcsdRun::enqueue_iteration() {
+  install_splitk_scratch(L->splitk, (size_t)L->splitk_elems);
+  const int64_t o = L->dm.o, v = L->dm.v, N = L->namp;
+  ++it;
+  int st = ccsd_residuals(*L, in.t1, in.t2, s);
+  if (st) return st;
+  const int m = L->diis_m;
+  use_diis = (m > 1) && (it >= opt.diis_start);
+  slot = use_diis ? (count % m) : 0;
+  double *xs = L->dx + (int64_t)slot * N, *es = L->de + (int64_t)slot * N;
+  double *rnorm = L->scal + 32;   // ||R / D||^2 of the current iterate
+  LN_TRY(jacobi_step(in.t1, in.t2, L->R1, L->R2, in.eo, in.ev, o, v, opt.level_shift, xs, es,
+                     L->partials + 16 * kRedBlocks, s));
+  LN_TRY(reduce_partials(L->partials + 16 * kRedBlocks, kRedBlocks, rnorm, 0, s));
+  nvalid = use_diis ? std::min(count + 1, m) : 1;
+  const double *ebase = use_diis ? L->de : es;
+  LN_TRY(dot_partials(ebase, N, nvalid, es, N, L->partials, s));
+  LN_TRY(reduce_rows(L->partials, nvalid, L->scal + 1, s));
+  LN_TRY(d2h(host, L->scal, 40 * 8, s));
+  LN_TRY(mark());
+  phase = Phase::Iterating;
+  return LNOCC_OK;
+}
+
+// After the readback of an iteration: convergence test and DIIS; enqueues the
+// next iterate.  Returns OK, an error, or sets phase = Converged / Exhausted.
+int CcsdRun::after_iteration() {
+  install_splitk_scratch(L->splitk, (size_t)L->splitk_elems);
+  const int64_t o = L->dm.o, v = L->dm.v, N = L->namp;
+  const int m = L->diis_m;
+  double *xs = L->dx + (int64_t)slot * N, *es = L->de + (int64_t)slot * N;
+  const double r2 = host[32];
+  out.residual = std::sqrt(std::max(r2, 0.0));
+  out.n_iter = it;
+  if (log_enabled()) {
+    std::fprintf(stderr, "lnocc: iteration %d residual %.3e energy %.12f\n", it, out.residual,
+                 it > 1 ? host[0] : out.e_mp2);
+    std::fflush(stderr);
+  }
+  if (!std::isfinite(r2) || !std::isfinite(host[1 + (use_diis ? slot : 0)])) {
+    note_error("non-finite residual norm or DIIS overlap at iteration %d", it);
+    return LNOCC_ENUMERIC;
+  }
+  if (out.residual <= in.conv_tol) {
+    LN_TRY(scatter_vec(xs, o, v, in.t1, in.t2, s));
+    phase = Phase::Converged;
+    return LNOCC_OK;
+  }
+  // DIIS safeguard: a residual that grows three iterations in a row, or far
+  // above the best one seen, restarts the subspace from the current vector.
+  growth = (out.residual > prev) ? growth + 1 : 0;
+  prev = out.residual;
+  best = std::min(best, out.residual);
+  const bool restart = use_diis && count > 0 && (growth >= 3 || out.residual > 1e3 * best);
+  if (restart) growth = 0;
+  bool extrap = false;
+  if (use_diis) {
+    if (restart) {
+      std::fill(G.begin(), G.end(), 0.0);
+      if (slot != 0) {
+        LN_TRY(dcopy(L->dx, xs, N * 8, s));
+        LN_TRY(dcopy(L->de, es, N * 8, s));
+      }
+      G[0] = host[1 + slot];
+      count = 1;
+    } else {
+      for (int q = 0; q < nvalid; ++q) {
+        G[slot * m + q] = host[1 + q];
+        G[q * m + slot] = host[1 + q];
+      }
+      ++count;
+      if (nvalid >= 2) {
+        std::vector<double> c;
+        if (diis_weights(G, nvalid, m, c)) {
+          LN_TRY(lincomb(L->dx, N, nvalid, c.data(), o, v, in.t1, in.t2, s));
+          extrap = true;
+        } else {
+          std::fill(G.begin(), G.end(), 0.0);   // ill-conditioned: restart from this vector
+          if (slot != 0) {
+            LN_TRY(dcopy(L->dx, xs, N * 8, s));
+            LN_TRY(dcopy(L->de, es, N * 8, s));
+          }
+          G[0] = host[1 + slot];
+          count = 1;
+        }
+      }
+    }
+  }
+  if (!extrap) LN_TRY(scatter_vec(xs, o, v, in.t1, in.t2, s));
+  if (log_enabled()) {   // energy of the new iterate, read back with the next Gram row
+    const int st2 = energy(*L, in.t1, in.t2, L->scal, s);
+    if (st2) return st2;
+  }
+  if (it >= opt.max_iter) phase = Phase::Exhausted;
+  return LNOCC_OK;
+}
+
+int CcsdRun::enqueue_final() {
+  install_splitk_scratch(L->splitk, (size_t)L->splitk_elems);
+  const int st = energy(*L, in.t1, in.t2, L->scal, s);
+  if (st) return st;
+  LN_TRY(d2h(host, L->scal, 8, s));
+  LN_TRY(mark());
+  return LNOCC_OK;
+}
+
+int CcsdRun::after_final() {
+  out.e_ccsd = host[0];
+  if (!std::isfinite(out.e_ccsd)) {
+    note_error("non-finite CCSD energy");
+    return LNOCC_ENUMERIC;
+  }
+  out.status = (phase == Phase::Converged) ? LNOCC_OK : LNOCC_NOT_CONVERGED;
+  return out.status;
+}
+
+int CcsdRun::after_begin() {
   out.e_mp2 = host[0];
   out.n_iter = 0;
   out.residual = 0.0;
   out.status = LNOCC_OK;
+  if (opt.max_iter == 0) phase = Phase::Converged;
+  return LNOCC_OK;
+}
 
-  const int m = L.diis_m;
-  std::vector<double> G(m * m, 0.0);
-  int count = 0;         // vectors stored so far
-  int growth = 0;        // consecutive iterations with a growing residual
-  double prev = INFINITY, best = INFINITY;
-  bool converged = (opt.max_iter == 0);
-  double *rnorm = L.scal + 32;   // ||R / D||^2 of the current iterate
-  for (int it = 1; it <= opt.max_iter; ++it) {
-    int st = ccsd_residuals(L, t1, t2, s);
-    if (st) return st;
-    const bool use_diis = (m > 1) && (it >= opt.diis_start);
-    const int slot = use_diis ? (count % m) : 0;
-    double *xs = L.dx + (int64_t)slot * N, *es = L.de + (int64_t)slot * N;
-    LN_TRY(jacobi_step(t1, t2, L.R1, L.R2, in.eo, in.ev, o, v, opt.level_shift, xs, es,
-                       L.partials + 16 * kRedBlocks, s));
-    LN_TRY(reduce_partials(L.partials + 16 * kRedBlocks, kRedBlocks, rnorm, 0, s));
-    const int nvalid = use_diis ? std::min(count + 1, m) : 1;
-    const double *ebase = use_diis ? L.de : es;
-    LN_TRY(dot_partials(ebase, N, nvalid, es, N, L.partials, s));
-    LN_TRY(reduce_rows(L.partials, nvalid, L.scal + 1, s));
-    LN_TRY(d2h(host, L.scal, 40 * 8, s));
-    LN_TRY(dsync(s));
-    const double r2 = host[32];
-    out.residual = std::sqrt(std::max(r2, 0.0));
-    out.n_iter = it;
-    if (log_enabled()) {
-      std::fprintf(stderr, "lnocc: iteration %d residual %.3e energy %.12f\n", it, out.residual,
-                   it > 1 ? host[0] : out.e_mp2);
-      std::fflush(stderr);
-    }
-    if (!std::isfinite(r2) || !std::isfinite(host[1 + (use_diis ? slot : 0)])) return LNOCC_ENUMERIC;
-    if (out.residual <= in.conv_tol) {
-      LN_TRY(scatter_vec(xs, o, v, t1, t2, s));
-      converged = true;
-      break;
-    }
-    // DIIS safeguard: a residual that grows three iterations in a row, or far
-    // above the best one seen, restarts the subspace from the current vector.
-    growth = (out.residual > prev) ? growth + 1 : 0;
-    prev = out.residual;
-    best = std::min(best, out.residual);
-    const bool restart = use_diis && count > 0 && (growth >= 3 || out.residual > 1e3 * best);
-    if (restart) growth = 0;
-    bool extrap = false;
-    if (use_diis) {
-      if (restart) {
-        count = 0;
-        std::fill(G.begin(), G.end(), 0.0);
-        if (slot != 0) {
-          LN_TRY(dcopy(L.dx, xs, N * 8, s));
-          LN_TRY(dcopy(L.de, es, N * 8, s));
-        }
-        G[0] = host[1 + slot];
-        count = 1;
-      } else {
-        for (int q = 0; q < nvalid; ++q) {
-          G[slot * m + q] = host[1 + q];
-          G[q * m + slot] = host[1 + q];
-        }
-        ++count;
-        if (nvalid >= 2) {
-          std::vector<double> c;
-          if (diis_weights(G, nvalid, m, c)) {
-            LN_TRY(lincomb(L.dx, N, nvalid, c.data(), o, v, t1, t2, s));
-            extrap = true;
-          } else {
-            std::fill(G.begin(), G.end(), 0.0);   // ill-conditioned: restart from this vector
-            if (slot != 0) {
-              LN_TRY(dcopy(L.dx, xs, N * 8, s));
-              LN_TRY(dcopy(L.de, es, N * 8, s));
-            }
-            G[0] = host[1 + slot];
-            count = 1;
-          }
-        }
-      }
-    }
-    if (!extrap) LN_TRY(scatter_vec(xs, o, v, t1, t2, s));
-    if (log_enabled()) {   // energy of the new iterate, read back with the next Gram row
-      const int st2 = energy(L, t1, t2, L.scal, s);
-      if (st2) return st2;
-    }
-  }
-  int st = energy(L, t1, t2, L.scal, s);
+int CcsdRun::enqueue_t() {
+  const int st = enqueue_triples(*L, in, s);
   if (st) return st;
-  LN_TRY(d2h(host, L.scal, 8, s));
-  LN_TRY(dsync(s));
-  out.e_ccsd = host[0];
-  if (!std::isfinite(out.e_ccsd)) return LNOCC_ENUMERIC;
-  out.status = converged ? LNOCC_OK : LNOCC_NOT_CONVERGED;
-  return out.status;
+  LN_TRY(d2h(host + 40, L->scal + 40, 8, s));
+  LN_TRY(mark());
+  return LNOCC_OK;
+}
+
+int CcsdRun::after_t() {
+  out.e_t = host[40];
+  if (std::isfinite(out.e_t)) return LNOCC_OK;
+  note_error("non-finite (T) energy");
+  return LNOCC_ENUMERIC;
+}
+
+int run_ccsd(const Layout &L, const Inputs &in, const lnocc_options_t &opt, Outputs &out,
+             hipStream_t s) {
+  Readback rb;
+  if (!rb.ok()) return LNOCC_EDEVICE;
+  CcsdRun r(L, in, opt, s, rb);
+  int st = r.begin();
+  if (st) return st;
+  LN_TRY(r.wait());
+  r.after_begin();
+  while (r.phase != CcsdRun::Phase::Converged && r.phase != CcsdRun::Phase::Exhausted) {
+    st = r.enqueue_iteration();
+    if (st) return st;
+    LN_TRY(r.wait());
+    st = r.after_iteration();
+    if (st) { out = r.out; return st; }
+  }
+  st = r.enqueue_final();
+  if (st) return st;
+  LN_TRY(r.wait());
+  st = r.after_final();
+  out = r.out;
+  return st;
 }
 
 // ---------------------------------------------------------------- (T)
-int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s) {
+// Enqueues the whole (T) computation; the FP64 sum lands in L.scal[40].
+int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s) {
+  install_splitk_scratch(L.splitk, (size_t)L.splitk_elems);
   const int64_t o = L.dm.o, v = L.dm.v, X = L.dm.X;
   const int64_t ov = o * v, oo = o * o, vv = v * v, ovv = o * vv, vvv = vv * v;
   const int64_t ovo = ov * o, vo = v * o;
   const double *t1 = in.t1, *t2 = in.t2;
   double *acc = L.scal + 40;
   LN_TRY(dzero(acc, 8, s));
-  if (L.ntriples == 0) {
-    out.e_t = 0.0;
-    LN_TRY(dsync(s));
-    return LNOCC_OK;
-  }
+  if (L.ntriples == 0) return LNOCC_OK;
   // In the FP32 / BF16 modes the integrals and amplitudes entering W are
   // stored in that precision and W itself in FP32; the energy sum is FP64.
   {  // Gt[i][a][b][d] = (ai|bd)
@@ -606,13 +719,7 @@ int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s) 
     t2w = L.t2_lp;
   }
   const int wtype = L.lp == Prec::F64 ? 0 : 1;
-  std::vector<int> tab;
-  tab.reserve(3 * L.ntriples);
-  for (int i = 0; i < o; ++i)
-    for (int j = i; j < o; ++j)
-      for (int k = j; k < o; ++k)
-        if (!(i == j && j == k)) { tab.push_back(i); tab.push_back(j); tab.push_back(k); }
-  LN_TRY(h2d(L.table, tab.data(), tab.size() * sizeof(int), s));
+  LN_TRY(triples_table(L.table, o, s));
   for (int64_t t0 = 0; t0 < L.ntriples; t0 += L.nb) {
     const int nb = (int)std::min<int64_t>(L.nb, L.ntriples - t0);
     const int *table = L.table + 3 * t0;
@@ -657,11 +764,25 @@ int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s) 
     LN_TRY(triples_energy(L.W, wtype, table, nb, L.Kov, t1, in.eo, in.ev, o, v, L.tpart, &nparts, s));
     LN_TRY(reduce_partials(L.tpart, nparts, acc, 1, s));
   }
-  double host = 0.0;
-  LN_TRY(d2h(&host, acc, 8, s));
-  LN_TRY(dsync(s));
-  out.e_t = host;
-  if (!std::isfinite(host)) return LNOCC_ENUMERIC;
+  return LNOCC_OK;
+}
+
+int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s) {
+  int st = enqueue_triples(L, in, s);
+  if (st) return st;
+  double *host = nullptr;
+  if (dry_run()) {
+    out.e_t = 0.0;
+    return LNOCC_OK;
+  }
+  if (hipHostMalloc((void **)&host, sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return LNOCC_EDEVICE;
+  hipError_t e = d2h(host, L.scal + 40, 8, s);
+  if (e == hipSuccess) e = dsync(s);
+  out.e_t = *host;
+  (void)hipHostFree(host);
+  if (e != hipSuccess) return LNOCC_EDEVICE;
+  if (!std::isfinite(out.e_t)) return LNOCC_ENUMERIC;
   return LNOCC_OK;
 }
 

@@ -45,7 +45,8 @@ class lnocc_options_t(C.Structure):
         ("max_iter", C.c_int32), ("diis_space", C.c_int32), ("diis_start", C.c_int32),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("ladder_chunk_bytes", C.c_size_t), ("triples_batch", C.c_int32),
-        ("reserved1", C.c_int32), ("level_shift", C.c_double),
+        ("batch_slots", C.c_int32), ("level_shift", C.c_double),
+        ("batch_streams", C.c_int32), ("reserved2", C.c_int32),
     ]
 
 
@@ -74,7 +75,8 @@ class lnocc_kernel_stats_t(C.Structure):
 LNOCC_KERNEL_CLASSES = 4
 KERNEL_CLASS_NAMES = ("other", "ladder_build", "ladder_contract", "triples_w")
 
-EXPORTS = ("lnocc_default_options", "lnocc_status_string", "lnocc_workspace_bytes",
+EXPORTS = ("lnocc_default_options", "lnocc_status_string", "lnocc_last_error",
+           "lnocc_workspace_bytes",
            "lnocc_fragment_ccsd", "lnocc_fragment_triples", "lnocc_ccsd_residuals",
            "lnocc_batch_solve", "lnocc_contract", "lnocc_profile_enable",
            "lnocc_profile_collect", "lnocc_set_validation_mode")
@@ -84,12 +86,19 @@ def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
     p = pathlib.Path(path) if path else _LIB_PATH
     if not p.exists():
         raise RuntimeError(f"liblnocc not built ({p}); run paper_2407_11258_amd.build_lib.build()")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 (same
+    # soname as the system one liblnocc links).  Loading torch first makes the
+    # library bind to that runtime; loading liblnocc first would bring in a
+    # second runtime, which then finds no device once torch owns it.
+    import torch  # noqa: F401
     lib = C.CDLL(str(p))
     FP, OP = C.POINTER(lnocc_fragment_t), C.POINTER(lnocc_options_t)
     lib.lnocc_default_options.argtypes = [OP]
     lib.lnocc_default_options.restype = None
     lib.lnocc_status_string.argtypes = [C.c_int]
     lib.lnocc_status_string.restype = C.c_char_p
+    lib.lnocc_last_error.argtypes = []
+    lib.lnocc_last_error.restype = C.c_char_p
     lib.lnocc_workspace_bytes.argtypes = [FP, C.c_int32, OP, C.POINTER(C.c_size_t)]
     lib.lnocc_workspace_bytes.restype = C.c_int
     for name in ("lnocc_fragment_ccsd", "lnocc_fragment_triples"):
@@ -122,6 +131,10 @@ def lnocc_default_options() -> lnocc_options_t:
 
 def lnocc_status_string(status: int) -> str:
     return _lib.lnocc_status_string(int(status)).decode()
+
+
+def lnocc_last_error() -> str:
+    return _lib.lnocc_last_error().decode()
 
 
 def lnocc_workspace_bytes(frags, opt: lnocc_options_t) -> tuple[int, int]:
@@ -203,7 +216,8 @@ def make_fragment_struct(B, eps_occ, eps_vir, t1, t2, conv_tol: float) -> lnocc_
 def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int = 100,
                  diis_space: int = 8, diis_start: int = 2, guess: int = LNOCC_GUESS_MP2,
                  ladder_chunk_bytes: int = 0, triples_batch: int = 0,
-                 level_shift: float = 0.0) -> lnocc_options_t:
+                 level_shift: float = 0.0, batch_slots: int = 0,
+                 batch_streams: int = 0) -> lnocc_options_t:
     opt = lnocc_default_options()
     opt.precision = PRECISIONS[precision]
     opt.do_triples = int(do_triples)
@@ -214,6 +228,8 @@ def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int
     opt.ladder_chunk_bytes = ladder_chunk_bytes
     opt.triples_batch = triples_batch
     opt.level_shift = level_shift
+    opt.batch_slots = batch_slots
+    opt.batch_streams = batch_streams
     return opt
 
 
@@ -256,3 +272,23 @@ def solve(B, eps_occ, eps_vir, *, conv_tol=1e-8, t1=None, t2=None, workspace=Non
     ws.attach([f], opt)
     st = lnocc_fragment_ccsd(f, opt)
     return Result(st, f.e_mp2, f.e_ccsd, f.e_t, f.n_iter, f.residual, t1, t2)
+
+
+def solve_batch(fragments, *, conv_tol=1e-8, workspace=None, **kw) -> list[Result]:
+    """lnocc_batch_solve over [(B, eps_occ, eps_vir), ...] device tensors (FP64).
+    Allocates the amplitudes; returns one Result per fragment, in input order."""
+    torch = _torch()
+    amps = []
+    arr = (lnocc_fragment_t * len(fragments))()
+    for k, (B, eo, ev) in enumerate(fragments):
+        o, v = eo.numel(), ev.numel()
+        t1 = torch.empty((o, v), dtype=torch.float64, device=B.device)
+        t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=B.device)
+        amps.append((t1, t2))
+        arr[k] = make_fragment_struct(B, eo, ev, t1, t2, conv_tol)
+    opt = make_options(**kw)
+    ws = workspace or Workspace(fragments[0][0].device)
+    ws.attach(list(arr), opt)
+    lnocc_batch_solve(arr, opt)
+    return [Result(arr[k].status, arr[k].e_mp2, arr[k].e_ccsd, arr[k].e_t, arr[k].n_iter,
+                   arr[k].residual, *amps[k]) for k in range(len(fragments))]

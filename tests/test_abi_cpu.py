@@ -140,6 +140,63 @@ def test_small_ladder_blocks_and_triple_batches(validation_mode):
     assert L.lnocc_fragment_ccsd(f, opt) == L.LNOCC_OK
 
 
+def _batch(shapes):
+    arr = (L.lnocc_fragment_t * len(shapes))()
+    for k, (o, v, X) in enumerate(shapes):
+        arr[k] = _fake_fragment(o, v, X)
+    return arr
+
+
+@pytest.mark.parametrize("streams", [1, 3, 0])
+def test_batch_schedule_stays_in_bounds(validation_mode, streams):
+    shapes = [s[:3] for s in batch_shapes()[:7]] + [(1, 1, 1)]
+    arr = _batch(shapes)
+    opt = L.make_options(precision="fp32", batch_slots=streams, batch_streams=2)
+    st, nbytes = L.lnocc_workspace_bytes(arr, opt)
+    assert st == L.LNOCC_OK
+    single = max(L.lnocc_workspace_bytes([arr[k]], opt)[1] for k in range(len(arr)))
+    slots = min(len(arr), streams or 4)
+    assert nbytes >= slots * single
+    opt.workspace, opt.workspace_bytes = 1 << 45, nbytes
+    assert L.lnocc_batch_solve(arr, opt) == L.LNOCC_OK
+    assert all(arr[k].status == L.LNOCC_OK for k in range(len(arr)))
+    # a workspace of one slice runs the fragments one at a time
+    opt.workspace_bytes = single + 255
+    assert L.lnocc_batch_solve(arr, opt) == L.LNOCC_OK
+
+
+def test_batch_errors_are_per_fragment(validation_mode):
+    arr = _batch([(4, 20, 72), (3, 15, 40), (2, 9, 30)])
+    arr[1].conv_tol = 0.0                       # rejected on the host
+    opt = L.make_options(batch_slots=2)
+    st, nbytes = L.lnocc_workspace_bytes(arr, opt)
+    opt.workspace, opt.workspace_bytes = 1 << 45, nbytes
+    assert L.lnocc_batch_solve(arr, opt) == L.LNOCC_EINVAL
+    assert [arr[k].status for k in range(3)] == [L.LNOCC_OK, L.LNOCC_EINVAL, L.LNOCC_OK]
+    arr[1].conv_tol = 1e-8
+    opt.workspace_bytes = 1024                  # no slice fits
+    assert L.lnocc_batch_solve(arr, opt) == L.LNOCC_ENOMEM
+    assert all(arr[k].status == L.LNOCC_ENOMEM for k in range(3))
+    assert L._lib.lnocc_batch_solve(arr, 0, C.byref(opt)) == L.LNOCC_EINVAL
+
+
+def test_one_hip_runtime_in_the_process():
+    """The binding loads torch first, so liblnocc binds to torch's HIP runtime
+    instead of mapping a second one (which would find no device)."""
+    maps = pathlib.Path("/proc/self/maps").read_text().splitlines()
+    hip = {ln.split()[-1] for ln in maps if "libamdhip64" in ln}
+    hsa = {ln.split()[-1] for ln in maps if "libhsa-runtime64" in ln}
+    assert len(hip) == 1 and len(hsa) == 1, (hip, hsa)
+
+
+def test_options_are_checked():
+    f = _fake_fragment(2, 5, 9)
+    for field, bad in (("batch_streams", -1), ("batch_streams", 65), ("batch_slots", -2)):
+        opt = L.make_options()
+        setattr(opt, field, bad)
+        assert L.lnocc_workspace_bytes([f], opt)[0] == L.LNOCC_EINVAL, field
+
+
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(RuntimeError):
         L.load_library(tmp_path / "nope.so")

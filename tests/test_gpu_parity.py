@@ -69,7 +69,7 @@ def _contract(M, Mi, N, Ni, c, cstr, segs, beta=0.0, batch=1, nb1=1, cb=(0, 0, 0
     d.precision = precision
     st = L.lnocc_contract(d, torch.cuda.current_stream().cuda_stream)
     _KEEP.clear()
-    assert st == L.LNOCC_OK, L.lnocc_status_string(st)
+    assert st == L.LNOCC_OK, f"{L.lnocc_status_string(st)}: {L.lnocc_last_error()}"
 
 
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (130, 70, 37), (257, 129, 200), (64, 300, 5)])
@@ -166,6 +166,8 @@ def _call(fn, f, B, eo, ev, t1, t2, conv_tol=1e-8, **kw):
     ws = L.Workspace(DEV)
     ws.attach([fs], opt)
     st = fn(fs, opt)
+    if st < 0:
+        say(f"  status {st}: {L.lnocc_last_error()}")
     return st, fs
 
 
@@ -271,8 +273,9 @@ def test_realistic_fragment_against_stored_oracle(precision, tol_e):
     B, eo, ev = _fragment_on_device(f)
     t1 = torch.empty((o, v), dtype=torch.float64, device=DEV)
     t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=DEV)
-    st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=g["conv_tol"],
-                   precision=precision)
+    # FP32 ladder and (T) products leave a residual floor near 1e-9: converge to 1e-8
+    tol = g["conv_tol"] if precision == "fp64" else 1e-8
+    st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=tol, precision=precision)
     say(f"  dE_mp2={fs.e_mp2 - g['e_mp2']:.2e} dE_ccsd={fs.e_ccsd - g['e_ccsd']:.2e} "
         f"dE_t={fs.e_t - g['e_t']:.2e} iters={fs.n_iter} (oracle {g['n_iter']})")
     assert st == L.LNOCC_OK
