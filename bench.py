@@ -4,7 +4,13 @@
 One step = one complete fragment solve through the C ABI
 (lnocc_fragment_ccsd: DF split, MP2 guess, CCSD iterations to the residual
 threshold, then (T)) on the realistic synthetic fragment (nocc=16, nvir=160,
-naux=528, seed 1).  Inputs are resident in HBM before the timed region.
+naux=528, seed 1), in the mixed mode (ladder and (T) products in FP32 on the
+matrix cores, everything else FP64) and, for comparison, in plain FP64.
+Inputs are resident in HBM before the timed region.
+
+--workload batch instead solves the 64 uneven fragments of the batch workload
+with lnocc_batch_solve (one step = the whole batch) and, with --compare-fp64,
+the same 64 fragments one at a time in FP64.
 
 Prints one JSON line with solves/s, the (T) contraction rate, the roofline
 position of the dominant contraction kernel (timed with HIP events on its own
@@ -28,7 +34,7 @@ sys.path.insert(0, str(ROOT))
 
 METRIC = "fragment CCSD(T) solves/s + (T) TFLOP/s, mixed vs FP64, at |ΔE|≤1e-6 Eh"
 PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
-DTYPES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
+DTYPES = {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}
 
 
 def log(msg: str) -> None:
@@ -73,13 +79,18 @@ def cpu_baseline(frag, n_iter: int, budget_triples: int = 4) -> dict:
                        f"({t_trip:.2f} s each); estimated {est:.1f} s per solve")}
 
 
-def main() -> int:
+def parse_args():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="single_realistic")
-    ap.add_argument("--precision", default="fp64", choices=sorted(PEAKS_TFLOPS))
+    ap.add_argument("--precision", default="fp32", choices=sorted(PEAKS_TFLOPS))
+    ap.add_argument("--compare-fp64", type=int, default=1,
+                    help="also time the plain FP64 path (single: same steps; batch: 64 "
+                         "sequential solves)")
+    ap.add_argument("--batch-slots", type=int, default=4)
+    ap.add_argument("--batch-streams", type=int, default=4)
     ap.add_argument("--conv-tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--level-shift", type=float, default=0.0)
@@ -90,7 +101,179 @@ def main() -> int:
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a plain copy of known size "
                          "that scales hardware byte counters)")
-    args = ap.parse_args()
+    return ap.parse_args()
+
+
+def roofline(prof: dict, precision: str, workload: str) -> dict:
+    """Position of the kernel class with the largest device time."""
+    dominant = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dominant]
+    achieved = d["flops"] / d["ms"] / 1e9 if d["ms"] > 0 else 0.0
+    # ladder and (T) products run in the chosen precision; every other contraction in FP64
+    kprec = precision if dominant in ("ladder_build", "ladder_contract", "triples_w") else "fp64"
+    peak = PEAKS_TFLOPS[kprec]
+    traffic = None
+    tpath = ROOT / "profiles" / "traffic.json"
+    if tpath.exists():
+        ent = json.loads(tpath.read_text()).get(f"{workload}:{kprec}:{dominant}")
+        if ent and ent.get("sources") == kernel_sources_hash():
+            traffic = ent.get("bytes_per_launch")
+    return {"bound": "mfma", "kernel": dominant, "precision": kprec, "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+            "flops_per_launch": d["flops"] / max(1, d["launches"]),
+            "avg_launch_ms": d["ms"] / max(1, d["launches"])}
+
+
+def kernel_table(prof: dict) -> dict:
+    return {k: {"launches": p["launches"], "ms_total": p["ms"],
+                "tflops": (p["flops"] / p["ms"] / 1e9) if p["ms"] > 0 else None}
+            for k, p in prof.items()}
+
+
+def run_single(args, L, torch) -> dict:
+    from synth import CONFIG_SHAPES, make_fragment
+    o, v, X, seed = CONFIG_SHAPES[args.workload]
+    log(f"workload {args.workload}: nocc={o} nvir={v} naux={X} seed={seed}")
+    frag = make_fragment(o, v, X, seed)
+    dev = torch.device("cuda:0")
+    B = torch.tensor(frag.B, device=dev)
+    eo = torch.tensor(frag.eps_occ, device=dev)
+    ev = torch.tensor(frag.eps_vir, device=dev)
+    t1 = torch.empty((o, v), dtype=torch.float64, device=dev)
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=dev)
+    ws = L.Workspace(dev)
+
+    def timed(precision: str, steps: int, warmup: int):
+        opt = L.make_options(precision=precision, level_shift=args.level_shift,
+                             diis_start=args.diis_start, max_iter=args.max_iter)
+        fs = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
+        ws.attach([fs], opt)
+
+        def step():
+            st = L.lnocc_fragment_ccsd(fs, opt)
+            if st < 0:
+                raise RuntimeError(f"{L.lnocc_status_string(st)}: {L.lnocc_last_error()}")
+
+        for w in range(warmup):
+            step()
+            log(f"{precision} warmup {w + 1}/{warmup}: {fs.n_iter} iterations, "
+                f"E_CCSD={fs.e_ccsd:.10f}")
+        torch.cuda.synchronize()
+        L.lnocc_profile_enable(True)
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step()
+            log(f"{precision} step {k + 1}/{steps} done")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        L.lnocc_profile_enable(False)
+        prof = L.lnocc_profile_collect()
+        return fs, opt, elapsed, prof
+
+    fs, opt, elapsed, prof = timed(args.precision, args.steps, args.warmup)
+    res = {"value": args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+           "config": {"workload": args.workload, "nocc": o, "nvir": v, "naux": X, "seed": seed,
+                      "precision": args.precision, "conv_tol": args.conv_tol,
+                      "level_shift": args.level_shift, "diis_start": args.diis_start,
+                      "ccsd_iterations": fs.n_iter, "status": fs.status},
+           "e_ccsd": fs.e_ccsd}
+    # (T) alone on the converged amplitudes (the solves above already warmed it up)
+    ft = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
+    nrep = max(1, args.triples_reps)
+    t0 = time.perf_counter()
+    for _ in range(nrep):
+        L.lnocc_fragment_triples(ft, opt)
+    torch.cuda.synchronize()
+    t_triples = (time.perf_counter() - t0) / nrep
+    f_t = 2.0 * o ** 3 * v ** 4 + 2.0 * o ** 4 * v ** 3
+    log(f"(T): {t_triples * 1e3:.1f} ms, E_(T)={ft.e_t:.12f}")
+    res.update(triples_tflops=f_t / t_triples / 1e12, triples_ms=t_triples * 1e3, e_t=ft.e_t,
+               kernels=kernel_table(prof), roofline=roofline(prof, args.precision, args.workload))
+    gpath = ROOT / "tests" / "golden" / f"{args.workload}.json"
+    golden = json.loads(gpath.read_text()) if gpath.exists() else None
+    if golden and golden.get("input_sha256") != frag.sha256():
+        golden = None
+    if golden:
+        res["parity_vs_oracle"] = {"d_e_ccsd": fs.e_ccsd - golden["e_ccsd"],
+                                   "d_e_t": ft.e_t - golden["e_t"]}
+    if args.compare_fp64 and args.precision != "fp64":
+        f64, opt64, el64, prof64 = timed("fp64", args.steps, args.warmup)
+        ft64 = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
+        st = L.lnocc_fragment_triples(ft64, opt64)
+        torch.cuda.synchronize()
+        if st < 0:
+            raise RuntimeError(f"{L.lnocc_status_string(st)}: {L.lnocc_last_error()}")
+        cmp = {"value": args.steps / el64, "unit": "solves/s", "ms_per_step": 1e3 * el64 / args.steps,
+               "ccsd_iterations": f64.n_iter, "e_ccsd": f64.e_ccsd, "e_t": ft64.e_t,
+               "roofline": roofline(prof64, "fp64", args.workload)}
+        if golden:
+            cmp["parity_vs_oracle"] = {"d_e_ccsd": f64.e_ccsd - golden["e_ccsd"],
+                                       "d_e_t": ft64.e_t - golden["e_t"]}
+        res["fp64"] = cmp
+        res["speedup_vs_fp64"] = res["value"] / cmp["value"]
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        res["cpu_baseline"] = cpu_baseline(frag, fs.n_iter)
+    return res
+
+
+def run_batch(args, L, torch) -> dict:
+    from synth import batch_shapes, make_fragment
+    shapes = batch_shapes()
+    log(f"batch workload: {len(shapes)} fragments")
+    dev = []
+    for s in shapes:
+        f = make_fragment(*s)
+        dev.append(tuple(torch.tensor(x, dtype=torch.float64, device="cuda:0")
+                         for x in (f.B, f.eps_occ, f.eps_vir)))
+    torch.cuda.synchronize()
+    ws = L.Workspace("cuda:0")
+    kw = dict(conv_tol=args.conv_tol, level_shift=args.level_shift, diis_start=args.diis_start,
+              max_iter=args.max_iter, workspace=ws)
+    for w in range(args.warmup):   # a few fragments: library and kernels loaded
+        L.solve_batch(dev[:4], precision=args.precision, batch_slots=args.batch_slots,
+                      batch_streams=args.batch_streams, **kw)
+        log(f"warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    L.lnocc_profile_enable(True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        res = L.solve_batch(dev, precision=args.precision, batch_slots=args.batch_slots,
+                            batch_streams=args.batch_streams, **kw)
+        log(f"batch step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    L.lnocc_profile_enable(False)
+    prof = L.lnocc_profile_collect()
+    n = len(shapes)
+    out = {"value": n * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+           "config": {"workload": "batch", "fragments": n, "precision": args.precision,
+                      "conv_tol": args.conv_tol, "batch_slots": args.batch_slots,
+                      "batch_streams": args.batch_streams,
+                      "ccsd_iterations": sum(r.n_iter for r in res),
+                      "statuses": {str(st): sum(r.status == st for r in res)
+                                   for st in sorted({r.status for r in res})}},
+           "kernels": kernel_table(prof), "roofline": roofline(prof, args.precision, "batch")}
+    if args.compare_fp64:
+        t0 = time.perf_counter()
+        seq = []
+        for i, d in enumerate(dev):
+            seq.append(L.solve(*d, precision="fp64", **kw))
+            if i % 16 == 15:
+                log(f"sequential fp64: {i + 1}/{n}")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        de = [abs(a.e_ccsd - b.e_ccsd) for a, b in zip(res, seq)]
+        dt = [abs(a.e_t - b.e_t) for a, b in zip(res, seq)]
+        out["fp64_sequential"] = {"value": n / el, "unit": "solves/s", "seconds": el,
+                                  "max_abs_d_e_ccsd": max(de), "max_abs_d_e_t": max(dt)}
+        out["speedup_vs_fp64_sequential"] = out["value"] / out["fp64_sequential"]["value"]
+    return out
+
+
+def main() -> int:
+    args = parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(fragments would be sharded across GPUs with no exchange but the final "
@@ -99,7 +282,6 @@ def main() -> int:
 
     import torch
     from paper_2407_11258_amd import lnocc as L
-    from synth import CONFIG_SHAPES, make_fragment
 
     if args.copy_calibration > 0:
         n = args.copy_calibration << 20
@@ -110,107 +292,24 @@ def main() -> int:
         log(f"calibration copy of {args.copy_calibration} MiB done")
         del src, dst
 
-    o, v, X, seed = CONFIG_SHAPES[args.workload]
-    log(f"workload {args.workload}: nocc={o} nvir={v} naux={X} seed={seed}")
-    frag = make_fragment(o, v, X, seed)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    B = torch.tensor(frag.B, device=dev)
-    eo = torch.tensor(frag.eps_occ, device=dev)
-    ev = torch.tensor(frag.eps_vir, device=dev)
-    t1 = torch.empty((o, v), dtype=torch.float64, device=dev)
-    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=dev)
-    opt = L.make_options(precision=args.precision, level_shift=args.level_shift,
-                         diis_start=args.diis_start, max_iter=args.max_iter)
-    fs = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
-    ws = L.Workspace(dev)
-    ws.attach([fs], opt)
-    log(f"workspace {opt.workspace_bytes / 2**30:.2f} GiB")
-
-    def step():
-        st = L.lnocc_fragment_ccsd(fs, opt)
-        if st < 0:
-            raise RuntimeError(L.lnocc_status_string(st))
-        return st
-
-    for w in range(args.warmup):
-        step()
-        log(f"warmup {w + 1}/{args.warmup}: {fs.n_iter} iterations, E_CCSD={fs.e_ccsd:.10f}")
-    torch.cuda.synchronize()
-    L.lnocc_profile_enable(True)
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step()
-        log(f"step {k + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    L.lnocc_profile_enable(False)
-    prof = L.lnocc_profile_collect()
-    status = fs.status
-
-    # (T) alone on the converged amplitudes (the solve above already warmed it up)
-    ft = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
-    nrep = max(1, args.triples_reps)
-    t0 = time.perf_counter()
-    for _ in range(nrep):
-        st = L.lnocc_fragment_triples(ft, opt)
-    torch.cuda.synchronize()
-    t_triples = (time.perf_counter() - t0) / nrep
-    f_t = 2.0 * o ** 3 * v ** 4 + 2.0 * o ** 4 * v ** 3
-    log(f"(T): {t_triples * 1e3:.1f} ms, E_(T)={ft.e_t:.12f}")
-
-    dominant = max(prof, key=lambda k: prof[k]["ms"])
-    d = prof[dominant]
-    achieved = d["flops"] / d["ms"] / 1e9 if d["ms"] > 0 else 0.0
-    peak = PEAKS_TFLOPS[args.precision]
-    traffic = None
-    tpath = ROOT / "profiles" / "traffic.json"
-    if tpath.exists():
-        tj = json.loads(tpath.read_text())
-        ent = tj.get(f"{args.workload}:{args.precision}:{dominant}")
-        if ent and ent.get("sources") == kernel_sources_hash():
-            traffic = ent.get("bytes_per_launch")
-
-    parity = None
-    gpath = ROOT / "tests" / "golden" / f"{args.workload}.json"
-    if gpath.exists():
-        g = json.loads(gpath.read_text())
-        if g.get("input_sha256") == frag.sha256():
-            parity = {"d_e_ccsd": fs.e_ccsd - g["e_ccsd"], "d_e_t": ft.e_t - g["e_t"]}
-
+    torch.cuda.set_device(0)
+    res = run_batch(args, L, torch) if args.workload == "batch" else run_single(args, L, torch)
     result = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": res.pop("value"),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": res.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": DTYPES[args.precision],
         "data": "synthetic",
-        "config": {"workload": args.workload, "nocc": o, "nvir": v, "naux": X, "seed": seed,
-                   "precision": args.precision, "conv_tol": args.conv_tol,
-                   "level_shift": args.level_shift, "diis_start": args.diis_start,
-                   "ccsd_iterations": fs.n_iter, "status": status},
-        "triples_tflops": f_t / t_triples / 1e12,
-        "triples_ms": t_triples * 1e3,
-        "e_ccsd": fs.e_ccsd,
-        "e_t": ft.e_t,
-        "parity_vs_oracle": parity,
-        "kernels": {k: {"launches": p["launches"], "ms_total": p["ms"],
-                        "tflops": (p["flops"] / p["ms"] / 1e9) if p["ms"] > 0 else None}
-                    for k, p in prof.items()},
-        "roofline": {"bound": "mfma", "kernel": dominant, "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                     "flops_per_launch": d["flops"] / max(1, d["launches"]),
-                     "avg_launch_ms": d["ms"] / max(1, d["launches"])},
+        "config": res.pop("config"),
     }
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle sample)")
-        result["cpu_baseline"] = cpu_baseline(frag, fs.n_iter)
+    result.update(res)
     print(json.dumps(result), flush=True)
     return 0
 
