@@ -23,14 +23,17 @@ The CCSD equations decide the final answer; the guess only changes the number
 of iterations.
 
 Features of amplitude (i, j, a, b), with K[i,a,j,b] = (ia|jb) and
-D = e_i + e_j - e_a - e_b:
+D = e_i + e_j - e_a - e_b.  Every feature is unchanged under
+(i, j, a, b) -> (j, i, b, a), so the guess keeps the symmetry
+t_ij^ab = t_ji^ba of the exact amplitudes:
      0  K[i,a,j,b] / D             (the MP1 amplitude t_ij^ab)
      1  K[i,b,j,a] / D             (its exchange partner t_ij^ba)
      2  K[i,a,j,b]
      3  K[i,b,j,a]
      4  1 / D
      5  D
-     6  e_i        7  e_j        8  e_a        9  e_b
+     6  e_i + e_j                  7  |e_i - e_j|
+     8  e_a + e_b                  9  |e_a - e_b|
     10  |B_ia| |B_jb|              (|B_pq| = Euclidean norm over Q of B[Q,p,q])
     11  |B_ib| |B_ja|
     12  1 if i == j else 0
@@ -73,10 +76,12 @@ def pair_features(B: np.ndarray, eps_occ: np.ndarray, eps_vir: np.ndarray) -> np
     X[..., 3] = Kx
     X[..., 4] = 1.0 / D
     X[..., 5] = D
-    X[..., 6] = eps_occ[:, None, None, None]
-    X[..., 7] = eps_occ[None, :, None, None]
-    X[..., 8] = eps_vir[None, None, :, None]
-    X[..., 9] = eps_vir[None, None, None, :]
+    eo_i, eo_j = eps_occ[:, None, None, None], eps_occ[None, :, None, None]
+    ev_a, ev_b = eps_vir[None, None, :, None], eps_vir[None, None, None, :]
+    X[..., 6] = eo_i + eo_j + 0 * ev_a
+    X[..., 7] = np.abs(eo_i - eo_j) + 0 * ev_a
+    X[..., 8] = ev_a + ev_b + 0 * eo_i
+    X[..., 9] = np.abs(ev_a - ev_b) + 0 * eo_i
     X[..., 10] = nrm[:, None, :, None] * nrm[None, :, None, :]
     X[..., 11] = nrm[:, None, None, :] * nrm[None, :, :, None]
     X[..., 12] = np.eye(o)[:, :, None, None]

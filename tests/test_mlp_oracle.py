@@ -105,7 +105,8 @@ def test_features_from_their_definitions():
         assert abs(x[2] - eri[i, A, j, Bv]) < 1e-13 and abs(x[3] - eri[i, Bv, j, A]) < 1e-13
         assert abs(x[1] - eri[i, Bv, j, A] / D) < 1e-12 and abs(x[5] - D) < 1e-14
         assert abs(x[4] * D - 1) < 1e-14
-        assert tuple(x[6:10]) == (f.eps_occ[i], f.eps_occ[j], f.eps_vir[a], f.eps_vir[b])
+        ei, ej, ea, eb = f.eps_occ[i], f.eps_occ[j], f.eps_vir[a], f.eps_vir[b]
+        assert tuple(x[6:10]) == (ei + ej, abs(ei - ej), ea + eb, abs(ea - eb))
         nia = np.linalg.norm(f.B[:, i, A])
         njb = np.linalg.norm(f.B[:, j, Bv])
         nib, nja = np.linalg.norm(f.B[:, i, Bv]), np.linalg.norm(f.B[:, j, A])
@@ -116,12 +117,9 @@ def test_features_from_their_definitions():
 
 
 def test_amplitude_symmetry_of_features():
-    """t_ij^ab = t_ji^ba, so the features of (i,j,a,b) and (j,i,b,a) agree up to
-    the order of the single-index entries."""
+    """t_ij^ab = t_ji^ba: the features of (i,j,a,b) and (j,i,b,a) are equal, so
+    any model predicts a guess with that symmetry."""
     f = make_fragment(2, 5, 12, 3)
     X = mlp.pair_features(f.B, f.eps_occ, f.eps_vir)
     Xs = X.transpose(1, 0, 3, 2, 4)
-    same = [0, 1, 2, 3, 4, 5, 10, 11, 12, 13, 14, 15]
-    np.testing.assert_allclose(X[..., same], Xs[..., same], rtol=1e-13, atol=1e-15)
-    np.testing.assert_array_equal(X[..., 6], Xs[..., 7])
-    np.testing.assert_array_equal(X[..., 8], Xs[..., 9])
+    np.testing.assert_allclose(X, Xs, rtol=1e-13, atol=1e-15)
