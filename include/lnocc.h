@@ -59,7 +59,10 @@ typedef enum {
 
 typedef enum {
   LNOCC_GUESS_MP2 = 0,  /* T1 = 0, T2 = MP1 amplitudes (Eq. 21 with i_F over all occupied) */
-  LNOCC_GUESS_USER = 1  /* start from the caller's t1 / t2 buffers (restart) */
+  LNOCC_GUESS_USER = 1, /* start from the caller's t1 / t2 buffers (restart) */
+  LNOCC_GUESS_MLP = 2   /* T1 = 0, T2 = MP1 amplitudes plus the correction predicted by the
+                           model options.mlp (see "learned starting guess" below); falls back
+                           to the MP2 start when that start is worse */
 } lnocc_guess_t;
 
 /* One fragment problem and its results. */
@@ -79,8 +82,11 @@ typedef struct lnocc_fragment_t {
   double e_ccsd;             /* CCSD correlation energy (Eq. 7, tau = t2 + t1 t1) */
   double e_t;                /* (T) energy; 0 when triples are off */
   double residual;           /* last ||t_new - t_old||_2 */
-  int32_t n_iter;            /* CCSD iterations taken */
+  int32_t n_iter;            /* CCSD residual evaluations, including the one at the MP2
+                                start that LNOCC_GUESS_MLP spends on its fallback test */
   int32_t status;            /* lnocc_status_t of this fragment */
+  int32_t guess_used;        /* lnocc_guess_t the iterations actually started from */
+  int32_t reserved1;
 } lnocc_fragment_t;
 
 typedef struct lnocc_options_t {
@@ -104,6 +110,7 @@ typedef struct lnocc_options_t {
                                 priority created for the call, so that small fragments run
                                 concurrently */
   int32_t reserved2;
+  const float *mlp;          /* device model blob (LNOCC_MLP_BLOB floats) for LNOCC_GUESS_MLP */
 } lnocc_options_t;
 
 /* Fills *opt with defaults: FP64, MP2 guess, triples on, max_iter 100,
@@ -205,6 +212,7 @@ int lnocc_contract(const lnocc_contract_t *desc, void *stream);
  *   1 (ac|bd) formation for the particle-particle ladder (Eq. 27a over Q)
  *   2 ladder contraction  sum_cd t_ij^cd (ac|bd)
  *   3 (T) W contraction   (SI Sec. S1) for batches of unique triples
+ *   4 products of the learned-guess network (forward and backward)
  * flops counts 2 M N K per product term (the algorithmic count). */
 typedef struct lnocc_kernel_stats_t {
   int64_t launches;
@@ -212,9 +220,79 @@ typedef struct lnocc_kernel_stats_t {
   double flops;
 } lnocc_kernel_stats_t;
 
-#define LNOCC_KERNEL_CLASSES 4
+#define LNOCC_KERNEL_CLASSES 5
 void lnocc_profile_enable(int on);
 void lnocc_profile_collect(lnocc_kernel_stats_t out[LNOCC_KERNEL_CLASSES]);
+
+/* ---- learned starting guess --------------------------------------------------
+ * Beyond the paper, which starts CCSD from the MP1 amplitudes (Eq. 21): a
+ * per-amplitude multilayer perceptron predicts t_CCSD - t_MP1 from sixteen
+ * features of the amplitude that exist before the first iteration, and the
+ * solver starts from t_MP1 plus that correction (T1 = 0).  The CCSD equations
+ * still decide the result; the guess changes the number of iterations only.
+ * Before the first iteration the solver also evaluates the residual at the MP2
+ * start; if the learned start gives a larger (or non-finite) first step
+ * ||t_new - t_old||, it continues from the MP2 start instead (guess_used).
+ *
+ * Features of t_ij^ab, with K = (ia|jb), K' = (ib|ja), D = e_i + e_j - e_a -
+ * e_b and |B_pq| the norm over Q of B[Q][p][q]:
+ *   K/D, K'/D, K, K', 1/D, D, e_i + e_j, |e_i - e_j|, e_a + e_b, |e_a - e_b|,
+ *   |B_ia||B_jb|, |B_ib||B_ja|, [i == j], [a == b], (ii|aa) + (jj|bb),
+ *   (ii|bb) + (jj|aa)
+ * (each unchanged under (i,j,a,b) -> (j,i,b,a), so the guess keeps
+ * t_ij^ab = t_ji^ba).  Network: x -> (x - mu) * inv_sigma -> three hidden
+ * layers of 256 SiLU units -> one output y; correction = y_mu + y_sigma * y.
+ * Model blob, FP32 in device memory: LNOCC_MLP_HEADER floats [mu(16),
+ * inv_sigma(16), y_mu, y_sigma, zeros] then LNOCC_MLP_PARAMS trainable floats
+ * W1[256][16], b1[256], W2[256][256], b2[256], W3[256][256], b3[256], w4[256],
+ * b4, zeros.  Products run in FP32 on the matrix cores.
+ *
+ * The calls below take stream, workspace and workspace_bytes from *opt (its
+ * other fields are ignored except where stated); arrays are device FP32 and
+ * 16-byte aligned; rows of X are LNOCC_MLP_FEATURES floats. */
+#define LNOCC_MLP_FEATURES 16
+#define LNOCC_MLP_HIDDEN 256
+#define LNOCC_MLP_HEADER 64
+#define LNOCC_MLP_PARAMS 136256
+#define LNOCC_MLP_BLOB (LNOCC_MLP_HEADER + LNOCC_MLP_PARAMS)
+
+/* Workspace for the network on up to `rows` rows per pass; training != 0 also
+ * holds the backward pass (train and loss_grad need rows >= their batch). */
+int lnocc_mlp_workspace_bytes(int64_t rows, int32_t training, size_t *bytes);
+
+/* Training samples of a solved fragment: features X[n][16] of the amplitudes
+ * with flat indices idx[r] = ((i nocc + j) nvir + a) nvir + b (device int64)
+ * and, when Y != NULL, targets Y[r] = t2 - t_MP1 from the amplitudes in f->t2.
+ * Uses opt->workspace as lnocc_fragment_triples does (same size).  An index
+ * outside the amplitude array gives a row of NaN. */
+int lnocc_mlp_samples(lnocc_fragment_t *f, const lnocc_options_t *opt, const int64_t *idx,
+                      int64_t n, float *X, float *Y);
+
+/* Header of blob from the statistics of (X, Y) over n rows (column means, inverse
+ * standard deviations; 0 for a constant feature), and weights drawn from a
+ * counter-based generator keyed by seed (uniform, Glorot limits; output layer
+ * scaled by 0.1; biases zero). */
+int lnocc_mlp_init(float *blob, const float *X, const float *Y, int64_t n, uint64_t seed,
+                   const lnocc_options_t *opt);
+
+/* out[r] = y_mu + y_sigma * net(norm(X[r])), r < n. */
+int lnocc_mlp_predict(const float *blob, const float *X, int64_t n, float *out,
+                      const lnocc_options_t *opt);
+
+/* Mean squared error L = mean_r (net(norm(X[r])) - (Y[r] - y_mu) / y_sigma)^2 over
+ * all n rows (*loss, host) and dL/dparams into grad (device, LNOCC_MLP_PARAMS
+ * floats, parameter layout of the blob). */
+int lnocc_mlp_loss_grad(const float *blob, const float *X, const float *Y, int64_t n,
+                        float *grad, double *loss, const lnocc_options_t *opt);
+
+/* nsteps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8; step numbers step0 + 1,
+ * ...) on the trainable part of blob, each on `batch` rows of (X, Y) drawn by a
+ * counter-based generator keyed by (seed, step); adam: device float
+ * [2 LNOCC_MLP_PARAMS] moments, zero before the first step.  losses (host, may be
+ * NULL) receives the minibatch loss before each step. */
+int lnocc_mlp_train(float *blob, float *adam, int64_t step0, int32_t nsteps, const float *X,
+                    const float *Y, int64_t n, int32_t batch, float lr, uint64_t seed,
+                    double *losses, const lnocc_options_t *opt);
 
 /* ---- validation mode -------------------------------------------------------
  * on != 0: every later call runs its host logic and launch sequence without

@@ -14,6 +14,7 @@
 #include "../../include/lnocc.h"
 #include "gett.h"
 #include "solver.h"
+#include "mlp.h"
 
 using namespace lnocc;
 
@@ -34,7 +35,11 @@ int check_options(const lnocc_options_t *opt) {
   if (!opt) return LNOCC_EINVAL;
   if (opt->precision != LNOCC_FP64 && opt->precision != LNOCC_FP32 && opt->precision != LNOCC_BF16)
     return LNOCC_EINVAL;
-  if (opt->guess != LNOCC_GUESS_MP2 && opt->guess != LNOCC_GUESS_USER) return LNOCC_EINVAL;
+  if (opt->guess != LNOCC_GUESS_MP2 && opt->guess != LNOCC_GUESS_USER &&
+      opt->guess != LNOCC_GUESS_MLP)
+    return LNOCC_EINVAL;
+  if (opt->guess == LNOCC_GUESS_MLP && (!opt->mlp || ((uintptr_t)opt->mlp) % 16))
+    return LNOCC_EINVAL;
   if (opt->max_iter < 0 || opt->diis_space < 1 || opt->diis_space > 16 || opt->diis_start < 1 ||
       opt->triples_batch < 0 || opt->batch_slots < 0 || opt->batch_streams < 0 ||
       opt->batch_streams > 64 || !(opt->level_shift >= 0.0) || !std::isfinite(opt->level_shift))
@@ -80,7 +85,7 @@ Dims dims_of(const lnocc_fragment_t *f) { return Dims{f->nocc, f->nvir, f->naux}
 
 // Installs the address guard of the contraction launcher for one call.
 struct Guard {
-  Region r[6];
+  Region r[7];
   Guard(const lnocc_fragment_t *f, const lnocc_options_t *opt, const Layout &L) {
     install_splitk_scratch(L.splitk, (size_t)L.splitk_elems);
     const size_t o = f->nocc, v = f->nvir, X = f->naux, n = o + v;
@@ -91,6 +96,7 @@ struct Guard {
     r[k++] = Region{f->eps_vir, v * 8};
     r[k++] = Region{f->t1, f->t1 ? o * v * 8 : 0};
     r[k++] = Region{f->t2, f->t2 ? o * o * v * v * 8 : 0};
+    r[k++] = Region{opt->mlp, opt->mlp ? (size_t)mlp::kBlob * 4 : 0};
     install_regions(r, k);
   }
   ~Guard() {
@@ -256,6 +262,7 @@ int lnocc_fragment_ccsd(lnocc_fragment_t *f, const lnocc_options_t *opt) {
   f->e_t = opt->do_triples ? out.e_t : 0.0;
   f->residual = out.residual;
   f->n_iter = out.n_iter;
+  f->guess_used = out.guess_used;
   return finish(f, st);
 }
 
@@ -333,7 +340,8 @@ int lnocc_batch_solve(lnocc_fragment_t *f, int32_t nfrag, const lnocc_options_t 
                    [&](int a, int b) { return fragment_cost(&f[a]) > fragment_cost(&f[b]); });
 
   // address guard over the workspace and every fragment's arrays
-  std::vector<Region> regions{Region{opt->workspace, opt->workspace_bytes}};
+  std::vector<Region> regions{Region{opt->workspace, opt->workspace_bytes},
+                              Region{opt->mlp, opt->mlp ? (size_t)mlp::kBlob * 4 : 0}};
   for (int k : order) {
     const size_t o = f[k].nocc, v = f[k].nvir, X = f[k].naux, n = o + v;
     regions.push_back(Region{f[k].B, X * n * n * 8});
@@ -387,6 +395,7 @@ int lnocc_batch_solve(lnocc_fragment_t *f, int32_t nfrag, const lnocc_options_t 
     g->e_t = opt->do_triples ? out.e_t : 0.0;
     g->residual = out.residual;
     g->n_iter = out.n_iter;
+    g->guess_used = out.guess_used;
     if (status == 1) status = out.status;
     worst = worse(worst, finish(g, status));
     q.run.reset();
@@ -439,6 +448,168 @@ int lnocc_batch_solve(lnocc_fragment_t *f, int32_t nfrag, const lnocc_options_t 
   }
   return worst;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ learned guess
+namespace {
+
+// Largest row count whose scratch fits in `bytes`.
+int64_t rows_that_fit(size_t bytes, bool training) {
+  mlp::Scratch S;
+  int64_t lo = 0, hi = (int64_t)1 << 26;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    mlp::plan_scratch(mid, training, nullptr, S);
+    if (S.bytes <= bytes) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p) % 16 == 0; }
+
+// Scratch on the caller's workspace with room for `need` rows (0: as many as fit).
+int mlp_scratch(const lnocc_options_t *opt, bool training, int64_t need, mlp::Scratch &S) {
+  if (!opt) return LNOCC_EINVAL;
+  if (!opt->workspace) return LNOCC_ENOMEM;
+  if (((uintptr_t)opt->workspace) % 256) return LNOCC_EINVAL;
+  const int64_t rows = rows_that_fit(opt->workspace_bytes, training);
+  if (rows < std::max<int64_t>(need, 1)) return LNOCC_ENOMEM;
+  mlp::plan_scratch(need > 0 ? need : rows, training, (char *)opt->workspace, S);
+  return LNOCC_OK;
+}
+
+struct MlpGuard {
+  std::vector<Region> r;
+  MlpGuard(const lnocc_options_t *opt, const mlp::Scratch &S, std::initializer_list<Region> extra)
+      : r(extra) {
+    r.push_back(Region{opt->workspace, opt->workspace_bytes});
+    install_regions(r.data(), (int)r.size());
+    install_splitk_scratch(S.splitk, (size_t)S.splitk_elems);
+  }
+  ~MlpGuard() {
+    install_regions(nullptr, 0);
+    install_splitk_scratch(nullptr, 0);
+  }
+};
+
+int device_status(hipError_t e, const char *what) {
+  if (e == hipSuccess) return LNOCC_OK;
+  if (!last_error()[0]) note_error("%s failed (%s)", what, hipGetErrorString(e));
+  return LNOCC_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lnocc_mlp_workspace_bytes(int64_t rows, int32_t training, size_t *bytes) {
+  if (bytes) *bytes = 0;
+  if (!bytes || rows < 1 || rows > ((int64_t)1 << 26)) return LNOCC_EINVAL;
+  mlp::Scratch S;
+  mlp::plan_scratch(rows, training != 0, nullptr, S);
+  *bytes = S.bytes;
+  return LNOCC_OK;
+}
+
+int lnocc_mlp_samples(lnocc_fragment_t *f, const lnocc_options_t *opt, const int64_t *idx,
+                      int64_t n, float *X, float *Y) {
+  clear_error();
+  Layout L;
+  int st = prepare(f, opt, false, false, L);
+  if (!st && (!idx || !X || n < 0 || !aligned16(X) || (Y && !f->t2))) st = LNOCC_EINVAL;
+  if (st) return finish(f, st);
+  hipStream_t s = (hipStream_t)opt->stream;
+  Guard guard(f, opt, L);
+  st = setup_fragment(L, f->B, f->eps_occ, f->eps_vir, false, s);
+  if (!st) st = device_status(mlp::pair_stats(L.Boo, L.Bov, L.Bvv, L.dm.X, L.dm.o, L.dm.v, L.nrm,
+                                              L.jd, s), "pair statistics");
+  if (!st) st = device_status(mlp::features(L.Kov, f->eps_occ, f->eps_vir, L.nrm, L.jd, L.dm.o,
+                                            L.dm.v, idx, 0, n, Y ? f->t2 : nullptr, X, Y, s),
+                              "feature kernel");
+  if (dsync(s) != hipSuccess && !st) st = LNOCC_EDEVICE;
+  return finish(f, st);
+}
+
+int lnocc_mlp_init(float *blob, const float *X, const float *Y, int64_t n, uint64_t seed,
+                   const lnocc_options_t *opt) {
+  clear_error();
+  if (!blob || !X || !Y || n < 1 || !aligned16(blob) || !aligned16(X)) return LNOCC_EINVAL;
+  mlp::Scratch S;
+  int st = mlp_scratch(opt, false, 0, S);
+  if (st) return st;
+  MlpGuard g(opt, S, {Region{blob, (size_t)mlp::kBlob * 4}, Region{X, (size_t)n * 64},
+                      Region{Y, (size_t)n * 4}});
+  hipStream_t s = (hipStream_t)opt->stream;
+  st = device_status(mlp::init(blob, X, Y, n, seed, S, s), "network initialisation");
+  if (dsync(s) != hipSuccess && !st) st = LNOCC_EDEVICE;
+  return st;
+}
+
+int lnocc_mlp_predict(const float *blob, const float *X, int64_t n, float *out,
+                      const lnocc_options_t *opt) {
+  clear_error();
+  if (!blob || !X || !out || n < 0 || !aligned16(blob) || !aligned16(X)) return LNOCC_EINVAL;
+  mlp::Scratch S;
+  int st = mlp_scratch(opt, false, 0, S);
+  if (st) return st;
+  MlpGuard g(opt, S, {Region{blob, (size_t)mlp::kBlob * 4}, Region{X, (size_t)n * 64},
+                      Region{out, (size_t)n * 4}});
+  hipStream_t s = (hipStream_t)opt->stream;
+  st = device_status(mlp::predict(blob, X, n, out, S, s), "network prediction");
+  if (dsync(s) != hipSuccess && !st) st = LNOCC_EDEVICE;
+  return st;
+}
+
+int lnocc_mlp_loss_grad(const float *blob, const float *X, const float *Y, int64_t n,
+                        float *grad, double *loss, const lnocc_options_t *opt) {
+  clear_error();
+  if (!blob || !X || !Y || !grad || !loss || n < 1 || !aligned16(blob) || !aligned16(X))
+    return LNOCC_EINVAL;
+  mlp::Scratch S;
+  int st = mlp_scratch(opt, true, n, S);
+  if (st) return st;
+  MlpGuard g(opt, S, {Region{blob, (size_t)mlp::kBlob * 4}, Region{X, (size_t)n * 64},
+                      Region{Y, (size_t)n * 4}, Region{grad, (size_t)mlp::kParams * 4}});
+  hipStream_t s = (hipStream_t)opt->stream;
+  st = device_status(mlp::loss_grad(blob, X, Y, n, S, s), "loss and gradient");
+  if (!st) st = device_status(dcopy(grad, S.grad, (size_t)mlp::kParams * 4, s), "gradient copy");
+  *loss = 0.0;
+  if (!st) st = device_status(d2h(loss, S.loss, 8, s), "loss readback");
+  if (dsync(s) != hipSuccess && !st) st = LNOCC_EDEVICE;
+  return st;
+}
+
+int lnocc_mlp_train(float *blob, float *adam, int64_t step0, int32_t nsteps, const float *X,
+                    const float *Y, int64_t n, int32_t batch, float lr, uint64_t seed,
+                    double *losses, const lnocc_options_t *opt) {
+  clear_error();
+  if (!blob || !adam || !X || !Y || n < 1 || batch < 1 || nsteps < 0 || step0 < 0 ||
+      !(lr > 0.0f) || !std::isfinite(lr) || !aligned16(blob) || !aligned16(X))
+    return LNOCC_EINVAL;
+  mlp::Scratch S;
+  int st = mlp_scratch(opt, true, batch, S);
+  if (st) return st;
+  MlpGuard g(opt, S, {Region{blob, (size_t)mlp::kBlob * 4}, Region{adam, (size_t)mlp::kParams * 8},
+                      Region{X, (size_t)n * 64}, Region{Y, (size_t)n * 4}});
+  hipStream_t s = (hipStream_t)opt->stream;
+  for (int k0 = 0; k0 < nsteps && !st; k0 += mlp::kLossChunk) {
+    const int m = std::min(mlp::kLossChunk, nsteps - k0);
+    st = device_status(mlp::train(blob, adam, step0 + k0, m, X, Y, n, batch, lr, seed,
+                                  losses ? S.losses : nullptr, S, s), "training steps");
+    if (!st && losses) {
+      st = device_status(d2h(losses + k0, S.losses, (size_t)m * 8, s), "loss readback");
+      if (!st) st = device_status(dsync(s), "stream synchronization");
+    }
+  }
+  if (dsync(s) != hipSuccess && !st) st = LNOCC_EDEVICE;
+  return st;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 const char *lnocc_last_error(void) { return last_error(); }
 

@@ -24,7 +24,8 @@ enum class Kind : int {
   LadderBuild = 1,    // (ac|bd)~ = sum_Q B~_Qac B~_Qbd for a block of a
   LadderContract = 2, // R2 += sum_cd t_ij^cd (ac|bd)~
   TriplesW = 3,       // W_ijk^abc for a batch of unique triples
-  Count = 4
+  Mlp = 4,            // learned-guess network layers and their gradients (FP32 only)
+  Count = 5
 };
 
 // Division by a runtime-invariant divisor via multiply-high (Granlund and

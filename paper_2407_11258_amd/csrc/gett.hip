@@ -509,6 +509,12 @@ void launch_kind(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t
       hipLaunchKernelGGL((gett_kernel<M, C, 2>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
     case Kind::TriplesW:
       hipLaunchKernelGGL((gett_kernel<M, C, 3>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
+    case Kind::Mlp:
+      if constexpr (std::is_same<M, ModeF32>::value) {
+        hipLaunchKernelGGL((gett_kernel<M, C, 4>), grid, dim3(C::T), 0, stream, d, tiles_m, sps);
+        break;
+      }
+      [[fallthrough]];
     default:
       hipLaunchKernelGGL((gett_kernel<M, C, 0>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
   }

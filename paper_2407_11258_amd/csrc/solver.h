@@ -8,6 +8,7 @@
 
 #include "../../include/lnocc.h"
 #include "gett.h"
+#include "mlp.h"
 
 namespace lnocc {
 
@@ -24,6 +25,7 @@ struct Layout {
   double *hoo, *hov, *hvo, *hvv;    // bare one-electron operator blocks
   double *J;                        // [X] occupied trace of B (or B~)
   double *scal, *partials;          // small scalars, reduction partials
+  double *nrm, *jd;                 // |B_ia| and (ii|aa) [o][v] (learned-guess features)
   double *splitk;                   // split-K partial sums of thin contractions
   int64_t splitk_elems;
   // CCSD
@@ -40,6 +42,9 @@ struct Layout {
   double *dx, *de;                  // DIIS vectors and errors [m][namp]
   int64_t chunk_a, namp;
   int diis_m;
+  // learned guess (only with LNOCC_GUESS_MLP)
+  mlp::Scratch ms;                  // network scratch
+  int64_t nunique = 0;              // amplitudes with i <= j: o (o + 1) / 2 v^2
   // (T)
   double *Gt, *Jt, *W, *tpart;      // (ai|bd) [i][a][b][d], (ck|jl) [j][k][c][l], W [nb][v][v][v]
   int *table;
@@ -57,6 +62,7 @@ struct Inputs {
 struct Outputs {
   double e_mp2 = 0, e_ccsd = 0, e_t = 0, residual = 0;
   int n_iter = 0, status = 0;
+  int guess_used = 0;
 };
 
 // Stream copies and synchronization that become no-ops in validation mode
@@ -91,7 +97,8 @@ int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s);
 int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s);
 
 // Pinned host buffer for the small readbacks of one solve ([0] energy,
-// [1..16] DIIS overlaps, [32] step norm, [40] (T) energy) and the event that
+// [1..16] DIIS overlaps, [32] step norm, [33] step norm from the MP2 start,
+// [34] its DIIS error norm, [40] (T) energy) and the event that
 // marks their arrival.  Owned by the caller of CcsdRun; reused across solves.
 struct Readback {
   double *host = nullptr;
@@ -123,6 +130,8 @@ struct CcsdRun {
   bool use_diis = false;
   double prev = INFINITY, best = INFINITY;
   mutable int polls = 0;
+  bool mlp_check = false;      // the first step from the learned start is still to be judged
+  double r_mp2 = 0.0;          // first step norm from the MP2 start
 
   CcsdRun(const Layout &L, const Inputs &in, const lnocc_options_t &opt, hipStream_t s,
           Readback &rb);
@@ -139,6 +148,7 @@ struct CcsdRun {
 
  private:
   hipError_t mark();
+  int learned_start();
 };
 
 }  // namespace lnocc

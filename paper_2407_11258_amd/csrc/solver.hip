@@ -109,6 +109,7 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.t1w = A.d(ov); L.t2w = A.d(oovv);
   L.hoo = A.d(oo); L.hov = A.d(ov); L.hvo = A.d(ov); L.hvv = A.d(vv);
   L.J = A.d(X);
+  L.nrm = A.d(ov); L.jd = A.d(ov);
   L.scal = A.d(64);   // [0] energy, [1..16] Gram row, [32] ||R/D||^2, [40] (T) sum
   L.partials = A.d(17 * kRedBlocks);   // 16 Gram-row slices + the step norm
   L.splitk_elems = std::max<int64_t>({(int64_t)1 << 22, 64 * vv, 4 * oovv});
@@ -134,6 +135,14 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.Tsa = A.d(oovv); L.SA = A.d(oovv);
   L.Btvv_lp = (L.lp != Prec::F64) ? A.d(X * vv) : nullptr;
   L.dx = A.d(L.diis_m * N); L.de = A.d(L.diis_m * N);
+  if (opt.guess == LNOCC_GUESS_MLP) {
+    L.nunique = o * (o + 1) / 2 * vv;
+    const int64_t rows = std::min<int64_t>(L.nunique, (int64_t)1 << 17);
+    mlp::Scratch probe;
+    mlp::plan_scratch(rows, false, nullptr, probe);
+    char *mb = (char *)A.d((int64_t)((probe.bytes + 7) / 8));
+    mlp::plan_scratch(rows, false, base ? mb : nullptr, L.ms);
+  }
   const size_t ccsd_end = A.off;
   // (T) phase (aliases the CCSD scratch)
   A.off = phase;
@@ -504,13 +513,40 @@ int CcsdRun::poll() const {
 
 hipError_t CcsdRun::wait() const { return dry_run() ? hipSuccess : hipEventSynchronize(rb->ev); }
 
+// Learned start: first the residual at the MP2 start, whose Jacobi step and
+// error become the first DIIS pair (slot 0; also the fallback) and whose step
+// norm goes to scal[33] (||e||^2 to scal[34]); then t2 += the network's
+// correction over the unique amplitudes, chunk by chunk.
+int CcsdRun::learned_start() {
+  const int64_t o = L->dm.o, v = L->dm.v, N = L->namp;
+  int st = ccsd_residuals(*L, in.t1, in.t2, s);
+  if (st) return st;
+  install_splitk_scratch(L->splitk, (size_t)L->splitk_elems);
+  LN_TRY(jacobi_step(in.t1, in.t2, L->R1, L->R2, in.eo, in.ev, o, v, opt.level_shift, L->dx,
+                     L->de, L->partials + 16 * kRedBlocks, s));
+  LN_TRY(reduce_partials(L->partials + 16 * kRedBlocks, kRedBlocks, L->scal + 33, 0, s));
+  LN_TRY(dot_partials(L->de, N, 1, L->de, N, L->partials, s));
+  LN_TRY(reduce_rows(L->partials, 1, L->scal + 34, s));
+  LN_TRY(mlp::pair_stats(L->Boo, L->Bov, L->Bvv, L->dm.X, o, v, L->nrm, L->jd, s));
+  const mlp::Scratch &S = L->ms;
+  for (int64_t u0 = 0; u0 < L->nunique; u0 += S.rows) {
+    const int64_t m = std::min<int64_t>(S.rows, L->nunique - u0);
+    // raw features go to h2, which the forward pass reads before overwriting
+    LN_TRY(mlp::features(L->Kov, in.eo, in.ev, L->nrm, L->jd, o, v, nullptr, u0, m, nullptr, S.h2,
+                         nullptr, s));
+    LN_TRY(mlp::forward(opt.mlp, S.h2, m, S, s));
+    LN_TRY(mlp::apply_guess(opt.mlp, S.y, o, v, u0, m, in.t2, s));
+  }
+  return LNOCC_OK;
+}
+
 int CcsdRun::begin() {
   install_splitk_scratch(L->splitk, (size_t)L->splitk_elems);
   const int64_t o = L->dm.o, v = L->dm.v;
   int st = setup_fragment(*L, in.B, in.eo, in.ev, true, s);
   if (st) return st;
   // MP2 energy (always from the MP1 amplitudes) and the starting point
-  if (opt.guess == LNOCC_GUESS_MP2) {
+  if (opt.guess != LNOCC_GUESS_USER) {
     LN_TRY(mp2_guess(L->Kov, in.eo, in.ev, o, v, in.t1, in.t2, s));
     st = energy(*L, in.t1, in.t2, L->scal, s);
   } else {
@@ -518,7 +554,11 @@ int CcsdRun::begin() {
     st = energy(*L, L->R1, L->R2, L->scal, s);
   }
   if (st) return st;
-  LN_TRY(d2h(host, L->scal, 8, s));
+  if (opt.guess == LNOCC_GUESS_MLP) {
+    st = learned_start();
+    if (st) return st;
+  }
+  LN_TRY(d2h(host, L->scal, 40 * 8, s));
   LN_TRY(mark());
   phase = Phase::Started;
   return LNOCC_OK;
@@ -531,7 +571,8 @@ int CcsdRun::enqueue_iteration() {
   int st = ccsd_residuals(*L, in.t1, in.t2, s);
   if (st) return st;
   const int m = L->diis_m;
-  use_diis = (m > 1) && (it >= opt.diis_start);
+  // (a learned start begins with the MP2 start's pair already in the subspace)
+  use_diis = (m > 1) && (it >= opt.diis_start || count > 0);
   slot = use_diis ? (count % m) : 0;
   double *xs = L->dx + (int64_t)slot * N, *es = L->de + (int64_t)slot * N;
   double *rnorm = L->scal + 32;   // ||R / D||^2 of the current iterate
@@ -557,7 +598,28 @@ int CcsdRun::after_iteration() {
   double *xs = L->dx + (int64_t)slot * N, *es = L->de + (int64_t)slot * N;
   const double r2 = host[32];
   out.residual = std::sqrt(std::max(r2, 0.0));
-  out.n_iter = it;
+  out.n_iter = it + (opt.guess == LNOCC_GUESS_MLP ? 1 : 0);
+  if (mlp_check) {   // judge the learned start by its first step against the MP2 start's
+    mlp_check = false;
+    const double gram = host[1 + (use_diis ? slot : 0)];
+    if (!std::isfinite(r2) || !std::isfinite(gram) || out.residual > r_mp2) {
+      if (log_enabled()) {
+        std::fprintf(stderr, "lnocc: learned start rejected (step %.3e, MP2 start %.3e)\n",
+                     out.residual, r_mp2);
+        std::fflush(stderr);
+      }
+      out.guess_used = LNOCC_GUESS_MP2;
+      out.residual = r_mp2;
+      LN_TRY(scatter_vec(L->dx, o, v, in.t1, in.t2, s));   // the MP2 path's first iterate
+      std::fill(G.begin(), G.end(), 0.0);
+      count = 0;
+      growth = 0;
+      prev = best = r_mp2;
+      if (r_mp2 <= in.conv_tol) phase = Phase::Converged;
+      else if (it >= opt.max_iter) phase = Phase::Exhausted;
+      return LNOCC_OK;
+    }
+  }
   if (log_enabled()) {
     std::fprintf(stderr, "lnocc: iteration %d residual %.3e energy %.12f\n", it, out.residual,
                  it > 1 ? host[0] : out.e_mp2);
@@ -645,6 +707,19 @@ int CcsdRun::after_begin() {
   out.n_iter = 0;
   out.residual = 0.0;
   out.status = LNOCC_OK;
+  out.guess_used = opt.guess;
+  if (opt.guess == LNOCC_GUESS_MLP) {
+    mlp_check = true;
+    r_mp2 = std::sqrt(std::max(host[33], 0.0));
+    if (!std::isfinite(r_mp2) || !std::isfinite(host[34])) {
+      note_error("non-finite residual at the MP2 start");
+      return LNOCC_ENUMERIC;
+    }
+    if (L->diis_m > 1) {   // the MP2 start's step seeds the DIIS subspace
+      G[0] = host[34];
+      count = 1;
+    }
+  }
   if (opt.max_iter == 0) phase = Phase::Converged;
   return LNOCC_OK;
 }

@@ -22,7 +22,9 @@ LNOCC_EDEVICE = -3
 LNOCC_ENUMERIC = -4
 
 LNOCC_FP64, LNOCC_FP32, LNOCC_BF16 = 0, 1, 2
-LNOCC_GUESS_MP2, LNOCC_GUESS_USER = 0, 1
+LNOCC_GUESS_MP2, LNOCC_GUESS_USER, LNOCC_GUESS_MLP = 0, 1, 2
+LNOCC_MLP_FEATURES, LNOCC_MLP_HIDDEN, LNOCC_MLP_HEADER, LNOCC_MLP_PARAMS = 16, 256, 64, 136256
+LNOCC_MLP_BLOB = LNOCC_MLP_HEADER + LNOCC_MLP_PARAMS
 
 PRECISIONS = {"fp64": LNOCC_FP64, "fp32": LNOCC_FP32, "bf16": LNOCC_BF16}
 
@@ -36,6 +38,7 @@ class lnocc_fragment_t(C.Structure):
         ("e_mp2", C.c_double), ("e_ccsd", C.c_double), ("e_t", C.c_double),
         ("residual", C.c_double),
         ("n_iter", C.c_int32), ("status", C.c_int32),
+        ("guess_used", C.c_int32), ("reserved1", C.c_int32),
     ]
 
 
@@ -47,6 +50,7 @@ class lnocc_options_t(C.Structure):
         ("ladder_chunk_bytes", C.c_size_t), ("triples_batch", C.c_int32),
         ("batch_slots", C.c_int32), ("level_shift", C.c_double),
         ("batch_streams", C.c_int32), ("reserved2", C.c_int32),
+        ("mlp", C.c_void_p),
     ]
 
 
@@ -72,14 +76,16 @@ class lnocc_kernel_stats_t(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("flops", C.c_double)]
 
 
-LNOCC_KERNEL_CLASSES = 4
-KERNEL_CLASS_NAMES = ("other", "ladder_build", "ladder_contract", "triples_w")
+LNOCC_KERNEL_CLASSES = 5
+KERNEL_CLASS_NAMES = ("other", "ladder_build", "ladder_contract", "triples_w", "mlp")
 
 EXPORTS = ("lnocc_default_options", "lnocc_status_string", "lnocc_last_error",
            "lnocc_workspace_bytes",
            "lnocc_fragment_ccsd", "lnocc_fragment_triples", "lnocc_ccsd_residuals",
            "lnocc_batch_solve", "lnocc_contract", "lnocc_profile_enable",
-           "lnocc_profile_collect", "lnocc_set_validation_mode")
+           "lnocc_profile_collect", "lnocc_set_validation_mode", "lnocc_mlp_workspace_bytes",
+           "lnocc_mlp_samples", "lnocc_mlp_init", "lnocc_mlp_predict", "lnocc_mlp_loss_grad",
+           "lnocc_mlp_train")
 
 
 def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
@@ -116,6 +122,17 @@ def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
     lib.lnocc_profile_collect.restype = None
     lib.lnocc_set_validation_mode.argtypes = [C.c_int]
     lib.lnocc_set_validation_mode.restype = None
+    P, I64 = C.c_void_p, C.c_int64
+    lib.lnocc_mlp_workspace_bytes.argtypes = [I64, C.c_int32, C.POINTER(C.c_size_t)]
+    lib.lnocc_mlp_samples.argtypes = [FP, OP, P, I64, P, P]
+    lib.lnocc_mlp_init.argtypes = [P, P, P, I64, C.c_uint64, OP]
+    lib.lnocc_mlp_predict.argtypes = [P, P, I64, P, OP]
+    lib.lnocc_mlp_loss_grad.argtypes = [P, P, P, I64, P, C.POINTER(C.c_double), OP]
+    lib.lnocc_mlp_train.argtypes = [P, P, I64, C.c_int32, P, P, I64, C.c_int32, C.c_float,
+                                    C.c_uint64, C.POINTER(C.c_double), OP]
+    for name in ("lnocc_mlp_workspace_bytes", "lnocc_mlp_samples", "lnocc_mlp_init",
+                 "lnocc_mlp_predict", "lnocc_mlp_loss_grad", "lnocc_mlp_train"):
+        getattr(lib, name).restype = C.c_int
     return lib
 
 
@@ -181,6 +198,42 @@ def lnocc_set_validation_mode(on: bool) -> None:
     _lib.lnocc_set_validation_mode(int(bool(on)))
 
 
+def lnocc_mlp_workspace_bytes(rows: int, training: bool) -> tuple[int, int]:
+    out = C.c_size_t(0)
+    st = _lib.lnocc_mlp_workspace_bytes(int(rows), int(bool(training)), C.byref(out))
+    return st, out.value
+
+
+def lnocc_mlp_samples(frag: lnocc_fragment_t, opt: lnocc_options_t, idx_ptr: int, n: int,
+                      x_ptr: int, y_ptr: int | None) -> int:
+    return _lib.lnocc_mlp_samples(C.byref(frag), C.byref(opt), idx_ptr, n, x_ptr, y_ptr)
+
+
+def lnocc_mlp_init(blob_ptr: int, x_ptr: int, y_ptr: int, n: int, seed: int,
+                   opt: lnocc_options_t) -> int:
+    return _lib.lnocc_mlp_init(blob_ptr, x_ptr, y_ptr, n, seed, C.byref(opt))
+
+
+def lnocc_mlp_predict(blob_ptr: int, x_ptr: int, n: int, out_ptr: int, opt: lnocc_options_t) -> int:
+    return _lib.lnocc_mlp_predict(blob_ptr, x_ptr, n, out_ptr, C.byref(opt))
+
+
+def lnocc_mlp_loss_grad(blob_ptr: int, x_ptr: int, y_ptr: int, n: int, grad_ptr: int,
+                        opt: lnocc_options_t) -> tuple[int, float]:
+    loss = C.c_double(0.0)
+    st = _lib.lnocc_mlp_loss_grad(blob_ptr, x_ptr, y_ptr, n, grad_ptr, C.byref(loss), C.byref(opt))
+    return st, loss.value
+
+
+def lnocc_mlp_train(blob_ptr: int, adam_ptr: int, step0: int, nsteps: int, x_ptr: int,
+                    y_ptr: int, n: int, batch: int, lr: float, seed: int,
+                    opt: lnocc_options_t, want_losses: bool = True) -> tuple[int, list]:
+    losses = (C.c_double * max(1, nsteps))() if want_losses else None
+    st = _lib.lnocc_mlp_train(blob_ptr, adam_ptr, step0, nsteps, x_ptr, y_ptr, n, batch, lr, seed,
+                              losses, C.byref(opt))
+    return st, (list(losses)[:nsteps] if want_losses else [])
+
+
 # ------------------------------------------------------------ torch helpers
 @dataclasses.dataclass
 class Result:
@@ -192,6 +245,7 @@ class Result:
     residual: float
     t1: object
     t2: object
+    guess_used: int = 0
 
 
 def _torch():
@@ -217,7 +271,7 @@ def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int
                  diis_space: int = 8, diis_start: int = 2, guess: int = LNOCC_GUESS_MP2,
                  ladder_chunk_bytes: int = 0, triples_batch: int = 0,
                  level_shift: float = 0.0, batch_slots: int = 0,
-                 batch_streams: int = 0) -> lnocc_options_t:
+                 batch_streams: int = 0, mlp=None) -> lnocc_options_t:
     opt = lnocc_default_options()
     opt.precision = PRECISIONS[precision]
     opt.do_triples = int(do_triples)
@@ -230,6 +284,8 @@ def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int
     opt.level_shift = level_shift
     opt.batch_slots = batch_slots
     opt.batch_streams = batch_streams
+    if mlp is not None:
+        opt.mlp = mlp if isinstance(mlp, int) else mlp.data_ptr()
     return opt
 
 
@@ -271,7 +327,7 @@ def solve(B, eps_occ, eps_vir, *, conv_tol=1e-8, t1=None, t2=None, workspace=Non
     ws = workspace or Workspace(B.device)
     ws.attach([f], opt)
     st = lnocc_fragment_ccsd(f, opt)
-    return Result(st, f.e_mp2, f.e_ccsd, f.e_t, f.n_iter, f.residual, t1, t2)
+    return Result(st, f.e_mp2, f.e_ccsd, f.e_t, f.n_iter, f.residual, t1, t2, f.guess_used)
 
 
 def solve_batch(fragments, *, conv_tol=1e-8, workspace=None, **kw) -> list[Result]:
@@ -291,4 +347,4 @@ def solve_batch(fragments, *, conv_tol=1e-8, workspace=None, **kw) -> list[Resul
     ws.attach(list(arr), opt)
     lnocc_batch_solve(arr, opt)
     return [Result(arr[k].status, arr[k].e_mp2, arr[k].e_ccsd, arr[k].e_t, arr[k].n_iter,
-                   arr[k].residual, *amps[k]) for k in range(len(fragments))]
+                   arr[k].residual, *amps[k], arr[k].guess_used) for k in range(len(fragments))]

@@ -180,6 +180,53 @@ def test_batch_errors_are_per_fragment(validation_mode):
     assert L._lib.lnocc_batch_solve(arr, 0, C.byref(opt)) == L.LNOCC_EINVAL
 
 
+FAKE_MODEL = 1 << 47
+
+
+@pytest.mark.parametrize("o,v,X", [(4, 20, 72), (1, 1, 1), (6, 45, 100), (16, 160, 528)])
+def test_learned_guess_launches_stay_in_bounds(validation_mode, o, v, X):
+    opt = L.make_options(guess=L.LNOCC_GUESS_MLP, mlp=FAKE_MODEL)
+    f = _fake_fragment(o, v, X)
+    st, nbytes = L.lnocc_workspace_bytes([f], opt)
+    assert st == L.LNOCC_OK
+    plain = L.lnocc_workspace_bytes([f], L.make_options())[1]
+    assert nbytes >= plain                      # the network scratch and the fallback step
+    opt.workspace, opt.workspace_bytes = 1 << 45, nbytes
+    assert L.lnocc_fragment_ccsd(f, opt) == L.LNOCC_OK
+    assert f.guess_used == L.LNOCC_GUESS_MLP and f.n_iter == 2
+    opt.mlp = None
+    assert L.lnocc_fragment_ccsd(f, opt) == L.LNOCC_EINVAL      # no model
+    opt.mlp = FAKE_MODEL + 4
+    assert L.lnocc_fragment_ccsd(f, opt) == L.LNOCC_EINVAL      # misaligned model
+
+
+def test_network_calls_stay_in_bounds(validation_mode):
+    base = 1 << 46
+    blob, X, Y, out, grad, adam = (base + k * (1 << 36) for k in range(6))
+    n = 5000
+    for training, rows in ((False, 1 << 17), (True, 4096)):
+        st, nbytes = L.lnocc_mlp_workspace_bytes(rows, training)
+        assert st == L.LNOCC_OK and nbytes > rows * 4 * 256
+    opt = L.lnocc_default_options()
+    opt.workspace = 1 << 45
+    opt.workspace_bytes = L.lnocc_mlp_workspace_bytes(n, True)[1]
+    assert L.lnocc_mlp_init(blob, X, Y, n, 7, opt) == L.LNOCC_OK
+    assert L.lnocc_mlp_predict(blob, X, 3 * n + 17, out, opt) == L.LNOCC_OK
+    st, loss = L.lnocc_mlp_loss_grad(blob, X, Y, n, grad, opt)
+    assert st == L.LNOCC_OK
+    st, losses = L.lnocc_mlp_train(blob, adam, 0, 70, X, Y, 10 * n, n, 1e-3, 3, opt)
+    assert st == L.LNOCC_OK and len(losses) == 70
+    # a batch larger than the workspace holds, bad arguments
+    assert L.lnocc_mlp_loss_grad(blob, X, Y, 2 * n, grad, opt)[0] == L.LNOCC_ENOMEM
+    assert L.lnocc_mlp_train(blob, adam, 0, 1, X, Y, n, n, -1.0, 3, opt)[0] == L.LNOCC_EINVAL
+    assert L.lnocc_mlp_predict(blob, X + 4, n, out, opt) == L.LNOCC_EINVAL
+    assert L.lnocc_mlp_workspace_bytes(0, False)[0] == L.LNOCC_EINVAL
+    f = _fake_fragment(5, 30, 70)
+    o2 = L.make_options()
+    o2.workspace, o2.workspace_bytes = 1 << 45, L.lnocc_workspace_bytes([f], o2)[1]
+    assert L.lnocc_mlp_samples(f, o2, base, 1000, X, Y) == L.LNOCC_OK
+
+
 def test_one_hip_runtime_in_the_process():
     """The binding loads torch first, so liblnocc binds to torch's HIP runtime
     instead of mapping a second one (which would find no device)."""

@@ -123,3 +123,20 @@ def test_amplitude_symmetry_of_features():
     X = mlp.pair_features(f.B, f.eps_occ, f.eps_vir)
     Xs = X.transpose(1, 0, 3, 2, 4)
     np.testing.assert_allclose(X, Xs, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.slow
+def test_exact_t2_start_saves_no_iterations():
+    """What a T2-only starting guess can gain here: with T1 = 0, even the exact
+    converged T2 takes as many iterations as the MP2 start (the T1 build-up and
+    its coupling set the pace), while the exact pair (T1, T2) converges at
+    once.  Bounds the learned start's iteration gain on these inputs."""
+    f = make_fragment(6, 45, 120, 8000)
+    ref = occ.ccsd(f.B, f.eps_occ, f.eps_vir, conv_tol=1e-10)
+    assert ref.converged
+    exact_t2 = occ.ccsd(f.B, f.eps_occ, f.eps_vir, conv_tol=1e-10, t1=np.zeros_like(ref.t1),
+                        t2=ref.t2)
+    both = occ.ccsd(f.B, f.eps_occ, f.eps_vir, conv_tol=1e-10, t1=ref.t1, t2=ref.t2)
+    assert exact_t2.n_iter >= ref.n_iter - 1
+    assert both.n_iter <= 2
+    assert abs(exact_t2.e_ccsd - ref.e_ccsd) < 1e-9
