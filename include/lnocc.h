@@ -65,6 +65,15 @@ typedef enum {
                            to the MP2 start when that start is worse */
 } lnocc_guess_t;
 
+/* How the particle-particle ladder gets its (ac|bd) integrals (Eq. 27a over Q). */
+typedef enum {
+  LNOCC_LADDER_AUTO = 0,      /* stored when that needs at most 32 GiB of workspace */
+  LNOCC_LADDER_STORED = 1,    /* bare (ac|bd) (b <= a blocks) and (kc|bd) formed once per
+                                 solve; the T1 dressing enters as o^3 v^3 correction terms */
+  LNOCC_LADDER_ON_THE_FLY = 2 /* T1-dressed (ac|bd) formed from B~_vv in every iteration,
+                                 ladder_chunk_bytes at a time (no v^4 storage) */
+} lnocc_ladder_mode_t;
+
 /* One fragment problem and its results. */
 typedef struct lnocc_fragment_t {
   int32_t nocc, nvir, naux;  /* active occupied, active virtual, auxiliary functions */
@@ -109,7 +118,7 @@ typedef struct lnocc_options_t {
                                 spread the fragments in flight over n streams of default
                                 priority created for the call, so that small fragments run
                                 concurrently */
-  int32_t reserved2;
+  int32_t ladder_mode;       /* lnocc_ladder_mode_t */
   const float *mlp;          /* device model blob (LNOCC_MLP_BLOB floats) for LNOCC_GUESS_MLP */
 } lnocc_options_t;
 

@@ -42,7 +42,9 @@ int check_options(const lnocc_options_t *opt) {
     return LNOCC_EINVAL;
   if (opt->max_iter < 0 || opt->diis_space < 1 || opt->diis_space > 16 || opt->diis_start < 1 ||
       opt->triples_batch < 0 || opt->batch_slots < 0 || opt->batch_streams < 0 ||
-      opt->batch_streams > 64 || !(opt->level_shift >= 0.0) || !std::isfinite(opt->level_shift))
+      opt->batch_streams > 64 || opt->ladder_mode < LNOCC_LADDER_AUTO ||
+      opt->ladder_mode > LNOCC_LADDER_ON_THE_FLY || !(opt->level_shift >= 0.0) ||
+      !std::isfinite(opt->level_shift))
     return LNOCC_EINVAL;
   return LNOCC_OK;
 }

@@ -36,6 +36,12 @@ struct Layout {
   double *chunk;                    // (ac|bd)~ for chunk_a values of a: [a][b][c][d]
   double *Tsa, *SA;                 // ladder rows [t + t^T ; t - t^T] and results [o^2][v][v]
   double *Btvv_lp;                  // B~_vv in the precision of the ladder products
+  // stored ladder (bare integrals formed once per solve)
+  bool lstore = false;
+  void *Lst = nullptr;              // (ac|bd) blocks [a in block][c][b < a1][d], ladder precision
+  double *Gkc = nullptr;            // (kc|bd) [k][c][b][d]
+  double *Zl = nullptr, *Yl = nullptr, *Wl = nullptr;   // [ij][k][b], [ij][k][b], [ij][k][l]
+  double *Bvv_lp = nullptr;         // bare B_vv in the ladder precision
   double *t2_lp;                    // t2 in the precision of the (T) products
   Prec lp;                          // precision of the ladder and (T) products
   int lpt;                          // its element type: 0 double, 1 float, 2 bf16

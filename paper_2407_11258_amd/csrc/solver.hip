@@ -131,9 +131,30 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.u = A.d(oovv); L.R1 = A.d(ov); L.R2 = A.d(oovv); L.S = A.d(oovv); L.Xc = A.d(oovv);
   L.Goovv = A.d(oovv); L.Cint = A.d(oovv); L.Dint = A.d(oovv);
   L.Wkl = A.d(oo * oo); L.Y1 = A.d(X * ov); L.Z1 = A.d(X * ov);
-  L.chunk = A.d(L.chunk_a * vvv);
   L.Tsa = A.d(oovv); L.SA = A.d(oovv);
-  L.Btvv_lp = (L.lp != Prec::F64) ? A.d(X * vv) : nullptr;
+  {  // stored ladder: every b <= a block of the bare (ac|bd) plus the correction tensors
+    const size_t esz = L.lp == Prec::F64 ? 8 : (L.lp == Prec::F32 ? 4 : 2);
+    int64_t blk = 0;
+    for (int64_t a0 = 0; a0 < v; a0 += L.chunk_a) {
+      const int64_t na = std::min<int64_t>(L.chunk_a, v - a0);
+      blk += na * (a0 + na) * vv;
+    }
+    const size_t need = (size_t)blk * esz + (size_t)(o * vvv + 2 * o * oo * v + oo * oo) * 8 +
+                        (L.lp != Prec::F64 ? (size_t)X * vv * esz : 0);
+    L.lstore = opt.ladder_mode == LNOCC_LADDER_STORED ||
+               (opt.ladder_mode == LNOCC_LADDER_AUTO && need <= ((size_t)32 << 30));
+    if (L.lstore) {
+      L.Lst = A.d((int64_t)(((size_t)blk * esz + 7) / 8));
+      L.Gkc = A.d(o * vvv);
+      L.Zl = A.d(oo * ov);
+      L.Yl = A.d(oo * ov);
+      L.Wl = A.d(oo * oo);
+      L.Bvv_lp = (L.lp != Prec::F64) ? A.d((int64_t)(((size_t)X * vv * esz + 7) / 8)) : nullptr;
+    } else {
+      L.chunk = A.d(L.chunk_a * vvv);
+      L.Btvv_lp = (L.lp != Prec::F64) ? A.d(X * vv) : nullptr;
+    }
+  }
   L.dx = A.d(L.diis_m * N); L.de = A.d(L.diis_m * N);
   if (opt.guess == LNOCC_GUESS_MLP) {
     L.nunique = o * (o + 1) / 2 * vv;
@@ -201,6 +222,41 @@ int fock_two_electron(const Layout &L, const double *Boo, const double *Bov, con
   return LNOCC_OK;
 }
 
+size_t ladder_esz(const Layout &L) {
+  return L.lp == Prec::F64 ? 8 : (L.lp == Prec::F32 ? 4 : 2);
+}
+
+// Bare (ac|bd) for every block of a (b < a1 of the block) and (kc|bd), formed
+// once per solve when the ladder is stored.
+int build_stored_ladder(const Layout &L, hipStream_t s) {
+  const int64_t o = L.dm.o, v = L.dm.v, X = L.dm.X, ov = o * v, vv = v * v, vvv = vv * v;
+  const size_t esz = ladder_esz(L);
+  const char *bvv = (const char *)L.Bvv;
+  if (L.lp != Prec::F64) {
+    LN_TRY(convert(L.Bvv, X * vv, L.Bvv_lp, L.lpt, s));
+    bvv = (const char *)L.Bvv_lp;
+  }
+  char *dst = (char *)L.Lst;
+  for (int64_t a0 = 0; a0 < v; a0 += L.chunk_a) {
+    const int64_t na = std::min<int64_t>(L.chunk_a, v - a0), a1 = a0 + na;
+    GemmDesc d = DESC(na * v, v, a1 * v, v, (double *)dst, a1 * vv, v, vv, 1, 0.0);
+    SEG(d, X, 1, 1.0, OP((const double *)(bvv + a0 * v * esz), v, 1, vv, 0),
+        OP((const double *)bvv, v, 1, vv, 0));
+    d.kind = Kind::LadderBuild;
+    d.prec = L.lp;
+    d.c_type = L.lpt;
+    LN_TRY(gett(d, s));
+    dst += (size_t)na * a1 * vv * esz;
+  }
+  {  // Gkc[k][c][b][d] = (kc|bd)
+    GemmDesc d = DESC(ov, 1, vv, 1, L.Gkc, vv, 0, 1, 0, 0.0);
+    SEG(d, X, 1, 1.0, OP(L.Bov, 1, 0, ov, 0), OP(L.Bvv, 1, 0, vv, 0));
+    LN_TRY(gett(d, s));
+  }
+  (void)vvv;
+  return LNOCC_OK;
+}
+
 }  // namespace
 
 // One-off: DF split, bare one-electron operator, (ia|jb) in the layouts used.
@@ -237,6 +293,10 @@ int setup_fragment(const Layout &L, const double *B, const double *eo, const dou
     LN_TRY(gett(d, s));
   }
   LN_TRY(build_lov(L.Kov, o, v, L.Lov, s));
+  if (L.lstore) {
+    const int st2 = build_stored_ladder(L, s);
+    if (st2) return st2;
+  }
   return LNOCC_OK;
 }
 
@@ -330,30 +390,73 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
   // In the FP32 / BF16 modes B~_vv, the (ac|bd) block and the rows are stored in
   // that precision; products accumulate in FP32 per tile and SA stays FP64.
   const bool lowp = L.lp != Prec::F64;
-  const size_t esz = L.lp == Prec::F64 ? 8 : (L.lp == Prec::F32 ? 4 : 2);
-  const char *bvv = (const char *)L.Btvv;
-  if (lowp) {
-    LN_TRY(convert(L.Btvv, X * vv, L.Btvv_lp, L.lpt, s));
-    bvv = (const char *)L.Btvv_lp;
-  }
+  const size_t esz = ladder_esz(L);
   LN_TRY(pack_t(t2, o, v, L.Tsa, L.lpt, s));
-  for (int64_t a0 = 0; a0 < v; a0 += L.chunk_a) {
-    const int64_t na = std::min<int64_t>(L.chunk_a, v - a0), a1 = a0 + na;
-    GemmDesc d = DESC(na * v, v, a1 * v, v, L.chunk, vvv, v, vv, 1, 0.0);
-    SEG(d, X, 1, 1.0, OP((const double *)(bvv + a0 * v * esz), v, 1, vv, 0),
-        OP((const double *)bvv, v, 1, vv, 0));
-    d.kind = Kind::LadderBuild;
-    d.prec = L.lp;
-    d.c_type = L.lpt;
-    LN_TRY(gett(d, s));
-    // SA[r][a][b] = sum_cd Tsa[r][cd] g[a][b][cd], rows (a, b < a1) of the block
-    d = DESC(na * a1, a1, oo, 1, L.SA + a0 * v, v, 1, vv, 0, 0.0);
-    SEG(d, vv, 1, 1.0, OP(L.chunk, vvv, vv, 1, 0), OP(L.Tsa, vv, 0, 1, 0));
-    d.kind = Kind::LadderContract;
-    d.prec = L.lp;
-    LN_TRY(gett(d, s));
+  if (L.lstore) {
+    // Bare integrals: B~_ac = B_ac - sum_k t_k^a B_kc makes
+    // (ac|bd)~ = (ac|bd) - t_k^a (kc|bd) - t_l^b (ac|ld) + t_k^a t_l^b (kc|ld), so
+    // R_ij^ab = sum_cd t_ij^cd (ac|bd) - sum_k t_k^a (Z - Y)_ij,k^b - sum_k Z_ji,k^a t_k^b
+    // with Z_ij,k^b = sum_cd t_ij^cd (kc|bd), Y_ij,k^b = sum_l W_ij,kl t_l^b and
+    // W_ij,kl = sum_cd t_ij^cd (kc|ld).
+    const char *blk = (const char *)L.Lst;
+    for (int64_t a0 = 0; a0 < v; a0 += L.chunk_a) {
+      const int64_t na = std::min<int64_t>(L.chunk_a, v - a0), a1 = a0 + na;
+      GemmDesc d = DESC(na * a1, a1, oo, 1, L.SA + a0 * v, v, 1, vv, 0, 0.0);
+      SEG(d, vv, 1, 1.0, OP((const double *)blk, a1 * vv, vv, 1, 0), OP(L.Tsa, vv, 0, 1, 0));
+      d.kind = Kind::LadderContract;
+      d.prec = L.lp;
+      LN_TRY(gett(d, s));
+      blk += (size_t)na * a1 * vv * esz;
+    }
+    LN_TRY(unpack_ladder(L.SA, o, v, L.R2, s));
+    {  // Z[ij][k][b] = sum_cd t_ij^cd (kc|bd)
+      GemmDesc d = DESC(oo, 1, ov, v, L.Zl, ov, 0, v, 1, 0.0);
+      SEG(d, vv, v, 1.0, OP(t2, vv, 0, v, 1), OP(L.Gkc, vvv, v, vv, 1));
+      LN_TRY(gett(d, s));
+    }
+    {  // W[ij][k][l] = sum_cd t_ij^cd (kc|ld) ; Y[ij][k][b] = sum_l W[ij][k][l] t_l^b
+      GemmDesc d = DESC(oo, 1, oo, o, L.Wl, oo, 0, o, 1, 0.0);
+      SEG(d, vv, v, 1.0, OP(t2, vv, 0, v, 1), OP(L.Kov, ovv, v, ov, 1));
+      LN_TRY(gett(d, s));
+      d = DESC(ooo, 1, v, 1, L.Yl, v, 0, 1, 0, 0.0);
+      SEG(d, o, 1, 1.0, OP(L.Wl, o, 0, 1, 0), OP(t1, 1, 0, v, 0));
+      LN_TRY(gett(d, s));
+    }
+    {  // R2[ij][a][b] += -t1^T (Z - Y)_ij - Z_ji^T t1, batched over (i, j)
+      GemmDesc d = DESC(v, 1, v, 1, L.R2, v, 0, 1, 0, 1.0);
+      d.batch = (int)oo;
+      d.nb1 = (int)o;
+      d.c_b0 = ovv;
+      d.c_b1 = vv;
+      SEG(d, o, 1, -1.0, OP(t1, 1, 0, v, 0), OPB(OP(L.Zl, 1, 0, v, 0), oo * v, ov, 0));
+      SEG(d, o, 1, 1.0, OP(t1, 1, 0, v, 0), OPB(OP(L.Yl, 1, 0, v, 0), oo * v, ov, 0));
+      SEG(d, o, 1, -1.0, OPB(OP(L.Zl, 1, 0, v, 0), ov, oo * v, 0), OP(t1, 1, 0, v, 0));
+      LN_TRY(gett(d, s));
+    }
+  } else {
+    const char *bvv = (const char *)L.Btvv;
+    if (lowp) {
+      LN_TRY(convert(L.Btvv, X * vv, L.Btvv_lp, L.lpt, s));
+      bvv = (const char *)L.Btvv_lp;
+    }
+    for (int64_t a0 = 0; a0 < v; a0 += L.chunk_a) {
+      const int64_t na = std::min<int64_t>(L.chunk_a, v - a0), a1 = a0 + na;
+      GemmDesc d = DESC(na * v, v, a1 * v, v, L.chunk, vvv, v, vv, 1, 0.0);
+      SEG(d, X, 1, 1.0, OP((const double *)(bvv + a0 * v * esz), v, 1, vv, 0),
+          OP((const double *)bvv, v, 1, vv, 0));
+      d.kind = Kind::LadderBuild;
+      d.prec = L.lp;
+      d.c_type = L.lpt;
+      LN_TRY(gett(d, s));
+      // SA[r][a][b] = sum_cd Tsa[r][cd] g[a][b][cd], rows (a, b < a1) of the block
+      d = DESC(na * a1, a1, oo, 1, L.SA + a0 * v, v, 1, vv, 0, 0.0);
+      SEG(d, vv, 1, 1.0, OP(L.chunk, vvv, vv, 1, 0), OP(L.Tsa, vv, 0, 1, 0));
+      d.kind = Kind::LadderContract;
+      d.prec = L.lp;
+      LN_TRY(gett(d, s));
+    }
+    LN_TRY(unpack_ladder(L.SA, o, v, L.R2, s));
   }
-  LN_TRY(unpack_ladder(L.SA, o, v, L.R2, s));
   {  // hole-hole ladder: W_klij = (ki|lj)~ + sum_cd (kc|ld) t_ij^cd ; R2 += sum_kl t_kl^ab W_klij
     GemmDesc d = DESC(oo, o, oo, o, L.Wkl, ooo, o, oo, 1, 0.0);
     SEG(d, X, 1, 1.0, OP(L.Btoo, o, 1, oo, 0), OP(L.Btoo, o, 1, oo, 0));

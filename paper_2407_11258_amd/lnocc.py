@@ -27,6 +27,8 @@ LNOCC_MLP_FEATURES, LNOCC_MLP_HIDDEN, LNOCC_MLP_HEADER, LNOCC_MLP_PARAMS = 16, 2
 LNOCC_MLP_BLOB = LNOCC_MLP_HEADER + LNOCC_MLP_PARAMS
 
 PRECISIONS = {"fp64": LNOCC_FP64, "fp32": LNOCC_FP32, "bf16": LNOCC_BF16}
+LNOCC_LADDER_AUTO, LNOCC_LADDER_STORED, LNOCC_LADDER_ON_THE_FLY = 0, 1, 2
+LADDER_MODES = {"auto": 0, "stored": 1, "on_the_fly": 2}
 
 
 class lnocc_fragment_t(C.Structure):
@@ -49,7 +51,7 @@ class lnocc_options_t(C.Structure):
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("ladder_chunk_bytes", C.c_size_t), ("triples_batch", C.c_int32),
         ("batch_slots", C.c_int32), ("level_shift", C.c_double),
-        ("batch_streams", C.c_int32), ("reserved2", C.c_int32),
+        ("batch_streams", C.c_int32), ("ladder_mode", C.c_int32),
         ("mlp", C.c_void_p),
     ]
 
@@ -271,7 +273,7 @@ def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int
                  diis_space: int = 8, diis_start: int = 2, guess: int = LNOCC_GUESS_MP2,
                  ladder_chunk_bytes: int = 0, triples_batch: int = 0,
                  level_shift: float = 0.0, batch_slots: int = 0,
-                 batch_streams: int = 0, mlp=None) -> lnocc_options_t:
+                 batch_streams: int = 0, mlp=None, ladder: str = "auto") -> lnocc_options_t:
     opt = lnocc_default_options()
     opt.precision = PRECISIONS[precision]
     opt.do_triples = int(do_triples)
@@ -284,6 +286,7 @@ def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int
     opt.level_shift = level_shift
     opt.batch_slots = batch_slots
     opt.batch_streams = batch_streams
+    opt.ladder_mode = LADDER_MODES[ladder]
     if mlp is not None:
         opt.mlp = mlp if isinstance(mlp, int) else mlp.data_ptr()
     return opt

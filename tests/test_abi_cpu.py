@@ -116,10 +116,11 @@ SHAPES = [v[:3] for v in CONFIG_SHAPES.values()] + [(1, 1, 1), (2, 37, 61), (1, 
                                                     (6, 45, 100)] + [s[:3] for s in batch_shapes()[:6]]
 
 
+@pytest.mark.parametrize("ladder", ["stored", "on_the_fly"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("o,v,X", SHAPES)
-def test_launch_sequence_stays_in_bounds(validation_mode, o, v, X, precision):
-    opt = L.make_options(precision=precision)
+def test_launch_sequence_stays_in_bounds(validation_mode, o, v, X, precision, ladder):
+    opt = L.make_options(precision=precision, ladder=ladder)
     f = _fake_fragment(o, v, X)
     st, nbytes = L.lnocc_workspace_bytes([f], opt)
     assert st == L.LNOCC_OK
@@ -133,7 +134,7 @@ def test_launch_sequence_stays_in_bounds(validation_mode, o, v, X, precision):
 
 
 def test_small_ladder_blocks_and_triple_batches(validation_mode):
-    opt = L.make_options(ladder_chunk_bytes=1 << 20, triples_batch=5)
+    opt = L.make_options(ladder_chunk_bytes=1 << 20, triples_batch=5, ladder="on_the_fly")
     f = _fake_fragment(7, 53, 90)
     st, nbytes = L.lnocc_workspace_bytes([f], opt)
     opt.workspace, opt.workspace_bytes = 1 << 45, nbytes
@@ -227,6 +228,18 @@ def test_network_calls_stay_in_bounds(validation_mode):
     assert L.lnocc_mlp_samples(f, o2, base, 1000, X, Y) == L.LNOCC_OK
 
 
+def test_ladder_mode_changes_the_workspace():
+    f = _fake_fragment(16, 160, 528)
+    st_a, auto = L.lnocc_workspace_bytes([f], L.make_options())
+    st_s, stored = L.lnocc_workspace_bytes([f], L.make_options(ladder="stored"))
+    st_f, fly = L.lnocc_workspace_bytes([f], L.make_options(ladder="on_the_fly"))
+    assert st_a == st_s == st_f == L.LNOCC_OK
+    assert auto == stored > fly                 # v^4 / 2 of stored integrals fit the 32 GiB cap
+    big = _fake_fragment(32, 400, 1300)
+    assert L.lnocc_workspace_bytes([big], L.make_options())[1] == \
+        L.lnocc_workspace_bytes([big], L.make_options(ladder="on_the_fly"))[1]
+
+
 def test_one_hip_runtime_in_the_process():
     """The binding loads torch first, so liblnocc binds to torch's HIP runtime
     instead of mapping a second one (which would find no device)."""
@@ -238,7 +251,8 @@ def test_one_hip_runtime_in_the_process():
 
 def test_options_are_checked():
     f = _fake_fragment(2, 5, 9)
-    for field, bad in (("batch_streams", -1), ("batch_streams", 65), ("batch_slots", -2)):
+    for field, bad in (("batch_streams", -1), ("batch_streams", 65), ("batch_slots", -2),
+                       ("ladder_mode", 3), ("ladder_mode", -1)):
         opt = L.make_options()
         setattr(opt, field, bad)
         assert L.lnocc_workspace_bytes([f], opt)[0] == L.LNOCC_EINVAL, field

@@ -172,8 +172,9 @@ def _call(fn, f, B, eo, ev, t1, t2, conv_tol=1e-8, **kw):
 
 
 @pytest.mark.parametrize("o,v,X,seed", [(3, 13, 40, 21), (2, 37, 61, 22), (5, 9, 17, 23)])
-def test_residuals_match_oracle(o, v, X, seed):
-    say(f"residuals o={o} v={v} X={X}")
+@pytest.mark.parametrize("ladder", ["stored", "on_the_fly"])
+def test_residuals_match_oracle(o, v, X, seed, ladder):
+    say(f"residuals o={o} v={v} X={X} ladder {ladder}")
     f = make_fragment(o, v, X, seed)
     t1, t2 = _random_amplitudes(o, v, seed)
     R1o, R2o = occ.residuals(2.0 * f.B, f.eps_occ, f.eps_vir, t1, t2)
@@ -181,7 +182,7 @@ def test_residuals_match_oracle(o, v, X, seed):
     t1d, t2d = dev(t1), dev(t2)
     r1 = torch.empty((o, v), dtype=torch.float64, device=DEV)
     r2 = torch.empty((o, o, v, v), dtype=torch.float64, device=DEV)
-    opt = L.make_options()
+    opt = L.make_options(ladder=ladder)
     fs = L.make_fragment_struct(B, eo, ev, t1d, t2d, 1e-8)
     ws = L.Workspace(DEV)
     ws.attach([fs], opt)
@@ -218,7 +219,7 @@ def test_full_solve_matches_oracle(o, v, X, seed, chunk):
     t1 = torch.empty((o, v), dtype=torch.float64, device=DEV)
     t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=DEV)
     st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=1e-10,
-                   ladder_chunk_bytes=chunk)
+                   ladder_chunk_bytes=chunk, ladder="on_the_fly" if chunk else "stored")
     assert st == L.LNOCC_OK, L.lnocc_status_string(st)
     assert abs(fs.e_mp2 - ref.e_mp2) < 1e-12
     assert abs(fs.e_ccsd - ref.e_ccsd) < 1e-8
