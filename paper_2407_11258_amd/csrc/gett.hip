@@ -17,6 +17,8 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <map>
+#include <string>
 #include <vector>
 #include <cstdarg>
 #include <cstdio>
@@ -466,14 +468,18 @@ bool descriptor_ok(const GemmDesc &d, int nsplit) {
 
 static bool g_dry = false;
 
-struct Record { Kind kind; hipEvent_t start, stop; double flops; };
+struct Record { Kind kind; hipEvent_t start, stop; double flops; std::string shape; };
 static bool g_profile = false;
 static std::vector<Record> g_records;
 
 void profile_enable(bool on) { g_profile = on; }
 
+// LNOCC_PROFILE_DUMP=1: profile_collect also prints every contraction shape
+// with its launch count, time and rate, largest time first.
 void profile_collect(KindStats out[(int)Kind::Count]) {
   for (int k = 0; k < (int)Kind::Count; ++k) out[k] = KindStats{0, 0.0, 0.0};
+  const bool dump = std::getenv("LNOCC_PROFILE_DUMP") != nullptr;
+  std::map<std::string, KindStats> by_shape;
   for (const Record &r : g_records) {
     float ms = 0.f;
     (void)hipEventSynchronize(r.stop);
@@ -482,10 +488,24 @@ void profile_collect(KindStats out[(int)Kind::Count]) {
     k.launches += 1;
     k.ms += ms;
     k.flops += r.flops;
+    if (dump) {
+      KindStats &b = by_shape[r.shape];
+      b.launches += 1;
+      b.ms += ms;
+      b.flops += r.flops;
+    }
     (void)hipEventDestroy(r.start);
     (void)hipEventDestroy(r.stop);
   }
   g_records.clear();
+  if (dump) {
+    std::vector<std::pair<std::string, KindStats>> v(by_shape.begin(), by_shape.end());
+    std::sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.second.ms > b.second.ms; });
+    for (const auto &e : v)
+      std::fprintf(stderr, "lnocc-prof %9.3f ms %6lld x %7.2f TF/s  %s\n", e.second.ms,
+                   (long long)e.second.launches, e.second.flops / (e.second.ms * 1e9),
+                   e.first.c_str());
+  }
 }
 bool dry_run() { return g_dry; }
 void set_dry_run(bool on) { g_dry = on; }
@@ -646,7 +666,21 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
     (void)hipEventRecord(ev[1], stream);
     double flops = 0.0;
     for (int s = 0; s < d.nseg; ++s) flops += 2.0 * d.M * (double)d.N * d.seg[s].K;
-    g_records.push_back(Record{d.kind, ev[0], ev[1], flops * d.batch});
+    std::string shape;
+    if (std::getenv("LNOCC_PROFILE_DUMP")) {
+      char buf[512];
+      const GSegment &g = d.seg[0];
+      std::snprintf(buf, sizeof(buf),
+                    "k%d p%d M%d/%d N%d/%d K%d/%d seg%d b%d | A %lld %lld %lld %lld | B %lld %lld "
+                    "%lld %lld | C %lld %lld %lld %lld | tile %dx%d split %d",
+                    (int)d.kind, (int)d.prec, d.M, d.Mi, d.N, d.Ni, g.K, g.Ki, d.nseg, d.batch,
+                    (long long)g.a.s_ro, (long long)g.a.s_ri, (long long)g.a.s_ko,
+                    (long long)g.a.s_ki, (long long)g.b.s_ro, (long long)g.b.s_ri,
+                    (long long)g.b.s_ko, (long long)g.b.s_ki, (long long)d.c_mo,
+                    (long long)d.c_mi, (long long)d.c_no, (long long)d.c_ni, BMx, BNx, nsplit);
+      shape = buf;
+    }
+    g_records.push_back(Record{d.kind, ev[0], ev[1], flops * d.batch, shape});
   }
   return err;
 }
