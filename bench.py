@@ -111,6 +111,8 @@ def roofline(prof: dict, precision: str, workload: str) -> dict:
     achieved = d["flops"] / d["ms"] / 1e9 if d["ms"] > 0 else 0.0
     # ladder and (T) products run in the chosen precision; every other contraction in FP64
     kprec = precision if dominant in ("ladder_build", "ladder_contract", "triples_w") else "fp64"
+    if dominant == "mlp":
+        kprec = "fp32"
     peak = PEAKS_TFLOPS[kprec]
     traffic = None
     tpath = ROOT / "profiles" / "traffic.json"

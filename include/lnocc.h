@@ -222,6 +222,8 @@ int lnocc_contract(const lnocc_contract_t *desc, void *stream);
  *   2 ladder contraction  sum_cd t_ij^cd (ac|bd)
  *   3 (T) W contraction   (SI Sec. S1) for batches of unique triples
  *   4 products of the learned-guess network (forward and backward)
+ *   5 o^3 v^3 ring products of the CCSD residual (exchange and Coulomb rings,
+ *     the T1 terms of the stored ladder)
  * flops counts 2 M N K per product term (the algorithmic count). */
 typedef struct lnocc_kernel_stats_t {
   int64_t launches;
@@ -229,7 +231,7 @@ typedef struct lnocc_kernel_stats_t {
   double flops;
 } lnocc_kernel_stats_t;
 
-#define LNOCC_KERNEL_CLASSES 5
+#define LNOCC_KERNEL_CLASSES 6
 void lnocc_profile_enable(int on);
 void lnocc_profile_collect(lnocc_kernel_stats_t out[LNOCC_KERNEL_CLASSES]);
 

@@ -25,7 +25,8 @@ enum class Kind : int {
   LadderContract = 2, // R2 += sum_cd t_ij^cd (ac|bd)~
   TriplesW = 3,       // W_ijk^abc for a batch of unique triples
   Mlp = 4,            // learned-guess network layers and their gradients (FP32 only)
-  Count = 5
+  Ring = 5,           // o^3 v^3 ring terms of the CCSD residual (and the ladder's T1 terms)
+  Count = 6
 };
 
 // Division by a runtime-invariant divisor via multiply-high (Granlund and

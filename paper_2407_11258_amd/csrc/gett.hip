@@ -387,17 +387,39 @@ __global__ __launch_bounds__(C::T) void gett_kernel(GemmDesc d, int tiles_m, int
 }
 
 // C[m, n] = sum_s partial[s][m][n] (+ beta C), summed in split order.
+__device__ inline void splitk_store(const GemmDesc &d, int64_t e, double acc) {
+  const int m = (int)(e / d.N), n = (int)(e % d.N);
+  const int64_t off = (int64_t)(m / d.Mi) * d.c_mo + (int64_t)(m % d.Mi) * d.c_mi +
+                      (int64_t)(n / d.Ni) * d.c_no + (int64_t)(n % d.Ni) * d.c_ni;
+  store_out(d, d.c, off, acc);
+}
 __global__ void splitk_reduce(GemmDesc d, int nsplit) {
   const int64_t total = (int64_t)d.M * d.N;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     double acc = 0.0;
     for (int s = 0; s < nsplit; ++s) acc += d.splitk[s * total + e];
-    const int m = (int)(e / d.N), n = (int)(e % d.N);
-    const int64_t off = (int64_t)(m / d.Mi) * d.c_mo + (int64_t)(m % d.Mi) * d.c_mi +
-                        (int64_t)(n / d.Ni) * d.c_no + (int64_t)(n % d.Ni) * d.c_ni;
-    store_out(d, d.c, off, acc);
+    splitk_store(d, e, acc);
   }
+}
+// Many splits of a small output: 32 lanes share the splits of each of 8
+// outputs per block (strided partial sums, then a fixed-order tree).
+constexpr int kRedLanes = 32, kRedOuts = 8;
+__global__ void splitk_reduce_wide(GemmDesc d, int nsplit) {
+  __shared__ double sm[kRedOuts][kRedLanes + 1];
+  const int64_t total = (int64_t)d.M * d.N;
+  const int lane = threadIdx.x % kRedLanes, oi = threadIdx.x / kRedLanes;
+  const int64_t e = (int64_t)blockIdx.x * kRedOuts + oi;
+  double acc = 0.0;
+  if (e < total)
+    for (int s = lane; s < nsplit; s += kRedLanes) acc += d.splitk[s * total + e];
+  sm[oi][lane] = acc;
+  __syncthreads();
+  for (int w = kRedLanes / 2; w > 0; w >>= 1) {
+    if (lane < w) sm[oi][lane] += sm[oi][lane + w];
+    __syncthreads();
+  }
+  if (lane == 0 && e < total) splitk_store(d, e, sm[oi][0]);
 }
 
 }  // namespace
@@ -529,6 +551,12 @@ void launch_kind(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t
       hipLaunchKernelGGL((gett_kernel<M, C, 2>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
     case Kind::TriplesW:
       hipLaunchKernelGGL((gett_kernel<M, C, 3>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
+    case Kind::Ring:   // FP64 only
+      if constexpr (std::is_same<M, ModeF64>::value)
+        hipLaunchKernelGGL((gett_kernel<M, C, 5>), grid, dim3(C::T), 0, stream, d, tiles_m, sps);
+      else
+        hipLaunchKernelGGL((gett_kernel<M, C, 0>), grid, dim3(C::T), 0, stream, d, tiles_m, sps);
+      break;
     case Kind::Mlp:
       if constexpr (std::is_same<M, ModeF32>::value) {
         hipLaunchKernelGGL((gett_kernel<M, C, 4>), grid, dim3(C::T), 0, stream, d, tiles_m, sps);
@@ -615,10 +643,13 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   const int64_t cap = g_splitk ? (int64_t)(g_splitk_elems / ((size_t)d.M * d.N)) : 0;
   if (d.batch == 1 && cap >= 2) {
     if (small) {
-      const int64_t target = 2048;
+      // single-wave tiles hide latency only by numbers: up to 16 workgroups per
+      // CU for outputs of a few tiles with long K (their partial sums are small)
+      const bool tiny = (int64_t)d.M * d.N <= 4096;
+      const int64_t target = tiny ? 4096 : 2048;
       if (tiles < target && slices >= 8) {
         int64_t want = (target + tiles - 1) / tiles;
-        want = std::min<int64_t>({want, (int64_t)slices / 4, cap, 1024});
+        want = std::min<int64_t>({want, (int64_t)slices / 4, cap, tiny ? (int64_t)8192 : 1024});
         if (want >= 2) nsplit = (int)want;
       }
     } else if (slices >= 16 && tiles < 4 * kCUs) {
@@ -659,7 +690,11 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   if (err == hipSuccess && nsplit > 1) {
     const int64_t total = (int64_t)d.M * d.N;
     const int blocks = (int)std::min<int64_t>(4096, (total + 255) / 256);
-    hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, stream, d, nsplit);
+    if (nsplit > 64)
+      hipLaunchKernelGGL(splitk_reduce_wide, dim3((unsigned)((total + kRedOuts - 1) / kRedOuts)),
+                         dim3(kRedLanes * kRedOuts), 0, stream, d, nsplit);
+    else
+      hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, stream, d, nsplit);
     err = hipGetLastError();
   }
   if (g_profile) {

@@ -412,6 +412,7 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     {  // Z[ij][k][b] = sum_cd t_ij^cd (kc|bd)
       GemmDesc d = DESC(oo, 1, ov, v, L.Zl, ov, 0, v, 1, 0.0);
       SEG(d, vv, v, 1.0, OP(t2, vv, 0, v, 1), OP(L.Gkc, vvv, v, vv, 1));
+      d.kind = Kind::Ring;
       LN_TRY(gett(d, s));
     }
     {  // W[ij][k][l] = sum_cd t_ij^cd (kc|ld) ; Y[ij][k][b] = sum_l W[ij][k][l] t_l^b
@@ -478,9 +479,11 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
   {
     GemmDesc d = DESC(ov, v, ov, v, L.Cint, vv, v, ovv, 1, 1.0);
     SEG(d, ov, v, -0.5, OP(t2, vv, v, ovv, 1), OP(L.Q2, ovv, v, vv, 1));
+    d.kind = Kind::Ring;
     LN_TRY(gett(d, s));
     d = DESC(ov, v, ov, v, L.Xc, ovv, v, vv, 1, 0.0);
     SEG(d, ov, v, 1.0, OP(L.Cint, vv, v, ovv, 1), OP(t2, vv, v, ovv, 1));
+    d.kind = Kind::Ring;
     LN_TRY(gett(d, s));
   }
   // Coulomb-type ring: Dint_iakc = 2 (ai|kc)~ - (ki|ac)~ + 1/2 sum_ld u_il^ad L_ldkc ;
@@ -492,9 +495,11 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     LN_TRY(sub_oovv_into_dint(L.Goovv, o, v, L.Dint, s));
     d = DESC(ov, v, ov, 1, L.Dint, ovv, ov, 1, 0, 1.0);
     SEG(d, ov, v, 0.5, OP(L.u, ovv, v, vv, 1), OP(L.Lov, 1, 0, ovv, ov));
+    d.kind = Kind::Ring;
     LN_TRY(gett(d, s));
     d = DESC(ov, v, ov, v, L.S, ovv, v, vv, 1, 0.0);
     SEG(d, ov, v, 0.5, OP(L.Dint, ovv, ov, v, 1), OP(L.u, ovv, v, vv, 1));
+    d.kind = Kind::Ring;
     LN_TRY(gett(d, s));
   }
   // Fock-type terms: F'_bc = F~_bc - sum_kld u_kl^bd (ld|kc), F'_kj = F~_kj + sum_lcd u_lj^cd (kd|lc)
