@@ -120,10 +120,14 @@ typedef struct lnocc_options_t {
                                 concurrently */
   int32_t ladder_mode;       /* lnocc_ladder_mode_t */
   const float *mlp;          /* device model blob (LNOCC_MLP_BLOB floats) for LNOCC_GUESS_MLP */
+  int32_t graphs;            /* nonzero: the residual evaluation of each CCSD iteration is
+                                captured once per solve as a HIP graph and replayed (not while
+                                launch timing is enabled) */
+  int32_t reserved3;
 } lnocc_options_t;
 
 /* Fills *opt with defaults: FP64, MP2 guess, triples on, max_iter 100,
- * DIIS space 8 from iteration 2, default stream, no workspace. */
+ * DIIS space 8 from iteration 2, graphs on, default stream, no workspace. */
 void lnocc_default_options(lnocc_options_t *opt);
 
 /* Human-readable name of a status code; never NULL. */

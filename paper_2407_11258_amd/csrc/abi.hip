@@ -211,6 +211,7 @@ void lnocc_default_options(lnocc_options_t *opt) {
   opt->max_iter = 100;
   opt->diis_space = 8;
   opt->diis_start = 2;
+  opt->graphs = 1;
 }
 
 const char *lnocc_status_string(int status) {

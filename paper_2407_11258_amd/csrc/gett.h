@@ -91,6 +91,7 @@ void install_splitk_scratch(double *p, size_t elems);
 // events on its stream; collect() waits for them and sums per Kind.
 struct KindStats { int64_t launches; double ms; double flops; };
 void profile_enable(bool on);
+bool profile_enabled();
 void profile_collect(KindStats out[(int)Kind::Count]);   // also clears
 
 // Address guard.  While a region list is installed (per host thread), gett()

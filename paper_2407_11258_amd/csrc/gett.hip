@@ -495,6 +495,7 @@ static bool g_profile = false;
 static std::vector<Record> g_records;
 
 void profile_enable(bool on) { g_profile = on; }
+bool profile_enabled() { return g_profile; }
 
 // LNOCC_PROFILE_DUMP=1: profile_collect also prints every contraction shape
 // with its launch count, time and rate, largest time first.

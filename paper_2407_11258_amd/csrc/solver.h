@@ -138,9 +138,13 @@ struct CcsdRun {
   mutable int polls = 0;
   bool mlp_check = false;      // the first step from the learned start is still to be judged
   double r_mp2 = 0.0;          // first step norm from the MP2 start
+  hipGraphExec_t graph = nullptr;   // captured residual evaluation (replayed per iteration)
 
   CcsdRun(const Layout &L, const Inputs &in, const lnocc_options_t &opt, hipStream_t s,
           Readback &rb);
+  ~CcsdRun();
+  CcsdRun(const CcsdRun &) = delete;
+  CcsdRun &operator=(const CcsdRun &) = delete;
   int poll() const;            // 1 landed, 0 pending, < 0 error
   hipError_t wait() const;
   int begin();
@@ -155,6 +159,7 @@ struct CcsdRun {
  private:
   hipError_t mark();
   int learned_start();
+  int residuals();             // eager, or through the captured graph
 };
 
 }  // namespace lnocc

@@ -608,6 +608,44 @@ CcsdRun::CcsdRun(const Layout &L_, const Inputs &in_, const lnocc_options_t &opt
     : L(&L_), in(in_), opt(opt_), s(s_), rb(&rb_), host(rb_.host),
       G((size_t)L_.diis_m * L_.diis_m, 0.0) {}
 
+CcsdRun::~CcsdRun() {
+  if (graph) (void)hipGraphExecDestroy(graph);
+}
+
+// The residual evaluation enqueues the same ~100 launches with the same
+// arguments in every iteration of a solve (only the amplitude values change),
+// so it is captured once and replayed.  It records no memset (copies only).
+int CcsdRun::residuals() {
+  if (!opt.graphs || dry_run() || profile_enabled())
+    return ccsd_residuals(*L, in.t1, in.t2, s);
+  if (!graph) {   // captured on a stream of its own (the caller's may be the null stream)
+    hipStream_t cs = nullptr;
+    LN_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      LN_TRY(e);
+    }
+    const int st = ccsd_residuals(*L, in.t1, in.t2, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    LN_TRY(e);
+    const hipError_t e2 = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+      graph = nullptr;
+      LN_TRY(e2);
+    }
+  }
+  LN_TRY(hipGraphLaunch(graph, s));
+  return LNOCC_OK;
+}
+
 hipError_t CcsdRun::mark() { return dry_run() ? hipSuccess : hipEventRecord(rb->ev, s); }
 
 int CcsdRun::poll() const {
@@ -676,7 +714,7 @@ int CcsdRun::enqueue_iteration() {
   install_splitk_scratch(L->splitk, (size_t)L->splitk_elems);
   const int64_t o = L->dm.o, v = L->dm.v, N = L->namp;
   ++it;
-  int st = ccsd_residuals(*L, in.t1, in.t2, s);
+  int st = residuals();
   if (st) return st;
   const int m = L->diis_m;
   // (a learned start begins with the MP2 start's pair already in the subspace)

@@ -52,7 +52,7 @@ class lnocc_options_t(C.Structure):
         ("ladder_chunk_bytes", C.c_size_t), ("triples_batch", C.c_int32),
         ("batch_slots", C.c_int32), ("level_shift", C.c_double),
         ("batch_streams", C.c_int32), ("ladder_mode", C.c_int32),
-        ("mlp", C.c_void_p),
+        ("mlp", C.c_void_p), ("graphs", C.c_int32), ("reserved3", C.c_int32),
     ]
 
 
@@ -273,7 +273,8 @@ def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int
                  diis_space: int = 8, diis_start: int = 2, guess: int = LNOCC_GUESS_MP2,
                  ladder_chunk_bytes: int = 0, triples_batch: int = 0,
                  level_shift: float = 0.0, batch_slots: int = 0,
-                 batch_streams: int = 0, mlp=None, ladder: str = "auto") -> lnocc_options_t:
+                 batch_streams: int = 0, mlp=None, ladder: str = "auto",
+                 graphs: bool = True) -> lnocc_options_t:
     opt = lnocc_default_options()
     opt.precision = PRECISIONS[precision]
     opt.do_triples = int(do_triples)
@@ -287,6 +288,7 @@ def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int
     opt.batch_slots = batch_slots
     opt.batch_streams = batch_streams
     opt.ladder_mode = LADDER_MODES[ladder]
+    opt.graphs = int(bool(graphs))
     if mlp is not None:
         opt.mlp = mlp if isinstance(mlp, int) else mlp.data_ptr()
     return opt

@@ -347,3 +347,22 @@ def test_restart_from_converged_amplitudes():
                      guess=L.LNOCC_GUESS_USER)
     assert st2 == L.LNOCC_OK and fs2.n_iter == 1
     assert abs(fs2.e_ccsd - fs.e_ccsd) < 1e-10 and abs(fs2.e_t - fs.e_t) < 1e-10
+
+
+@pytest.mark.parametrize("o,v,X,seed,precision", [(4, 20, 72, 0, "fp64"), (6, 45, 100, 5, "fp32")])
+def test_graph_replay_equals_eager(o, v, X, seed, precision):
+    """The residual evaluation captured once as a HIP graph and replayed in
+    every iteration (with the eager Jacobi / DIIS work between replays) gives
+    bit-for-bit the eager solve."""
+    say(f"graph replay o={o} v={v} {precision}")
+    f = make_fragment(o, v, X, seed)
+    B, eo, ev = _fragment_on_device(f)
+    out = []
+    for graphs in (False, True, True):
+        t1 = torch.empty((o, v), dtype=torch.float64, device=DEV)
+        t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=DEV)
+        st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=1e-9,
+                       precision=precision, graphs=graphs)
+        assert st == L.LNOCC_OK
+        out.append((fs.e_ccsd, fs.e_t, fs.n_iter, host(t2).tobytes()))
+    assert out[0] == out[1] == out[2]
