@@ -89,6 +89,9 @@ def parse_args():
     ap.add_argument("--compare-fp64", type=int, default=1,
                     help="also time the plain FP64 path (single: same steps; batch: 64 "
                          "sequential solves)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="tune tile shapes and split counts during the warmup (plans kept for "
+                         "the timed steps)")
     ap.add_argument("--batch-slots", type=int, default=4)
     ap.add_argument("--batch-streams", type=int, default=4)
     ap.add_argument("--conv-tol", type=float, default=1e-8)
@@ -148,7 +151,8 @@ def run_single(args, L, torch) -> dict:
 
     def timed(precision: str, steps: int, warmup: int):
         opt = L.make_options(precision=precision, level_shift=args.level_shift,
-                             diis_start=args.diis_start, max_iter=args.max_iter)
+                             diis_start=args.diis_start, max_iter=args.max_iter,
+                             autotune=bool(args.autotune))
         fs = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
         ws.attach([fs], opt)
 
@@ -178,7 +182,8 @@ def run_single(args, L, torch) -> dict:
            "config": {"workload": args.workload, "nocc": o, "nvir": v, "naux": X, "seed": seed,
                       "precision": args.precision, "conv_tol": args.conv_tol,
                       "level_shift": args.level_shift, "diis_start": args.diis_start,
-                      "ccsd_iterations": fs.n_iter, "status": fs.status},
+                      "autotune": bool(args.autotune), "ccsd_iterations": fs.n_iter,
+                      "status": fs.status},
            "e_ccsd": fs.e_ccsd}
     # (T) alone on the converged amplitudes (the solves above already warmed it up)
     ft = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)

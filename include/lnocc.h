@@ -123,7 +123,10 @@ typedef struct lnocc_options_t {
   int32_t graphs;            /* nonzero: the residual evaluation of each CCSD iteration is
                                 captured once per solve as a HIP graph and replayed (not while
                                 launch timing is enabled) */
-  int32_t reserved3;
+  int32_t autotune;          /* nonzero: before the first iteration of a solve whose contraction
+                                shapes have no tuned plan yet, time every tile / split
+                                candidate on one residual evaluation (and on the first (T)
+                                batch) and keep the fastest per shape for the process */
 } lnocc_options_t;
 
 /* Fills *opt with defaults: FP64, MP2 guess, triples on, max_iter 100,
@@ -308,6 +311,15 @@ int lnocc_mlp_loss_grad(const float *blob, const float *X, const float *Y, int64
 int lnocc_mlp_train(float *blob, float *adam, int64_t step0, int32_t nsteps, const float *X,
                     const float *Y, int64_t n, int32_t batch, float lr, uint64_t seed,
                     double *losses, const lnocc_options_t *opt);
+
+/* ---- autotuning ---------------------------------------------------------------
+ * Tuned plans (tile shape and split count per contraction shape) are shared by
+ * the whole process.  Save / load them as text; returns the number of plans or
+ * -1 when the file cannot be written / read.  Clearing returns to the built-in
+ * heuristics. */
+int lnocc_autotune_save(const char *path);
+int lnocc_autotune_load(const char *path);
+void lnocc_autotune_clear(void);
 
 /* ---- validation mode -------------------------------------------------------
  * on != 0: every later call runs its host logic and launch sequence without

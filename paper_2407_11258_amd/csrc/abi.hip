@@ -256,7 +256,7 @@ int lnocc_fragment_ccsd(lnocc_fragment_t *f, const lnocc_options_t *opt) {
   Outputs out;
   st = run_ccsd(L, in, *opt, out, s);
   if (st >= 0 && opt->do_triples) {
-    const int st2 = run_triples(L, in, out, s);
+    const int st2 = run_triples(L, in, out, s, opt->autotune != 0);
     if (st2 < 0) st = st2;
   }
   if (st < 0) dsync(s);
@@ -279,7 +279,7 @@ int lnocc_fragment_triples(lnocc_fragment_t *f, const lnocc_options_t *opt) {
   Inputs in{f->B, f->eps_occ, f->eps_vir, f->t1, f->t2, f->conv_tol};
   st = setup_fragment(L, f->B, f->eps_occ, f->eps_vir, false, s);
   Outputs out;
-  if (!st) st = run_triples(L, in, out, s);
+  if (!st) st = run_triples(L, in, out, s, opt->autotune != 0);
   if (st < 0) dsync(s);
   f->e_t = out.e_t;
   return finish(f, st);
@@ -615,6 +615,10 @@ int lnocc_mlp_train(float *blob, float *adam, int64_t step0, int32_t nsteps, con
 extern "C" {
 
 const char *lnocc_last_error(void) { return last_error(); }
+
+int lnocc_autotune_save(const char *path) { return path ? tune_save(path) : -1; }
+int lnocc_autotune_load(const char *path) { return path ? tune_load(path) : -1; }
+void lnocc_autotune_clear(void) { tune_clear(); }
 
 void lnocc_set_validation_mode(int on) { set_dry_run(on != 0); }
 

@@ -115,6 +115,23 @@ void note_error(const char *fmt, ...);
 const char *last_error();
 void clear_error();
 
+// Autotuning of tile shape and split count per contraction shape.
+// tune_candidate(c) for c < tune_candidates() makes every later launch use
+// candidate c and time it; tune_candidate(-1) stops; tune_commit() waits for
+// those launches and stores, per shape, the fastest candidate's choice (used
+// by every later launch of that shape; returns the number of shapes).  A probe
+// pass (tune_probe_begin/end) launches nothing and counts shapes without a
+// plan.  Plans are process-wide; save/load use a text file.
+int tune_candidates();
+void tune_candidate(int c);
+void tune_probe_begin();
+int tune_probe_end();
+int tune_commit();
+size_t tune_plans();
+int tune_save(const char *path);
+int tune_load(const char *path);
+void tune_clear();
+
 // Enqueue on `stream`.  Returns hipSuccess or the launch error.
 hipError_t gett(const GemmDesc &d, hipStream_t stream);
 

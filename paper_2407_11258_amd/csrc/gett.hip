@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <type_traits>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 #include <cstdarg>
@@ -604,6 +605,113 @@ void install_splitk_scratch(double *p, size_t elems) {
   g_splitk_elems = p ? elems : 0;
 }
 
+// ---------------------------------------------------------------- autotuning
+// Candidate c = (tile, split rule): tiles 128x128, 128x80, 128x64, 32x32; split
+// rules: the cost-model split, no split, twice the cost-model split.  While a
+// candidate is active every launch is timed with events under its shape key;
+// tune_commit() keeps, per key, the fastest candidate's (tile, split count),
+// which later launches of that shape use instead of the heuristic.
+namespace {
+constexpr int kTileCands = 4, kSplitRules = 3;
+struct TilePlan { int tile; int nsplit; };
+std::mutex g_plan_mu;
+std::map<std::string, TilePlan> g_plans;
+thread_local int g_cand = -1;          // -1 off, kProbeCand: keys only
+constexpr int kProbeCand = 1 << 20;
+thread_local int g_unplanned = 0;      // keys seen by a probe pass without a plan
+struct TuneRec { std::string key; int cand; TilePlan plan; hipEvent_t a, b; };
+thread_local std::vector<TuneRec> g_tune;
+
+std::string plan_key(const GemmDesc &d) {
+  std::string k;
+  char buf[192];
+  std::snprintf(buf, sizeof(buf), "%d.%d.%d|%d.%d.%d.%d|%d.%d.%d.%d.%d", (int)d.kind, (int)d.prec,
+                d.c_type, d.M, d.Mi, d.N, d.Ni, d.batch, d.nb1, d.table ? 1 : 0,
+                d.beta == 0.0 ? 0 : 1, d.nseg);
+  k += buf;
+  for (int s = 0; s < d.nseg; ++s) {
+    const GSegment &g = d.seg[s];
+    std::snprintf(buf, sizeof(buf), "|%d.%d:%lld.%lld.%lld.%lld:%lld.%lld.%lld.%lld", g.K, g.Ki,
+                  (long long)g.a.s_ro, (long long)g.a.s_ri, (long long)g.a.s_ko,
+                  (long long)g.a.s_ki, (long long)g.b.s_ro, (long long)g.b.s_ri,
+                  (long long)g.b.s_ko, (long long)g.b.s_ki);
+    k += buf;
+  }
+  std::snprintf(buf, sizeof(buf), "|%lld.%lld.%lld.%lld", (long long)d.c_mo, (long long)d.c_mi,
+                (long long)d.c_no, (long long)d.c_ni);
+  k += buf;
+  return k;
+}
+}  // namespace
+
+int tune_candidates() { return kTileCands * kSplitRules; }
+void tune_candidate(int c) { g_cand = c; }
+void tune_probe_begin() {
+  g_cand = kProbeCand;
+  g_unplanned = 0;
+}
+int tune_probe_end() {
+  g_cand = -1;
+  return g_unplanned;
+}
+
+int tune_commit() {
+  std::map<std::string, std::map<int, std::pair<double, TilePlan>>> t;
+  for (TuneRec &r : g_tune) {
+    float ms = 0.f;
+    (void)hipEventSynchronize(r.b);
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    auto &e = t[r.key][r.cand];
+    e.first += ms;
+    e.second = r.plan;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_tune.clear();
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  for (auto &kv : t) {
+    double best = -1.0;
+    TilePlan plan{0, 1};
+    for (auto &c : kv.second)
+      if (best < 0 || c.second.first < best) { best = c.second.first; plan = c.second.second; }
+    g_plans[kv.first] = plan;
+  }
+  return (int)t.size();
+}
+
+size_t tune_plans() {
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  return g_plans.size();
+}
+
+int tune_save(const char *path) {
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  FILE *f = std::fopen(path, "w");
+  if (!f) return -1;
+  for (auto &kv : g_plans) std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.tile, kv.second.nsplit);
+  return std::fclose(f) == 0 ? (int)g_plans.size() : -1;
+}
+
+int tune_load(const char *path) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return -1;
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  char key[1024];
+  int tile = 0, ns = 0, n = 0;
+  while (std::fscanf(f, "%1023s %d %d", key, &tile, &ns) == 3) {
+    if (tile < 0 || tile >= kTileCands || ns < 1) continue;
+    g_plans[key] = TilePlan{tile, ns};
+    ++n;
+  }
+  std::fclose(f);
+  return n;
+}
+
+void tune_clear() {
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  g_plans.clear();
+}
+
 hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   GemmDesc d = din;
   d.splitk = nullptr;
@@ -624,7 +732,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   d.ndiv = make_fastdiv((uint32_t)d.Ni);
   // Tile shape: the 32 x 32 single-wave tile for thin outputs; otherwise 128
   // rows by the N width (128, 80 or 64) that pads N least.
-  const bool small = (d.M <= 64 || d.N <= 64);
+  bool small = (d.M <= 64 || d.N <= 64);
   int BNx = 128;
   // (the (ac|bd) formation keeps one tile shape so that it is one kernel symbol)
   if (!small && d.kind != Kind::LadderBuild) {
@@ -634,16 +742,15 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
       if (best < 0 || pad < best) { best = pad; BNx = bn; }
     }
   }
-  const int BMx = small ? Small::BM : Big::BM;
   if (small) BNx = Small::BN;
-  const int tiles_m = (d.M + BMx - 1) / BMx, tiles_n = (d.N + BNx - 1) / BNx;
-  const int64_t tiles = (int64_t)tiles_m * tiles_n * d.batch;
+  const int64_t cap = g_splitk ? (int64_t)(g_splitk_elems / ((size_t)d.M * d.N)) : 0;
   // Split K when the tiles alone leave the chip idle: thin outputs with long K,
   // or a tile count that fills the last round of workgroups poorly.
-  int nsplit = 1;
-  const int64_t cap = g_splitk ? (int64_t)(g_splitk_elems / ((size_t)d.M * d.N)) : 0;
-  if (d.batch == 1 && cap >= 2) {
-    if (small) {
+  auto heuristic_split = [&](bool sm, int bm, int bn) {
+    int ns_out = 1;
+    const int64_t tiles = (int64_t)((d.M + bm - 1) / bm) * ((d.N + bn - 1) / bn) * d.batch;
+    if (d.batch != 1 || cap < 2) return 1;
+    if (sm) {
       // single-wave tiles hide latency only by numbers: up to 16 workgroups per
       // CU for outputs of a few tiles with long K (their partial sums are small)
       const bool tiny = (int64_t)d.M * d.N <= 4096;
@@ -651,20 +758,59 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
       if (tiles < target && slices >= 8) {
         int64_t want = (target + tiles - 1) / tiles;
         want = std::min<int64_t>({want, (int64_t)slices / 4, cap, tiny ? (int64_t)8192 : 1024});
-        if (want >= 2) nsplit = (int)want;
+        if (want >= 2) ns_out = (int)want;
       }
     } else if (slices >= 16 && tiles < 4 * kCUs) {
       // rounds of workgroups x slices per workgroup, plus the partial-sum traffic
-      const double t_slice = 2.0 * BMx * BNx * bk / (45e12 / kCUs);   // s per slice
+      const double t_slice = 2.0 * bm * bn * bk / (45e12 / kCUs);   // s per slice
       double best = -1.0;
       for (int ns = 1; ns <= 64 && ns <= cap && ns * 4 <= slices; ++ns) {
         const int64_t rounds = (tiles * ns + kCUs - 1) / kCUs;
         const double t = rounds * (double)((slices + ns - 1) / ns) * t_slice +
                          (ns > 1 ? 16.0 * ns * d.M * (double)d.N / 4e12 : 0.0);
-        if (best < 0 || t < best * 0.98) { best = t; nsplit = ns; }
+        if (best < 0 || t < best * 0.98) { best = t; ns_out = ns; }
+      }
+    }
+    return ns_out;
+  };
+  int nsplit = heuristic_split(small, small ? Small::BM : Big::BM, BNx);
+  // autotuning: a probe pass only collects keys; a candidate overrides the
+  // choice (and is timed); otherwise a stored plan for this shape is used
+  std::string key;
+  int cand = -1;
+  if (!g_dry && d.kind != Kind::LadderBuild && (g_cand >= 0 || !g_plans.empty())) {
+    key = plan_key(d);
+    if (g_cand == kProbeCand) {
+      std::lock_guard<std::mutex> lock(g_plan_mu);
+      if (!g_plans.count(key)) ++g_unplanned;
+      return hipSuccess;
+    }
+    auto set_tile = [&](int tile) {
+      small = (tile == 3);
+      BNx = (tile == 0) ? 128 : (tile == 1) ? 80 : (tile == 2) ? 64 : Small::BN;
+    };
+    if (g_cand >= 0) {
+      cand = g_cand;
+      set_tile(cand / kSplitRules);
+      const int h = heuristic_split(small, small ? Small::BM : Big::BM, BNx);
+      const int rule = cand % kSplitRules;
+      nsplit = (rule == 0) ? h : (rule == 1) ? 1 : std::max(2, 2 * h);
+      if (d.batch != 1) nsplit = 1;
+      nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nsplit, cap < 2 ? 1 : cap,
+                                                            (int64_t)slices}));
+    } else {
+      std::lock_guard<std::mutex> lock(g_plan_mu);
+      auto it = g_plans.find(key);
+      if (it != g_plans.end()) {
+        set_tile(it->second.tile);
+        nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)it->second.nsplit,
+                                                              cap < 2 ? 1 : cap, (int64_t)slices}));
+        if (d.batch != 1) nsplit = 1;
       }
     }
   }
+  const int BMx = small ? Small::BM : Big::BM;
+  const int tiles_m = (d.M + BMx - 1) / BMx, tiles_n = (d.N + BNx - 1) / BNx;
   const int sps = (slices + nsplit - 1) / nsplit;
   nsplit = (slices + sps - 1) / sps;
   if (nsplit > 1) d.splitk = g_splitk;
@@ -677,7 +823,8 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   if (g_dry) return hipSuccess;
 
   hipEvent_t ev[2] = {nullptr, nullptr};
-  if (g_profile) {
+  const bool timed = g_profile || cand >= 0;
+  if (timed) {
     if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
       return hipErrorOutOfMemory;
     (void)hipEventRecord(ev[0], stream);
@@ -698,7 +845,11 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
       hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, stream, d, nsplit);
     err = hipGetLastError();
   }
-  if (g_profile) {
+  if (cand >= 0) {
+    (void)hipEventRecord(ev[1], stream);
+    g_tune.push_back(TuneRec{key, cand, TilePlan{small ? 3 : (BNx == 128 ? 0 : BNx == 80 ? 1 : 2),
+                                                 nsplit}, ev[0], ev[1]});
+  } else if (g_profile) {
     (void)hipEventRecord(ev[1], stream);
     double flops = 0.0;
     for (int s = 0; s < d.nseg; ++s) flops += 2.0 * d.M * (double)d.N * d.seg[s].K;

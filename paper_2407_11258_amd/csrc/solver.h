@@ -96,11 +96,13 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
 int setup_fragment(const Layout &L, const double *B, const double *eo, const double *ev,
                    bool ccsd_phase, hipStream_t s);
 int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s);
+int tune_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s);
 int energy(const Layout &L, const double *t1, const double *t2, double *dev_out, hipStream_t s);
 int run_ccsd(const Layout &L, const Inputs &in, const lnocc_options_t &opt, Outputs &out,
              hipStream_t s);
-int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s);
-int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s);
+int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s,
+                bool autotune = false);
+int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s, bool autotune = false);
 
 // Pinned host buffer for the small readbacks of one solve ([0] energy,
 // [1..16] DIIS overlaps, [32] step norm, [33] step norm from the MP2 start,

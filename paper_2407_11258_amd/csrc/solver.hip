@@ -300,6 +300,27 @@ int setup_fragment(const Layout &L, const double *B, const double *eo, const dou
   return LNOCC_OK;
 }
 
+// Autotuning on the residual evaluation, which recomputes every intermediate
+// from (t1, t2): one evaluation per candidate, each timed launch by launch.
+int tune_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s) {
+  tune_probe_begin();
+  int st = ccsd_residuals(L, t1, t2, s);
+  const int unplanned = tune_probe_end();
+  if (st || unplanned == 0) return st;
+  for (int c = 0; c < tune_candidates() && !st; ++c) {
+    tune_candidate(c);
+    st = ccsd_residuals(L, t1, t2, s);
+  }
+  tune_candidate(-1);
+  tune_commit();
+  if (log_enabled()) {
+    std::fprintf(stderr, "lnocc: tuned %d residual contraction shapes (%zu plans)\n", unplanned,
+                 tune_plans());
+    std::fflush(stderr);
+  }
+  return st;
+}
+
 int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s) {
   const int64_t o = L.dm.o, v = L.dm.v, X = L.dm.X;
   const int64_t ov = o * v, oo = o * o, vv = v * v, ovv = o * vv, vvv = vv * v, ooo = oo * o;
@@ -714,6 +735,10 @@ int CcsdRun::enqueue_iteration() {
   install_splitk_scratch(L->splitk, (size_t)L->splitk_elems);
   const int64_t o = L->dm.o, v = L->dm.v, N = L->namp;
   ++it;
+  if (it == 1 && opt.autotune && !dry_run()) {
+    const int st = tune_residuals(*L, in.t1, in.t2, s);
+    if (st) return st;
+  }
   int st = residuals();
   if (st) return st;
   const int m = L->diis_m;
@@ -871,7 +896,7 @@ int CcsdRun::after_begin() {
 }
 
 int CcsdRun::enqueue_t() {
-  const int st = enqueue_triples(*L, in, s);
+  const int st = enqueue_triples(*L, in, s, opt.autotune != 0);
   if (st) return st;
   LN_TRY(d2h(host + 40, L->scal + 40, 8, s));
   LN_TRY(mark());
@@ -911,7 +936,7 @@ int run_ccsd(const Layout &L, const Inputs &in, const lnocc_options_t &opt, Outp
 
 // ---------------------------------------------------------------- (T)
 // Enqueues the whole (T) computation; the FP64 sum lands in L.scal[40].
-int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s) {
+int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s, bool autotune) {
   install_splitk_scratch(L.splitk, (size_t)L.splitk_elems);
   const int64_t o = L.dm.o, v = L.dm.v, X = L.dm.X;
   const int64_t ov = o * v, oo = o * o, vv = v * v, ovv = o * vv, vvv = vv * v;
@@ -949,32 +974,52 @@ int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s) {
       d.prec = L.lp; d.c_type = wtype;
       d.tmax[0] = d.tmax[1] = d.tmax[2] = (int)(o - 1);
     };
-    {  // rows (a,b), column c: P1, P3, H1, H3
-      GemmDesc d = DESC(vv, v, v, 1, L.W, vv, v, 1, 0, 0.0);
-      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), vvv, 0, 0), OPB(OP(t2w, v, 0, 1, 0), 0, vv, ovv));
-      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, vvv, 0), OPB(OP(t2w, v, 0, 1, 0), vv, 0, ovv));
-      SEG(d, o, 1, -1.0, OPB(OP(t2w, v, 1, vv, 0), ovv, 0, 0), OPB(OP(L.Jt, o, 0, 1, 0), 0, ovo, vo));
-      SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, ovv, 0), OPB(OP(L.Jt, o, 0, 1, 0), ovo, 0, vo));
-      finish(d);
-      LN_TRY(gett(d, s));
+    auto w_launches = [&]() -> int {
+      {  // rows (a,b), column c: P1, P3, H1, H3
+        GemmDesc d = DESC(vv, v, v, 1, L.W, vv, v, 1, 0, 0.0);
+        SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), vvv, 0, 0), OPB(OP(t2w, v, 0, 1, 0), 0, vv, ovv));
+        SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, vvv, 0), OPB(OP(t2w, v, 0, 1, 0), vv, 0, ovv));
+        SEG(d, o, 1, -1.0, OPB(OP(t2w, v, 1, vv, 0), ovv, 0, 0), OPB(OP(L.Jt, o, 0, 1, 0), 0, ovo, vo));
+        SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, ovv, 0), OPB(OP(L.Jt, o, 0, 1, 0), ovo, 0, vo));
+        finish(d);
+        LN_TRY(gett(d, s));
+      }
+      {  // rows (a,c), column b: P2, P5, H2, H5
+        GemmDesc d = DESC(vv, v, v, 1, L.W, vv, 1, v, 0, 1.0);
+        SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), vvv, 0, 0), OPB(OP(t2w, v, 0, 1, 0), 0, ovv, vv));
+        SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, 0, vvv), OPB(OP(t2w, v, 0, 1, 0), vv, ovv, 0));
+        SEG(d, o, 1, -1.0, OPB(OP(t2w, v, 1, vv, 0), ovv, 0, 0), OPB(OP(L.Jt, o, 0, 1, 0), 0, vo, ovo));
+        SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), ovo, vo, 0));
+        finish(d);
+        LN_TRY(gett(d, s));
+      }
+      {  // rows (b,c), column a: P4, P6, H4, H6
+        GemmDesc d = DESC(vv, v, v, 1, L.W, v, 1, vv, 0, 1.0);
+        SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), 0, vvv, 0), OPB(OP(t2w, v, 0, 1, 0), ovv, 0, vv));
+        SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, 0, vvv), OPB(OP(t2w, v, 0, 1, 0), ovv, vv, 0));
+        SEG(d, o, 1, -1.0, OPB(OP(t2w, v, 1, vv, 0), 0, ovv, 0), OPB(OP(L.Jt, o, 0, 1, 0), vo, 0, ovo));
+        SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), vo, ovo, 0));
+        finish(d);
+        LN_TRY(gett(d, s));
+      }
+        return LNOCC_OK;
+    };
+    if (autotune && t0 == 0 && !dry_run()) {   // tune the W launches on the first batch
+      tune_probe_begin();
+      int st = w_launches();
+      if (tune_probe_end() > 0 && !st) {
+        for (int c = 0; c < tune_candidates() && !st; ++c) {
+          tune_candidate(c);
+          st = w_launches();
+        }
+        tune_candidate(-1);
+        tune_commit();
+      }
+      if (st) return st;
     }
-    {  // rows (a,c), column b: P2, P5, H2, H5
-      GemmDesc d = DESC(vv, v, v, 1, L.W, vv, 1, v, 0, 1.0);
-      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), vvv, 0, 0), OPB(OP(t2w, v, 0, 1, 0), 0, ovv, vv));
-      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, 0, vvv), OPB(OP(t2w, v, 0, 1, 0), vv, ovv, 0));
-      SEG(d, o, 1, -1.0, OPB(OP(t2w, v, 1, vv, 0), ovv, 0, 0), OPB(OP(L.Jt, o, 0, 1, 0), 0, vo, ovo));
-      SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), ovo, vo, 0));
-      finish(d);
-      LN_TRY(gett(d, s));
-    }
-    {  // rows (b,c), column a: P4, P6, H4, H6
-      GemmDesc d = DESC(vv, v, v, 1, L.W, v, 1, vv, 0, 1.0);
-      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), 0, vvv, 0), OPB(OP(t2w, v, 0, 1, 0), ovv, 0, vv));
-      SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, 0, vvv), OPB(OP(t2w, v, 0, 1, 0), ovv, vv, 0));
-      SEG(d, o, 1, -1.0, OPB(OP(t2w, v, 1, vv, 0), 0, ovv, 0), OPB(OP(L.Jt, o, 0, 1, 0), vo, 0, ovo));
-      SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), vo, ovo, 0));
-      finish(d);
-      LN_TRY(gett(d, s));
+    {
+      const int st = w_launches();
+      if (st) return st;
     }
     if (log_enabled() && (t0 / L.nb) % 8 == 0) {
       std::fprintf(stderr, "lnocc: (T) triples %lld..%lld of %lld\n", (long long)t0,
@@ -988,8 +1033,9 @@ int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s) {
   return LNOCC_OK;
 }
 
-int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s) {
-  int st = enqueue_triples(L, in, s);
+int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s,
+                bool autotune) {
+  int st = enqueue_triples(L, in, s, autotune);
   if (st) return st;
   double *host = nullptr;
   if (dry_run()) {

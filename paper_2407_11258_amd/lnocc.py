@@ -52,7 +52,7 @@ class lnocc_options_t(C.Structure):
         ("ladder_chunk_bytes", C.c_size_t), ("triples_batch", C.c_int32),
         ("batch_slots", C.c_int32), ("level_shift", C.c_double),
         ("batch_streams", C.c_int32), ("ladder_mode", C.c_int32),
-        ("mlp", C.c_void_p), ("graphs", C.c_int32), ("reserved3", C.c_int32),
+        ("mlp", C.c_void_p), ("graphs", C.c_int32), ("autotune", C.c_int32),
     ]
 
 
@@ -87,7 +87,8 @@ EXPORTS = ("lnocc_default_options", "lnocc_status_string", "lnocc_last_error",
            "lnocc_batch_solve", "lnocc_contract", "lnocc_profile_enable",
            "lnocc_profile_collect", "lnocc_set_validation_mode", "lnocc_mlp_workspace_bytes",
            "lnocc_mlp_samples", "lnocc_mlp_init", "lnocc_mlp_predict", "lnocc_mlp_loss_grad",
-           "lnocc_mlp_train")
+           "lnocc_mlp_train", "lnocc_autotune_save", "lnocc_autotune_load",
+           "lnocc_autotune_clear")
 
 
 def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
@@ -132,6 +133,12 @@ def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
     lib.lnocc_mlp_loss_grad.argtypes = [P, P, P, I64, P, C.POINTER(C.c_double), OP]
     lib.lnocc_mlp_train.argtypes = [P, P, I64, C.c_int32, P, P, I64, C.c_int32, C.c_float,
                                     C.c_uint64, C.POINTER(C.c_double), OP]
+    lib.lnocc_autotune_save.argtypes = [C.c_char_p]
+    lib.lnocc_autotune_save.restype = C.c_int
+    lib.lnocc_autotune_load.argtypes = [C.c_char_p]
+    lib.lnocc_autotune_load.restype = C.c_int
+    lib.lnocc_autotune_clear.argtypes = []
+    lib.lnocc_autotune_clear.restype = None
     for name in ("lnocc_mlp_workspace_bytes", "lnocc_mlp_samples", "lnocc_mlp_init",
                  "lnocc_mlp_predict", "lnocc_mlp_loss_grad", "lnocc_mlp_train"):
         getattr(lib, name).restype = C.c_int
@@ -150,6 +157,18 @@ def lnocc_default_options() -> lnocc_options_t:
 
 def lnocc_status_string(status: int) -> str:
     return _lib.lnocc_status_string(int(status)).decode()
+
+
+def lnocc_autotune_save(path) -> int:
+    return _lib.lnocc_autotune_save(str(path).encode())
+
+
+def lnocc_autotune_load(path) -> int:
+    return _lib.lnocc_autotune_load(str(path).encode())
+
+
+def lnocc_autotune_clear() -> None:
+    _lib.lnocc_autotune_clear()
 
 
 def lnocc_last_error() -> str:
@@ -274,7 +293,7 @@ def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int
                  ladder_chunk_bytes: int = 0, triples_batch: int = 0,
                  level_shift: float = 0.0, batch_slots: int = 0,
                  batch_streams: int = 0, mlp=None, ladder: str = "auto",
-                 graphs: bool = True) -> lnocc_options_t:
+                 graphs: bool = True, autotune: bool = False) -> lnocc_options_t:
     opt = lnocc_default_options()
     opt.precision = PRECISIONS[precision]
     opt.do_triples = int(do_triples)
@@ -289,6 +308,7 @@ def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int
     opt.batch_streams = batch_streams
     opt.ladder_mode = LADDER_MODES[ladder]
     opt.graphs = int(bool(graphs))
+    opt.autotune = int(bool(autotune))
     if mlp is not None:
         opt.mlp = mlp if isinstance(mlp, int) else mlp.data_ptr()
     return opt

@@ -366,3 +366,31 @@ def test_graph_replay_equals_eager(o, v, X, seed, precision):
         assert st == L.LNOCC_OK
         out.append((fs.e_ccsd, fs.e_t, fs.n_iter, host(t2).tobytes()))
     assert out[0] == out[1] == out[2]
+
+
+def test_autotuned_plans_keep_the_results(tmp_path):
+    """Tile / split plans chosen by timing every candidate change only the
+    summation order: energies agree with the heuristic choice to rounding, and
+    the plans survive a save / clear / load round trip."""
+    say("autotune")
+    L.lnocc_autotune_clear()
+    f = make_fragment(6, 45, 100, 5)
+    B, eo, ev = _fragment_on_device(f)
+    res = []
+    for autotune in (False, True, True):
+        t1 = torch.empty((6, 45), dtype=torch.float64, device=DEV)
+        t2 = torch.empty((6, 6, 45, 45), dtype=torch.float64, device=DEV)
+        st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=1e-10,
+                       autotune=autotune)
+        assert st == L.LNOCC_OK
+        res.append((fs.e_ccsd, fs.e_t, fs.n_iter))
+    say(f"  heuristic {res[0]}, tuned {res[1]}, reused {res[2]}")
+    assert abs(res[1][0] - res[0][0]) < 1e-10 and abs(res[1][1] - res[0][1]) < 1e-10
+    # the setup contractions of the first tuned solve ran before any plan existed
+    assert abs(res[2][0] - res[1][0]) < 1e-12 and abs(res[2][1] - res[1][1]) < 1e-12
+    path = tmp_path / "plans.txt"
+    n = L.lnocc_autotune_save(path)
+    assert n > 10 and len(path.read_text().splitlines()) == n
+    L.lnocc_autotune_clear()
+    assert L.lnocc_autotune_load(path) == n
+    L.lnocc_autotune_clear()
