@@ -215,7 +215,9 @@ typedef struct lnocc_contract_t {
   double beta;
   int32_t batch, nb1;
   int32_t precision;             /* lnocc_precision_t of the operands */
-  int32_t reserved;
+  int32_t tile;                  /* 0: automatic (tuned plan or heuristic); 1..6 force a tile
+                                    of 128x128, 128x80, 128x64, 32x32, 128x160, 256x128
+                                    rows x columns (the last two FP32 only; ignored otherwise) */
 } lnocc_contract_t;
 
 int lnocc_contract(const lnocc_contract_t *desc, void *stream);

@@ -80,6 +80,7 @@ struct GemmDesc {
                           // F64 double, F32 float, BF16 bf16 (FP32 accumulation)
   int c_type;             // output element: 0 double, 1 float, 2 bf16
   Kind kind;
+  int tile_hint;          // 0 automatic, t + 1 forces tile t (see the launcher)
   double *splitk;         // set by gett(): partial-sum scratch when K is split
   FastDiv mdiv, ndiv;     // set by gett(): division by Mi, Ni
 };

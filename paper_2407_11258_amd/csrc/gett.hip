@@ -81,6 +81,14 @@ using Big = Cfg<128, 128, 4, 2>;     // 8 waves, 32 x 64 (2 x 4 MFMA blocks) eac
 using Big80 = Cfg<128, 80, 4, 1>;    // 4 waves, 32 x 80 (2 x 5) each: N = 80 q
 using Big64 = Cfg<128, 64, 4, 1>;    // 4 waves, 32 x 64 (2 x 4) each
 using Small = Cfg<32, 32, 1, 1>;
+// FP32 only (accumulators are half the size of FP64 ones): more MFMA work per
+// LDS slice to cover the load latency of the faster FP32 matrix cores.
+using Wide160 = Cfg<128, 160, 4, 1>; // 4 waves, 32 x 160 (2 x 10) each: N = 160
+using Tall = Cfg<256, 128, 4, 2>;    // 8 waves, 64 x 64 (4 x 4) each
+
+// Tile ids of the launcher and the autotuner (rows x columns per workgroup).
+constexpr int kTileBM[6] = {128, 128, 128, 32, 128, 256};
+constexpr int kTileBN[6] = {128, 80, 64, 32, 160, 128};
 
 struct BatchIdx { int64_t i0, i1, i2; };
 
@@ -570,6 +578,10 @@ void launch_kind(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t
   }
 }
 template <class C>
+void launch_f32(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
+  launch_kind<ModeF32, C>(d, grid, tiles_m, sps, stream);
+}
+template <class C>
 void launch(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
   switch (d.prec) {
     case Prec::F32: launch_kind<ModeF32, C>(d, grid, tiles_m, sps, stream); break;
@@ -612,7 +624,7 @@ void install_splitk_scratch(double *p, size_t elems) {
 // tune_commit() keeps, per key, the fastest candidate's (tile, split count),
 // which later launches of that shape use instead of the heuristic.
 namespace {
-constexpr int kTileCands = 4, kSplitRules = 3;
+constexpr int kTileCands = 6, kSplitRules = 3;
 struct TilePlan { int tile; int nsplit; };
 std::mutex g_plan_mu;
 std::map<std::string, TilePlan> g_plans;
@@ -732,17 +744,17 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   d.ndiv = make_fastdiv((uint32_t)d.Ni);
   // Tile shape: the 32 x 32 single-wave tile for thin outputs; otherwise 128
   // rows by the N width (128, 80 or 64) that pads N least.
-  bool small = (d.M <= 64 || d.N <= 64);
-  int BNx = 128;
-  // (the (ac|bd) formation keeps one tile shape so that it is one kernel symbol)
-  if (!small && d.kind != Kind::LadderBuild) {
+  int tile = 0;
+  if (d.M <= 64 || d.N <= 64) {
+    tile = 3;
+  } else if (d.kind != Kind::LadderBuild) {   // (the (ac|bd) formation keeps one tile shape)
     int64_t best = -1;
-    for (int bn : {128, 80, 64}) {
+    for (int t : {0, 1, 2}) {
+      const int bn = kTileBN[t];
       const int64_t pad = ((int64_t)(d.N + bn - 1) / bn) * bn - d.N;
-      if (best < 0 || pad < best) { best = pad; BNx = bn; }
+      if (best < 0 || pad < best) { best = pad; tile = t; }
     }
   }
-  if (small) BNx = Small::BN;
   const int64_t cap = g_splitk ? (int64_t)(g_splitk_elems / ((size_t)d.M * d.N)) : 0;
   // Split K when the tiles alone leave the chip idle: thin outputs with long K,
   // or a tile count that fills the last round of workgroups poorly.
@@ -773,26 +785,29 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
     }
     return ns_out;
   };
-  int nsplit = heuristic_split(small, small ? Small::BM : Big::BM, BNx);
+  if (d.tile_hint > 0 && d.tile_hint <= kTileCands && (d.tile_hint <= 4 || d.prec == Prec::F32))
+    tile = d.tile_hint - 1;
+  int nsplit = heuristic_split(tile == 3, kTileBM[tile], kTileBN[tile]);
   // autotuning: a probe pass only collects keys; a candidate overrides the
   // choice (and is timed); otherwise a stored plan for this shape is used
   std::string key;
   int cand = -1;
-  if (!g_dry && d.kind != Kind::LadderBuild && (g_cand >= 0 || !g_plans.empty())) {
+  if (!g_dry && d.kind != Kind::LadderBuild && d.tile_hint == 0 &&
+      (g_cand >= 0 || !g_plans.empty())) {
     key = plan_key(d);
     if (g_cand == kProbeCand) {
       std::lock_guard<std::mutex> lock(g_plan_mu);
       if (!g_plans.count(key)) ++g_unplanned;
       return hipSuccess;
     }
-    auto set_tile = [&](int tile) {
-      small = (tile == 3);
-      BNx = (tile == 0) ? 128 : (tile == 1) ? 80 : (tile == 2) ? 64 : Small::BN;
+    // the FP32-only tiles stand in for the heuristic choice in other precisions
+    auto set_tile = [&](int t) {
+      if (t >= 0 && t < kTileCands && (t < 4 || d.prec == Prec::F32)) tile = t;
     };
     if (g_cand >= 0) {
       cand = g_cand;
       set_tile(cand / kSplitRules);
-      const int h = heuristic_split(small, small ? Small::BM : Big::BM, BNx);
+      const int h = heuristic_split(tile == 3, kTileBM[tile], kTileBN[tile]);
       const int rule = cand % kSplitRules;
       nsplit = (rule == 0) ? h : (rule == 1) ? 1 : std::max(2, 2 * h);
       if (d.batch != 1) nsplit = 1;
@@ -809,7 +824,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
       }
     }
   }
-  const int BMx = small ? Small::BM : Big::BM;
+  const int BMx = kTileBM[tile], BNx = kTileBN[tile];
   const int tiles_m = (d.M + BMx - 1) / BMx, tiles_n = (d.N + BNx - 1) / BNx;
   const int sps = (slices + nsplit - 1) / nsplit;
   nsplit = (slices + sps - 1) / sps;
@@ -830,10 +845,14 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
     (void)hipEventRecord(ev[0], stream);
   }
   dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)d.batch, (unsigned)nsplit);
-  if (small) launch<Small>(d, grid, tiles_m, sps, stream);
-  else if (BNx == 80) launch<Big80>(d, grid, tiles_m, sps, stream);
-  else if (BNx == 64) launch<Big64>(d, grid, tiles_m, sps, stream);
-  else launch<Big>(d, grid, tiles_m, sps, stream);
+  switch (tile) {
+    case 1: launch<Big80>(d, grid, tiles_m, sps, stream); break;
+    case 2: launch<Big64>(d, grid, tiles_m, sps, stream); break;
+    case 3: launch<Small>(d, grid, tiles_m, sps, stream); break;
+    case 4: launch_f32<Wide160>(d, grid, tiles_m, sps, stream); break;
+    case 5: launch_f32<Tall>(d, grid, tiles_m, sps, stream); break;
+    default: launch<Big>(d, grid, tiles_m, sps, stream); break;
+  }
   hipError_t err = hipGetLastError();
   if (err == hipSuccess && nsplit > 1) {
     const int64_t total = (int64_t)d.M * d.N;
@@ -847,8 +866,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   }
   if (cand >= 0) {
     (void)hipEventRecord(ev[1], stream);
-    g_tune.push_back(TuneRec{key, cand, TilePlan{small ? 3 : (BNx == 128 ? 0 : BNx == 80 ? 1 : 2),
-                                                 nsplit}, ev[0], ev[1]});
+    g_tune.push_back(TuneRec{key, cand, TilePlan{tile, nsplit}, ev[0], ev[1]});
   } else if (g_profile) {
     (void)hipEventRecord(ev[1], stream);
     double flops = 0.0;

@@ -70,7 +70,7 @@ class lnocc_contract_t(C.Structure):
         ("c", C.c_void_p), ("c_mo", C.c_int64), ("c_mi", C.c_int64), ("c_no", C.c_int64),
         ("c_ni", C.c_int64), ("c_b0", C.c_int64), ("c_b1", C.c_int64), ("c_bid", C.c_int64),
         ("beta", C.c_double), ("batch", C.c_int32), ("nb1", C.c_int32),
-        ("precision", C.c_int32), ("reserved", C.c_int32),
+        ("precision", C.c_int32), ("tile", C.c_int32),
     ]
 
 

@@ -55,7 +55,8 @@ def _operand(t, ro, ri, ko, ki, b0=0, b1=0, bid=0):
     return L.lnocc_operand_t(t.data_ptr(), ro, ri, ko, ki, b0, b1, bid)
 
 
-def _contract(M, Mi, N, Ni, c, cstr, segs, beta=0.0, batch=1, nb1=1, cb=(0, 0, 0), precision=0):
+def _contract(M, Mi, N, Ni, c, cstr, segs, beta=0.0, batch=1, nb1=1, cb=(0, 0, 0), precision=0,
+              tile=0):
     d = L.lnocc_contract_t()
     d.M, d.Mi, d.N, d.Ni = M, Mi, N, Ni
     d.nseg = len(segs)
@@ -67,6 +68,7 @@ def _contract(M, Mi, N, Ni, c, cstr, segs, beta=0.0, batch=1, nb1=1, cb=(0, 0, 0
     d.c_b0, d.c_b1, d.c_bid = cb
     d.beta, d.batch, d.nb1 = beta, batch, nb1
     d.precision = precision
+    d.tile = tile
     st = L.lnocc_contract(d, torch.cuda.current_stream().cuda_stream)
     _KEEP.clear()
     assert st == L.LNOCC_OK, f"{L.lnocc_status_string(st)}: {L.lnocc_last_error()}"
@@ -153,6 +155,31 @@ def test_contract_low_precision(M, N, K):
               [(K, 1, 1.0, _operand(a_t, 1, 0, M, 0), _operand(b_t, K, 0, 1, 0))], precision=2)
     err = np.abs(host(c) - ref).max() / np.abs(ref).max()
     assert err < 2e-6 * np.sqrt(K), err
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_contract_every_tile(tile, precision):
+    """Each tile shape of the launcher (forced) on a ragged, segmented, two-index
+    product, FP64 and FP32 operands (the 128x160 and 256x128 tiles are FP32 only;
+    FP64 falls back to the automatic choice)."""
+    say(f"contract tile {tile} precision {precision}")
+    rng = np.random.default_rng(100 + tile)
+    M, N, K1, K2 = 301, 263, 45, 19
+    A1, B1 = rng.standard_normal((M, K1)), rng.standard_normal((N, K1))
+    A2, B2 = rng.standard_normal((K2, M)), rng.standard_normal((N, K2))
+    dt = np.float64 if precision == 0 else np.float32
+    A1, B1, A2, B2 = (x.astype(dt) for x in (A1, B1, A2, B2))
+    ref = (A1.astype(np.float64) @ B1.astype(np.float64).T
+           - 0.5 * A2.astype(np.float64).T @ B2.astype(np.float64).T)
+    c = torch.zeros((M, N), dtype=torch.float64, device=DEV)
+    t = [torch.tensor(x, device=DEV) for x in (A1, B1, A2, B2)]
+    _contract(M, 1, N, 1, c, (N, 0, 1, 0),
+              [(K1, 1, 1.0, _operand(t[0], K1, 0, 1, 0), _operand(t[1], K1, 0, 1, 0)),
+               (K2, 1, -0.5, _operand(t[2], 1, 0, M, 0), _operand(t[3], K2, 0, 1, 0))],
+              precision=precision, tile=tile)
+    err = np.abs(host(c) - ref).max() / np.abs(ref).max()
+    assert err < (1e-13 if precision == 0 else 2e-6 * np.sqrt(K1 + K2)), err
 
 
 # ------------------------------------------------------------ solver pieces
@@ -366,6 +393,25 @@ def test_graph_replay_equals_eager(o, v, X, seed, precision):
         assert st == L.LNOCC_OK
         out.append((fs.e_ccsd, fs.e_t, fs.n_iter, host(t2).tobytes()))
     assert out[0] == out[1] == out[2]
+
+
+def test_autotuned_mixed_precision_solve():
+    """Tuned plans in the FP32 mode (where the FP32-only tiles compete) keep the
+    energies at FP32 rounding distance from the untuned solve."""
+    say("autotune fp32")
+    L.lnocc_autotune_clear()
+    f = make_fragment(6, 45, 100, 5)
+    B, eo, ev = _fragment_on_device(f)
+    res = []
+    for autotune in (False, True):
+        t1 = torch.empty((6, 45), dtype=torch.float64, device=DEV)
+        t2 = torch.empty((6, 6, 45, 45), dtype=torch.float64, device=DEV)
+        st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=1e-9,
+                       precision="fp32", autotune=autotune)
+        assert st == L.LNOCC_OK
+        res.append((fs.e_ccsd, fs.e_t))
+    L.lnocc_autotune_clear()
+    assert abs(res[1][0] - res[0][0]) < 1e-8 and abs(res[1][1] - res[0][1]) < 1e-8
 
 
 def test_autotuned_plans_keep_the_results(tmp_path):
