@@ -50,7 +50,10 @@ hipError_t scatter_vec(const double *x, int64_t o, int64_t v, double *t1, double
 // type: 0 double, 1 float, 2 bf16 (round to nearest even)
 hipError_t pack_t(const double *t2, int64_t o, int64_t v, void *Tsa, int type, hipStream_t s);
 hipError_t convert(const double *in, int64_t n, void *out, int type, hipStream_t s);
-hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, double *R2, hipStream_t s);
+// SA rows of ld entries; ca == 0: entry P = a v + b; ca > 0: the stored-ladder
+// order of blocks of ca values of a (see the kernel).
+hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, int64_t ca, int64_t ld,
+                         double *R2, hipStream_t s);
 
 // table[3 n + {0,1,2}] <- (i, j, k) of the n-th unique triple i <= j <= k, not
 // all equal, in lexicographic order (o (o + 1) (o + 2) / 6 - o entries).

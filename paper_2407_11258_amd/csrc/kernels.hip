@@ -289,19 +289,30 @@ __global__ void k_pack_t(const double *__restrict__ t2, int64_t o, int64_t v, T 
   }
 }
 
-// R2[i][j][a][b] += (S_ij^ab + A_ij^ab) / 2 from SA[r][a][b] (a >= b), where
+// R2[i][j][a][b] += (S_ij^ab + A_ij^ab) / 2 from SA[r][P(a, b)] (a >= b), where
 // rows r < o(o+1)/2 hold S (symmetric in ij and ab) and the rest A
-// (antisymmetric in both).
-__global__ void k_unpack_ladder(const double *__restrict__ SA, int64_t o, int64_t v, double *R2) {
+// (antisymmetric in both).  ca == 0: P = a v + b, rows of v^2; ca > 0: the
+// stored-ladder row order (blocks of ca values of a, each [a - a0][b < a1]):
+// P = ca^2 q (q + 1) / 2 + (a - a0) a1 + b with q = a / ca, a0 = q ca,
+// a1 = min(a0 + ca, v), rows of ld entries.
+__global__ void k_unpack_ladder(const double *__restrict__ SA, int64_t o, int64_t v, int64_t ca,
+                                int64_t ld, double *R2) {
   const int64_t vv = v * v, total = o * o * vv, op = o * (o + 1) / 2;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t ij = e / vv, ab = e % vv, i = ij / o, j = ij % o, a = ab / v, b = ab % v;
-    const int64_t P = (a >= b) ? a * v + b : b * v + a;
-    double r = SA[((i <= j) ? tri(j, i) : tri(i, j)) * vv + P];
+    const int64_t hi = (a >= b) ? a : b, lo = (a >= b) ? b : a;
+    int64_t P;
+    if (ca == 0) {
+      P = hi * v + lo;
+    } else {
+      const int64_t q = hi / ca, a0 = q * ca, a1 = (a0 + ca < v) ? a0 + ca : v;
+      P = ca * ca * q * (q + 1) / 2 + (hi - a0) * a1 + lo;
+    }
+    double r = SA[((i <= j) ? tri(j, i) : tri(i, j)) * ld + P];
     if (i != j && a != b) {
       const double sg = ((i < j) == (a > b)) ? 1.0 : -1.0;
-      r += sg * SA[(op + ((i < j) ? stri(j, i) : stri(i, j))) * vv + P];
+      r += sg * SA[(op + ((i < j) ? stri(j, i) : stri(i, j))) * ld + P];
     }
     R2[e] += 0.5 * r;
   }
@@ -542,10 +553,11 @@ hipError_t convert(const double *in, int64_t n, void *out, int type, hipStream_t
   else hipLaunchKernelGGL(k_convert<double>, g, b, 0, s, in, n, (double *)out);
   return hipGetLastError();
 }
-hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, double *R2, hipStream_t s) {
+hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, int64_t ca, int64_t ld,
+                         double *R2, hipStream_t s) {
   if (dry_run()) return hipSuccess;
   hipLaunchKernelGGL(k_unpack_ladder, dim3(ew_blocks(o * o * v * v)), dim3(kEwThreads), 0, s, SA,
-                     o, v, R2);
+                     o, v, ca, ld, R2);
   return hipGetLastError();
 }
 // Unique triples i <= j <= k (not all equal) in lexicographic order; one

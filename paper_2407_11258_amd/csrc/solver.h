@@ -38,7 +38,8 @@ struct Layout {
   double *Btvv_lp;                  // B~_vv in the precision of the ladder products
   // stored ladder (bare integrals formed once per solve)
   bool lstore = false;
-  void *Lst = nullptr;              // (ac|bd) blocks [a in block][c][b < a1][d], ladder precision
+  void *Lst = nullptr;              // (ac|bd) blocks [a in block][b < a1][c][d], ladder precision
+  int64_t lrows = 0;                // rows (a, b < a1) of all stored blocks
   double *Gkc = nullptr;            // (kc|bd) [k][c][b][d]
   double *Zl = nullptr, *Yl = nullptr, *Wl = nullptr;   // [ij][k][b], [ij][k][b], [ij][k][l]
   double *Bvv_lp = nullptr;         // bare B_vv in the ladder precision

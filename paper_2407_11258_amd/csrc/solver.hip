@@ -139,6 +139,7 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
       const int64_t na = std::min<int64_t>(L.chunk_a, v - a0);
       blk += na * (a0 + na) * vv;
     }
+    L.lrows = blk / vv;
     const size_t need = (size_t)blk * esz + (size_t)(o * vvv + 2 * o * oo * v + oo * oo) * 8 +
                         (L.lp != Prec::F64 ? (size_t)X * vv * esz : 0);
     L.lstore = opt.ladder_mode == LNOCC_LADDER_STORED ||
@@ -419,17 +420,17 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     // R_ij^ab = sum_cd t_ij^cd (ac|bd) - sum_k t_k^a (Z - Y)_ij,k^b - sum_k Z_ji,k^a t_k^b
     // with Z_ij,k^b = sum_cd t_ij^cd (kc|bd), Y_ij,k^b = sum_l W_ij,kl t_l^b and
     // W_ij,kl = sum_cd t_ij^cd (kc|ld).
-    const char *blk = (const char *)L.Lst;
-    for (int64_t a0 = 0; a0 < v; a0 += L.chunk_a) {
-      const int64_t na = std::min<int64_t>(L.chunk_a, v - a0), a1 = a0 + na;
-      GemmDesc d = DESC(na * a1, a1, oo, 1, L.SA + a0 * v, v, 1, vv, 0, 0.0);
-      SEG(d, vv, 1, 1.0, OP((const double *)blk, a1 * vv, vv, 1, 0), OP(L.Tsa, vv, 0, 1, 0));
+    // one product over all stored rows (a, b < a1) of every block:
+    // SA[r][row] = sum_cd Tsa[r][cd] (ac|bd)[row][cd]
+    {
+      GemmDesc d = DESC(L.lrows, 1, oo, 1, L.SA, 1, 0, L.lrows, 0, 0.0);
+      SEG(d, vv, 1, 1.0, OP((const double *)L.Lst, vv, 0, 1, 0), OP(L.Tsa, vv, 0, 1, 0));
       d.kind = Kind::LadderContract;
       d.prec = L.lp;
       LN_TRY(gett(d, s));
-      blk += (size_t)na * a1 * vv * esz;
     }
-    LN_TRY(unpack_ladder(L.SA, o, v, L.R2, s));
+    LN_TRY(unpack_ladder(L.SA, o, v, L.chunk_a, L.lrows, L.R2, s));
+    (void)esz;
     {  // Z[ij][k][b] = sum_cd t_ij^cd (kc|bd)
       GemmDesc d = DESC(oo, 1, ov, v, L.Zl, ov, 0, v, 1, 0.0);
       SEG(d, vv, v, 1.0, OP(t2, vv, 0, v, 1), OP(L.Gkc, vvv, v, vv, 1));
@@ -477,7 +478,7 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
       d.prec = L.lp;
       LN_TRY(gett(d, s));
     }
-    LN_TRY(unpack_ladder(L.SA, o, v, L.R2, s));
+    LN_TRY(unpack_ladder(L.SA, o, v, 0, vv, L.R2, s));
   }
   {  // hole-hole ladder: W_klij = (ki|lj)~ + sum_cd (kc|ld) t_ij^cd ; R2 += sum_kl t_kl^ab W_klij
     GemmDesc d = DESC(oo, o, oo, o, L.Wkl, ooo, o, oo, 1, 0.0);
