@@ -83,6 +83,8 @@ struct GemmDesc {
   int tile_hint;          // 0 automatic, t + 1 forces tile t (see the launcher)
   double *splitk;         // set by gett(): partial-sum scratch when K is split
   FastDiv mdiv, ndiv;     // set by gett(): division by Mi, Ni
+  int c_vec4;             // set by gett(): output rows 4q .. 4q+3 are consecutive,
+                          // 4-element-aligned elements of C (stored as one vector)
 };
 
 // Scratch for split-K partial sums (per host thread); without it K is never split.

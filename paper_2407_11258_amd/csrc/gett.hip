@@ -279,6 +279,63 @@ __device__ inline void store_out(const GemmDesc &d, void *base, int64_t off, dou
   }
 }
 
+// Four consecutive rows of one output column (the FP32 accumulator registers
+// of a lane), stored with one vector access; same rounding as store_out.
+__device__ inline void store_out4(const GemmDesc &d, void *base, int64_t off, float4_t v) {
+  if (d.c_type == 1) {
+    float4_t *p = (float4_t *)((float *)base + off);
+    if (d.beta != 0.0) {
+      const float4_t o = *p;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = (float)((double)v[r] + d.beta * (double)o[r]);
+    }
+    *p = v;
+  } else {
+    double4_t *p = (double4_t *)((double *)base + off);
+    double4_t w;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) w[r] = (double)v[r];
+    if (d.beta != 0.0) {
+      const double4_t o = *p;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) w[r] = w[r] + d.beta * o[r];
+    }
+    *p = w;
+  }
+}
+
+__device__ inline void store_out4(const GemmDesc &d, void *base, int64_t off, double4_t w) {
+  double4_t *p = (double4_t *)((double *)base + off);
+  if (d.beta != 0.0) {
+    const double4_t o = *p;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) w[r] = w[r] + d.beta * o[r];
+  }
+  *p = w;
+}
+
+// FP64 accumulators hold rows q + 4 r (q = lane / 16) of column lane % 16;
+// three lane exchanges regroup them so that the lane holds rows 4 q + s,
+// s = 0..3.  Round t: the lane offers its row q - t (mod 4) value and takes,
+// from the lane of the same column with q' = q + t (mod 4), that lane's offer,
+// which is row 4 q + q'.  Every lane of the wave must take part.
+__device__ inline double pick4(const double4_t &a, int k) {
+  return k == 0 ? a[0] : (k == 1 ? a[1] : (k == 2 ? a[2] : a[3]));
+}
+__device__ inline double4_t regroup_rows_f64(const double4_t &a, int lane) {
+  const int q = lane >> 4, col = lane & 15;
+  double4_t out = a;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const double offer = pick4(a, (q - t) & 3);
+    const double got = t == 0 ? offer : __shfl(offer, (((q + t) & 3) << 4) | col, 64);
+    const int s = (q + t) & 3;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[r] = s == r ? got : out[r];
+  }
+  return out;
+}
+
 template <class M, class C, int KIND>
 __global__ __launch_bounds__(C::T) void gett_kernel(GemmDesc d, int tiles_m, int slices_per_split) {
   using E = typename M::T;
@@ -378,6 +435,26 @@ __global__ __launch_bounds__(C::T) void gett_kernel(GemmDesc d, int tiles_m, int
     const int n = n0 + wn * (C::BN / C::WN) + j * 16 + lane % 16;
     cok[j] = n < d.N;
     coff[j] = cok[j] ? two_index_off(d.ndiv, (uint32_t)n, d.c_no, d.c_ni) : 0;
+  }
+  if (d.c_vec4) {
+    // rows 4 (lane / 16) + s, s = 0..3, of one column are adjacent in C: one
+    // 16- or 32-byte access per column instead of four scattered ones
+#pragma unroll
+    for (int i = 0; i < C::MI; ++i) {
+      const int m = m0 + wm * (C::BM / C::WM) + i * 16 + 4 * (lane / 16);
+      const bool mok = m < d.M;
+      const int64_t moff = mok ? two_index_off(d.mdiv, (uint32_t)m, d.c_mo, d.c_mi) : 0;
+#pragma unroll
+      for (int j = 0; j < C::NI; ++j) {
+        if constexpr (std::is_same<E, double>::value) {
+          const double4_t w = regroup_rows_f64(acc[i][j], lane);   // whole wave
+          if (mok && cok[j]) store_out4(d, pc, moff + coff[j], w);
+        } else {
+          if (mok && cok[j]) store_out4(d, pc, moff + coff[j], acc[i][j]);
+        }
+      }
+    }
+    return;
   }
 #pragma unroll
   for (int i = 0; i < C::MI; ++i) {
@@ -742,6 +819,16 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   if (d.table == nullptr && d.nb1 <= 0) return hipErrorInvalidValue;
   d.mdiv = make_fastdiv((uint32_t)d.Mi);
   d.ndiv = make_fastdiv((uint32_t)d.Ni);
+  {  // vector stores of 4-row groups (FP64 or FP32 C; FP64 products: FP64 C)
+    const int64_t esz = d.c_type == 0 ? 8 : 4;
+    const bool rows = (d.Mi % 4 == 0 && d.c_mi == 1 && d.c_mo % 4 == 0) ||
+                      (d.Mi == 1 && d.c_mo == 1);
+    const bool cols = d.c_no % 4 == 0 && (d.Ni == 1 || d.c_ni % 4 == 0);
+    d.c_vec4 = (d.prec != Prec::F64 || d.c_type == 0) && d.c_type != 2 && rows && cols &&
+               d.M % 4 == 0 &&
+               d.c_b0 % 4 == 0 && d.c_b1 % 4 == 0 && d.c_b2 % 4 == 0 && d.c_bid % 4 == 0 &&
+               (reinterpret_cast<uintptr_t>(d.c) % (4 * esz)) == 0;
+  }
   // Tile shape: the 32 x 32 single-wave tile for thin outputs; otherwise 128
   // rows by the N width (128, 80 or 64) that pads N least.
   int tile = 0;

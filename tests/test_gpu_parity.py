@@ -182,6 +182,37 @@ def test_contract_every_tile(tile, precision):
     assert err < (1e-13 if precision == 0 else 2e-6 * np.sqrt(K1 + K2)), err
 
 
+@pytest.mark.parametrize("shift", [0, 1])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_contract_column_major_output(tile, precision, shift):
+    """Outputs whose row index is the contiguous one (C[e][n][mo][mi]), read and
+    written back with beta != 0: with shift = 0 every 4-row group is one aligned
+    vector, so the kernels store it at once (FP64 accumulators after a lane
+    exchange); shift = 1 misaligns C by one element and takes the element-wise
+    path.  Ragged in M and N, batched, every tile."""
+    say(f"contract column-major C tile {tile} precision {precision} shift {shift}")
+    rng = np.random.default_rng(300 + 10 * tile + precision)
+    nb, Mo, Mi, N, K = 2, 7, 36, 263, 53
+    M = Mo * Mi
+    dt = np.float64 if precision == 0 else np.float32
+    A = rng.standard_normal((nb, M, K)).astype(dt)
+    Bm = rng.standard_normal((nb, N, K)).astype(dt)
+    C0 = rng.standard_normal((nb, N, M))
+    ref = 0.75 * C0 + np.einsum("emk,enk->enm", A.astype(np.float64), Bm.astype(np.float64))
+    buf = torch.zeros(nb * N * M + shift, dtype=torch.float64, device=DEV)
+    c = buf[shift:]
+    c.copy_(torch.tensor(C0.ravel(), device=DEV))
+    a_t, b_t = torch.tensor(A, device=DEV), torch.tensor(Bm, device=DEV)
+    _contract(M, Mi, N, 1, c, (Mi, 1, M, 0),
+              [(K, 1, 1.0, _operand(a_t, Mi * K, K, 1, 0, bid=M * K),
+                _operand(b_t, K, 0, 1, 0, bid=N * K))],
+              beta=0.75, batch=nb, cb=(0, 0, N * M), precision=precision, tile=tile)
+    got = host(c).reshape(nb, N, M)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < (1e-14 if precision == 0 else 2e-6 * np.sqrt(K)), err
+
+
 # ------------------------------------------------------------ solver pieces
 def _fragment_on_device(f, scale=1.0):
     return dev(scale * f.B), dev(f.eps_occ), dev(f.eps_vir)
