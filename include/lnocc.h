@@ -53,8 +53,15 @@ typedef enum {
  * residual norms and DIIS stay FP64 in every mode. */
 typedef enum {
   LNOCC_FP64 = 0,
-  LNOCC_FP32 = 1, /* FP32 matrix-core products, FP32 accumulation per tile */
-  LNOCC_BF16 = 2  /* BF16 matrix-core products (round to nearest even), FP32 accumulation */
+  LNOCC_FP32 = 1, /* FP32 storage; FP32-accurate products: on the FP32 matrix cores, or
+                     split as in LNOCC_FP32_SPLIT where that is faster (the ladder
+                     contraction; the autotuner may pick either per shape); FP32
+                     accumulation per tile */
+  LNOCC_BF16 = 2, /* BF16 matrix-core products (round to nearest even), FP32 accumulation */
+  LNOCC_FP32_SPLIT = 3 /* lnocc_contract only (not a solve precision): FP32 operands, each
+                          split into three bf16 parts (round to nearest even); a product is
+                          the sum of the six largest part products on the BF16 matrix
+                          cores, FP32 accumulation: FP32-level accuracy at BF16 rates */
 } lnocc_precision_t;
 
 typedef enum {
@@ -197,7 +204,8 @@ int lnocc_batch_solve(lnocc_fragment_t *f, int32_t nfrag, const lnocc_options_t 
  * moves each base pointer by b0*(e / nb1) + b1*(e % nb1) + bid*e.  All strides
  * are in elements.  precision selects the operand element type and product
  * arithmetic (LNOCC_FP64: double; LNOCC_FP32: float, FP32 accumulation;
- * LNOCC_BF16: bf16 bit patterns, FP32 accumulation); C is always FP64. */
+ * LNOCC_BF16: bf16 bit patterns, FP32 accumulation; LNOCC_FP32_SPLIT: float,
+ * split bf16 products, FP32 accumulation); C is always FP64. */
 typedef struct lnocc_operand_t {
   const double *p;
   int64_t s_ro, s_ri, s_ko, s_ki;
@@ -215,9 +223,11 @@ typedef struct lnocc_contract_t {
   double beta;
   int32_t batch, nb1;
   int32_t precision;             /* lnocc_precision_t of the operands */
-  int32_t tile;                  /* 0: automatic (tuned plan or heuristic); 1..6 force a tile
+  int32_t tile;                  /* 0: automatic (tuned plan or heuristic); 1..7 force a tile
                                     of 128x128, 128x80, 128x64, 32x32, 128x160, 256x128
-                                    rows x columns (the last two FP32 only; ignored otherwise) */
+                                    rows x columns, or 7: 128x128 with the products of
+                                    LNOCC_FP32_SPLIT (5..7 for LNOCC_FP32 operands only;
+                                    ignored otherwise) */
 } lnocc_contract_t;
 
 int lnocc_contract(const lnocc_contract_t *desc, void *stream);

@@ -15,7 +15,9 @@
 
 namespace lnocc {
 
-enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2 };
+// F32S: FP32 operands whose products run on the bf16 matrix cores as sums of
+// split products (FP32-level accuracy; see the kernel source).
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2, F32S = 3 };
 
 // What a contraction computes; each class is its own kernel symbol (so
 // profiler statistics separate them) and its own timing bucket.

@@ -40,6 +40,8 @@ typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 // row(lane, r): output row of accumulator register r.
 struct ModeF64 {
   using T = double;
+  using L = double;                               // LDS element
+  static constexpr int kPlanes = 1;               // LDS tiles per operand slice
   using Acc = double4_t;
   static constexpr int KS = 4, BK = 16;
   static constexpr bool kRowMajor = false;        // LDS tile [k][row]
@@ -48,6 +50,8 @@ struct ModeF64 {
 };
 struct ModeF32 {
   using T = float;
+  using L = float;
+  static constexpr int kPlanes = 1;
   using Acc = float4_t;
   static constexpr int KS = 4, BK = 16;
   static constexpr bool kRowMajor = false;
@@ -56,9 +60,27 @@ struct ModeF32 {
 };
 struct ModeBF16 {
   using T = uint16_t;                              // bf16 bit pattern
+  using L = uint16_t;
+  static constexpr int kPlanes = 1;
   using Acc = float4_t;
   static constexpr int KS = 32, BK = 32;
   static constexpr bool kRowMajor = true;         // LDS tile [row][k]: 8 k per lane read at once
+  __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
+// FP32 operands multiplied on the bf16 matrix cores: each element x is split
+// into x = h + m + l + e with h = bf16(x), m = bf16(x - h), l = bf16(x - h - m)
+// (round to nearest even; both differences are exact in FP32, |e| <= 2^-27 |x|),
+// and a product is the sum of the six split products h h', h m', m h', h l',
+// l h', m m' (the dropped ones are below 2^-24 of it), accumulated in FP32
+// (Henry, Tang and Heinecke, ARITH 2019).  The splits are made once per element
+// when the slice is written to LDS, as three bf16 tiles.
+struct ModeF32S {
+  using T = float;
+  using L = uint16_t;
+  static constexpr int kPlanes = 3;
+  using Acc = float4_t;
+  static constexpr int KS = 32, BK = 32;
+  static constexpr bool kRowMajor = true;
   __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
 };
 
@@ -87,8 +109,11 @@ using Wide160 = Cfg<128, 160, 4, 1>; // 4 waves, 32 x 160 (2 x 10) each: N = 160
 using Tall = Cfg<256, 128, 4, 2>;    // 8 waves, 64 x 64 (4 x 4) each
 
 // Tile ids of the launcher and the autotuner (rows x columns per workgroup).
-constexpr int kTileBM[6] = {128, 128, 128, 32, 128, 256};
-constexpr int kTileBN[6] = {128, 80, 64, 32, 160, 128};
+// Id 6 is the 128 x 128 tile with FP32 products evaluated as split bf16
+// products (an arithmetic choice for FP32 contractions, same accuracy class).
+constexpr int kTileBM[7] = {128, 128, 128, 32, 128, 256, 128};
+constexpr int kTileBN[7] = {128, 80, 64, 32, 160, 128, 128};
+constexpr int kTileSplit = 6;
 
 struct BatchIdx { int64_t i0, i1, i2; };
 
@@ -127,6 +152,17 @@ template <> struct BitsOf<uint16_t> { using U = uint16_t; };
 template <class M> __device__ inline typename M::T scaled(typename M::T x, double s);
 template <> __device__ inline double scaled<ModeF64>(double x, double s) { return s * x; }
 template <> __device__ inline float scaled<ModeF32>(float x, double s) { return (float)s * x; }
+template <> __device__ inline float scaled<ModeF32S>(float x, double s) { return (float)s * x; }
+
+__device__ inline uint16_t bf16_rn_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+// x -> (h, m, l) of the split-product mode
+__device__ inline void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
+  h = bf16_rn_bits(x);
+  const float r1 = x - bf16_to_f32(h);
+  m = bf16_rn_bits(r1);
+  const float r2 = r1 - bf16_to_f32(m);
+  l = bf16_rn_bits(r2);
+}
 // (scale = 1 for the B operand: the multiply folds away after inlining)
 template <> __device__ inline uint16_t scaled<ModeBF16>(uint16_t x, double s) {
   return s == 1.0 ? x : f32_to_bf16((float)s * bf16_to_f32(x));
@@ -200,26 +236,67 @@ struct Slice {
       }
     }
   }
-  // LDS tile: [k][row] with leading dimension LD, or [row][k] (kRowMajor).
-  template <int LD>
-  __device__ static void store(E *lds, bool kfast, const E *reg, uint32_t okbits, double scale) {
+  // LDS tile: [k][row] with leading dimension LD, or [row][k] (kRowMajor);
+  // split-product mode: three [row][k] tiles PS elements apart.
+  template <int LD, int PS>
+  __device__ static void store(typename M::L *lds, bool kfast, const E *reg, uint32_t okbits,
+                               double scale) {
     using U = typename BitsOf<E>::U;
 #pragma unroll
     for (int s = 0; s < PER; ++s) {
       const U m = ((okbits >> s) & 1u) ? (U)~(U)0 : (U)0;
       const E x = scaled<M>(__builtin_bit_cast(E, (U)(__builtin_bit_cast(U, reg[s]) & m)), scale);
-      if (M::kRowMajor) lds[row_of(kfast, s) * LD + k_of(kfast, s)] = x;
-      else lds[k_of(kfast, s) * LD + row_of(kfast, s)] = x;
+      if constexpr (M::kPlanes == 3) {
+        uint16_t h, mid, l;
+        split3(x, h, mid, l);
+        const int o = row_of(kfast, s) * LD + k_of(kfast, s);
+        lds[o] = h;
+        lds[PS + o] = mid;
+        lds[2 * PS + o] = l;
+      } else if (M::kRowMajor) {
+        lds[row_of(kfast, s) * LD + k_of(kfast, s)] = x;
+      } else {
+        lds[k_of(kfast, s) * LD + row_of(kfast, s)] = x;
+      }
     }
   }
 };
 
 // One LDS slice of MFMA steps.
-template <class M, class C, int LDA, int LDB>
-__device__ inline void mma_slice_impl(const typename M::T *Ab, const typename M::T *Bb, int lane,
+template <class M, class C, int LDA, int LDB, int PSA, int PSB>
+__device__ inline void mma_slice_impl(const typename M::L *Ab, const typename M::L *Bb, int lane,
                                       int wm, int wn, typename M::Acc (&acc)[C::MI][C::NI]) {
   const int mw = wm * (C::BM / C::WM), nw = wn * (C::BN / C::WN);
-  if constexpr (M::kRowMajor) {
+  if constexpr (M::kPlanes == 3) {
+    // planes 0, 1, 2 = h, m, l; the six split products, each pass over all
+    // (i, j) blocks so that consecutive matrix ops use different accumulators
+    constexpr int kA[6] = {0, 0, 1, 0, 2, 1};
+    constexpr int kB[6] = {0, 1, 0, 2, 0, 1};
+#pragma unroll
+    for (int kk = 0; kk < M::BK; kk += M::KS) {
+      bf16x8_t af[3][C::MI], bf[3][C::NI];
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+#pragma unroll
+        for (int i = 0; i < C::MI; ++i) {
+          const u16x8_t raw = *(const u16x8_t *)(Ab + p * PSA + (mw + i * 16 + lane % 16) * LDA + kk + 8 * (lane / 16));
+          af[p][i] = __builtin_bit_cast(bf16x8_t, raw);
+        }
+#pragma unroll
+        for (int j = 0; j < C::NI; ++j) {
+          const u16x8_t raw = *(const u16x8_t *)(Bb + p * PSB + (nw + j * 16 + lane % 16) * LDB + kk + 8 * (lane / 16));
+          bf[p][j] = __builtin_bit_cast(bf16x8_t, raw);
+        }
+      }
+#pragma unroll
+      for (int t = 5; t >= 0; --t)   // smallest products first
+#pragma unroll
+        for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+          for (int j = 0; j < C::NI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[kA[t]][i], bf[kB[t]][j], acc[i][j], 0, 0, 0);
+    }
+  } else if constexpr (M::kRowMajor) {
     // bf16: lane reads 8 consecutive k of row (lane % 16) starting at 8 (lane / 16)
 #pragma unroll
     for (int kk = 0; kk < M::BK; kk += M::KS) {
@@ -346,8 +423,10 @@ __global__ __launch_bounds__(C::T) void gett_kernel(GemmDesc d, int tiles_m, int
   constexpr int LDB = M::kRowMajor ? BK + 8 : C::BN + 4;
   constexpr int SZA = M::kRowMajor ? C::BM * LDA : BK * LDA;
   constexpr int SZB = M::kRowMajor ? C::BN * LDB : BK * LDB;
-  __shared__ __attribute__((aligned(16))) E As[2][SZA];
-  __shared__ __attribute__((aligned(16))) E Bs[2][SZB];
+  using LE = typename M::L;
+  constexpr int NP = M::kPlanes;
+  __shared__ __attribute__((aligned(16))) LE As[2][NP * SZA];
+  __shared__ __attribute__((aligned(16))) LE Bs[2][NP * SZB];
 
   const int tile = blockIdx.x;
   const int tm = tile % tiles_m, tn = tile / tiles_m;
@@ -392,8 +471,8 @@ __global__ __launch_bounds__(C::T) void gett_kernel(GemmDesc d, int tiles_m, int
     sa.load(pa, S.a, S.kdiv, akf, S.K, lo * BK, ra, oka);
     sb.load(pb, S.b, S.kdiv, bkf, S.K, lo * BK, rb, okb);
     __syncthreads();   // previous segment may still read buffer 0
-    SA::template store<LDA>(As[0], akf, ra, oka, S.scale);
-    SB::template store<LDB>(Bs[0], bkf, rb, okb, 1.0);
+    SA::template store<LDA, SZA>(As[0], akf, ra, oka, S.scale);
+    SB::template store<LDB, SZB>(Bs[0], bkf, rb, okb, 1.0);
     __syncthreads();
     for (int q = lo; q < hi; ++q) {
       const int buf = (q - lo) & 1;
@@ -401,10 +480,10 @@ __global__ __launch_bounds__(C::T) void gett_kernel(GemmDesc d, int tiles_m, int
         sa.load(pa, S.a, S.kdiv, akf, S.K, (q + 1) * BK, ra, oka);
         sb.load(pb, S.b, S.kdiv, bkf, S.K, (q + 1) * BK, rb, okb);
       }
-      mma_slice_impl<M, C, LDA, LDB>(As[buf], Bs[buf], lane, wm, wn, acc);
+      mma_slice_impl<M, C, LDA, LDB, SZA, SZB>(As[buf], Bs[buf], lane, wm, wn, acc);
       if (q + 1 < hi) {
-        SA::template store<LDA>(As[buf ^ 1], akf, ra, oka, S.scale);
-        SB::template store<LDB>(Bs[buf ^ 1], bkf, rb, okb, 1.0);
+        SA::template store<LDA, SZA>(As[buf ^ 1], akf, ra, oka, S.scale);
+        SB::template store<LDB, SZB>(Bs[buf ^ 1], bkf, rb, okb, 1.0);
       }
       __syncthreads();
     }
@@ -544,7 +623,7 @@ bool operand_ok(const GemmDesc &d, const GOperand &op, int64_t rows, int64_t Ri,
   add_term(s, bmax[1], op.b1);
   add_term(s, bmax[2], op.b2);
   add_term(s, d.batch - 1, op.bid);
-  const size_t esz = d.prec == Prec::F64 ? 8 : (d.prec == Prec::F32 ? 4 : 2);
+  const size_t esz = d.prec == Prec::F64 ? 8 : (d.prec == Prec::BF16 ? 2 : 4);
   return inside(op.p, s, esz);
 }
 
@@ -663,6 +742,7 @@ void launch(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stre
   switch (d.prec) {
     case Prec::F32: launch_kind<ModeF32, C>(d, grid, tiles_m, sps, stream); break;
     case Prec::BF16: launch_kind<ModeBF16, C>(d, grid, tiles_m, sps, stream); break;
+    case Prec::F32S: launch_kind<ModeF32S, C>(d, grid, tiles_m, sps, stream); break;
     default: launch_kind<ModeF64, C>(d, grid, tiles_m, sps, stream); break;
   }
 }
@@ -695,13 +775,14 @@ void install_splitk_scratch(double *p, size_t elems) {
 }
 
 // ---------------------------------------------------------------- autotuning
-// Candidate c = (tile, split rule): tiles 128x128, 128x80, 128x64, 32x32; split
-// rules: the cost-model split, no split, twice the cost-model split.  While a
+// Candidate c = (tile, split rule): tiles 128x128, 128x80, 128x64, 32x32 (and,
+// for FP32 products, 128x160, 256x128 and 128x128 with split bf16 products);
+// split rules: the cost-model split, no split, twice the cost-model split.  While a
 // candidate is active every launch is timed with events under its shape key;
 // tune_commit() keeps, per key, the fastest candidate's (tile, split count),
 // which later launches of that shape use instead of the heuristic.
 namespace {
-constexpr int kTileCands = 6, kSplitRules = 3;
+constexpr int kTileCands = 7, kSplitRules = 3;
 struct TilePlan { int tile; int nsplit; };
 std::mutex g_plan_mu;
 std::map<std::string, TilePlan> g_plans;
@@ -806,15 +887,20 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   d.splitk = nullptr;
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   if (d.Mi <= 0 || d.Ni <= 0 || d.nseg <= 0 || d.nseg > kMaxSeg) return hipErrorInvalidValue;
-  const int bk = (d.prec == Prec::BF16) ? 32 : 16;   // k per LDS slice of the mode
-  int slices = 0;
+  // k per LDS slice: 32 for the bf16 matrix-core arithmetics, else 16
+  auto tile_bk = [&](int t) {
+    return (d.prec == Prec::BF16 || d.prec == Prec::F32S || t == kTileSplit) ? 32 : 16;
+  };
+  int slices16 = 0, slices32 = 0;
   for (int s = 0; s < d.nseg; ++s) {
     if (d.seg[s].K < 0 || d.seg[s].Ki <= 0) return hipErrorInvalidValue;
     d.seg[s].a_kfast = contiguous_along_k(d.seg[s].a, d.seg[s].Ki);
     d.seg[s].b_kfast = contiguous_along_k(d.seg[s].b, d.seg[s].Ki);
     d.seg[s].kdiv = make_fastdiv((uint32_t)d.seg[s].Ki);
-    slices += (d.seg[s].K + bk - 1) / bk;
+    slices16 += (d.seg[s].K + 15) / 16;
+    slices32 += (d.seg[s].K + 31) / 32;
   }
+  auto tile_slices = [&](int t) { return tile_bk(t) == 32 ? slices32 : slices16; };
   if (d.batch > 65535) return hipErrorInvalidValue;
   if (d.table == nullptr && d.nb1 <= 0) return hipErrorInvalidValue;
   d.mdiv = make_fastdiv((uint32_t)d.Mi);
@@ -845,7 +931,9 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   const int64_t cap = g_splitk ? (int64_t)(g_splitk_elems / ((size_t)d.M * d.N)) : 0;
   // Split K when the tiles alone leave the chip idle: thin outputs with long K,
   // or a tile count that fills the last round of workgroups poorly.
-  auto heuristic_split = [&](bool sm, int bm, int bn) {
+  auto heuristic_split = [&](int t) {
+    const bool sm = t == 3;
+    const int bm = kTileBM[t], bn = kTileBN[t], bk = tile_bk(t), slices = tile_slices(t);
     int ns_out = 1;
     const int64_t tiles = (int64_t)((d.M + bm - 1) / bm) * ((d.N + bn - 1) / bn) * d.batch;
     if (d.batch != 1 || cap < 2) return 1;
@@ -872,9 +960,11 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
     }
     return ns_out;
   };
+  // the ladder contraction (long K, large output) of the FP32 modes: split products
+  if (d.prec == Prec::F32 && d.kind == Kind::LadderContract && tile != 3) tile = kTileSplit;
   if (d.tile_hint > 0 && d.tile_hint <= kTileCands && (d.tile_hint <= 4 || d.prec == Prec::F32))
     tile = d.tile_hint - 1;
-  int nsplit = heuristic_split(tile == 3, kTileBM[tile], kTileBN[tile]);
+  int nsplit = heuristic_split(tile);
   // autotuning: a probe pass only collects keys; a candidate overrides the
   // choice (and is timed); otherwise a stored plan for this shape is used
   std::string key;
@@ -894,25 +984,27 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
     if (g_cand >= 0) {
       cand = g_cand;
       set_tile(cand / kSplitRules);
-      const int h = heuristic_split(tile == 3, kTileBM[tile], kTileBN[tile]);
+      const int h = heuristic_split(tile);
       const int rule = cand % kSplitRules;
       nsplit = (rule == 0) ? h : (rule == 1) ? 1 : std::max(2, 2 * h);
       if (d.batch != 1) nsplit = 1;
       nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nsplit, cap < 2 ? 1 : cap,
-                                                            (int64_t)slices}));
+                                                            (int64_t)tile_slices(tile)}));
     } else {
       std::lock_guard<std::mutex> lock(g_plan_mu);
       auto it = g_plans.find(key);
       if (it != g_plans.end()) {
         set_tile(it->second.tile);
         nsplit = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)it->second.nsplit,
-                                                              cap < 2 ? 1 : cap, (int64_t)slices}));
+                                                              cap < 2 ? 1 : cap,
+                                                              (int64_t)tile_slices(tile)}));
         if (d.batch != 1) nsplit = 1;
       }
     }
   }
   const int BMx = kTileBM[tile], BNx = kTileBN[tile];
   const int tiles_m = (d.M + BMx - 1) / BMx, tiles_n = (d.N + BNx - 1) / BNx;
+  const int slices = tile_slices(tile);
   const int sps = (slices + nsplit - 1) / nsplit;
   nsplit = (slices + sps - 1) / sps;
   if (nsplit > 1) d.splitk = g_splitk;
@@ -938,6 +1030,12 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
     case 3: launch<Small>(d, grid, tiles_m, sps, stream); break;
     case 4: launch_f32<Wide160>(d, grid, tiles_m, sps, stream); break;
     case 5: launch_f32<Tall>(d, grid, tiles_m, sps, stream); break;
+    case kTileSplit: {
+      GemmDesc e = d;
+      e.prec = Prec::F32S;
+      launch<Big>(e, grid, tiles_m, sps, stream);
+      break;
+    }
     default: launch<Big>(d, grid, tiles_m, sps, stream); break;
   }
   hipError_t err = hipGetLastError();
@@ -964,12 +1062,13 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
       const GSegment &g = d.seg[0];
       std::snprintf(buf, sizeof(buf),
                     "k%d p%d M%d/%d N%d/%d K%d/%d seg%d b%d | A %lld %lld %lld %lld | B %lld %lld "
-                    "%lld %lld | C %lld %lld %lld %lld | tile %dx%d split %d",
+                    "%lld %lld | C %lld %lld %lld %lld | tile %dx%d%s split %d",
                     (int)d.kind, (int)d.prec, d.M, d.Mi, d.N, d.Ni, g.K, g.Ki, d.nseg, d.batch,
                     (long long)g.a.s_ro, (long long)g.a.s_ri, (long long)g.a.s_ko,
                     (long long)g.a.s_ki, (long long)g.b.s_ro, (long long)g.b.s_ri,
                     (long long)g.b.s_ko, (long long)g.b.s_ki, (long long)d.c_mo,
-                    (long long)d.c_mi, (long long)d.c_no, (long long)d.c_ni, BMx, BNx, nsplit);
+                    (long long)d.c_mi, (long long)d.c_no, (long long)d.c_ni, BMx, BNx,
+                    tile == kTileSplit ? " bf16-split" : "", nsplit);
       shape = buf;
     }
     g_records.push_back(Record{d.kind, ev[0], ev[1], flops * d.batch, shape});

@@ -157,12 +157,13 @@ def test_contract_low_precision(M, N, K):
     assert err < 2e-6 * np.sqrt(K), err
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_contract_every_tile(tile, precision):
     """Each tile shape of the launcher (forced) on a ragged, segmented, two-index
-    product, FP64 and FP32 operands (the 128x160 and 256x128 tiles are FP32 only;
-    FP64 falls back to the automatic choice)."""
+    product, FP64 and FP32 operands (the 128x160 and 256x128 tiles and the split
+    bf16 products of tile 7 are for FP32 operands only; FP64 falls back to the
+    automatic choice)."""
     say(f"contract tile {tile} precision {precision}")
     rng = np.random.default_rng(100 + tile)
     M, N, K1, K2 = 301, 263, 45, 19
@@ -183,7 +184,7 @@ def test_contract_every_tile(tile, precision):
 
 
 @pytest.mark.parametrize("shift", [0, 1])
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_contract_column_major_output(tile, precision, shift):
     """Outputs whose row index is the contiguous one (C[e][n][mo][mi]), read and
@@ -211,6 +212,60 @@ def test_contract_column_major_output(tile, precision, shift):
     got = host(c).reshape(nb, N, M)
     err = np.abs(got - ref).max() / np.abs(ref).max()
     assert err < (1e-14 if precision == 0 else 2e-6 * np.sqrt(K)), err
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+def test_contract_split_products_exact(tile):
+    """Split bf16 products (LNOCC_FP32_SPLIT) on operands x = s (1 + c 2^-9),
+    s = +-1, c in {-1, 0, 1}: x needs 10 significant bits, so it splits into a
+    bf16 high part s and a nonzero middle part s c 2^-9.  Every part product the
+    kernel forms is exact, and with K = 16 every partial sum fits FP32's 24 bits,
+    so C must equal the exact product bit for bit; dropping the middle-part
+    products (h m', m h', m m') would change it by multiples of 2^-18."""
+    say(f"contract split products exact tile {tile}")
+    rng = np.random.default_rng(40 + tile)
+    M, N, K = 133, 70, 16
+
+    def draw(*shape):
+        sgn = rng.choice([-1.0, 1.0], size=shape)
+        return sgn * (1.0 + rng.integers(-1, 2, size=shape) * 2.0 ** -9)
+
+    A, Bm = draw(M, K), draw(N, K)
+    ref = A @ Bm.T                                   # exact in FP64 (<= 30 bits)
+    c = torch.zeros((M, N), dtype=torch.float64, device=DEV)
+    a_t = torch.tensor(A.astype(np.float32), device=DEV)
+    b_t = torch.tensor(Bm.astype(np.float32), device=DEV)
+    _contract(M, 1, N, 1, c, (N, 0, 1, 0),
+              [(K, 1, 1.0, _operand(a_t, K, 0, 1, 0), _operand(b_t, K, 0, 1, 0))],
+              precision=L.LNOCC_FP32_SPLIT, tile=tile)
+    np.testing.assert_array_equal(host(c), ref)
+
+
+@pytest.mark.parametrize("tile", [0, 1, 3])
+def test_contract_split_products_accuracy(tile):
+    """Split bf16 products on full-mantissa FP32 operands: FP32-level accuracy
+    (the representation error of the three parts is below 2^-27 and the dropped
+    part products below 2^-24 of each product), far from what bf16 operands
+    give on the same data.  Two segments, one with a row-contiguous operand."""
+    say(f"contract split products accuracy tile {tile}")
+    rng = np.random.default_rng(60 + tile)
+    M, N, K1, K2 = 301, 263, 300, 37
+    A1, B1 = rng.standard_normal((M, K1)), rng.standard_normal((N, K1))
+    A2, B2 = rng.standard_normal((K2, M)), rng.standard_normal((N, K2))
+    A1, B1, A2, B2 = (x.astype(np.float32) for x in (A1, B1, A2, B2))
+    ref = (A1.astype(np.float64) @ B1.astype(np.float64).T
+           + 0.25 * A2.astype(np.float64).T @ B2.astype(np.float64).T)
+    t = [torch.tensor(x, device=DEV) for x in (A1, B1, A2, B2)]
+    segs = [(K1, 1, 1.0, _operand(t[0], K1, 0, 1, 0), _operand(t[1], K1, 0, 1, 0)),
+            (K2, 1, 0.25, _operand(t[2], 1, 0, M, 0), _operand(t[3], K2, 0, 1, 0))]
+    errs = {}
+    for prec in (L.LNOCC_FP32, L.LNOCC_FP32_SPLIT):
+        c = torch.zeros((M, N), dtype=torch.float64, device=DEV)
+        _contract(M, 1, N, 1, c, (N, 0, 1, 0), segs, precision=prec, tile=tile)
+        errs[prec] = np.abs(host(c) - ref).max() / np.abs(ref).max()
+    say(f"  relative error fp32 {errs[L.LNOCC_FP32]:.2e} split {errs[L.LNOCC_FP32_SPLIT]:.2e}")
+    assert errs[L.LNOCC_FP32_SPLIT] < 2e-6 * np.sqrt(K1 + K2)
+    assert errs[L.LNOCC_FP32_SPLIT] < 4 * errs[L.LNOCC_FP32] + 1e-7
 
 
 # ------------------------------------------------------------ solver pieces
