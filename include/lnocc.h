@@ -223,11 +223,11 @@ typedef struct lnocc_contract_t {
   double beta;
   int32_t batch, nb1;
   int32_t precision;             /* lnocc_precision_t of the operands */
-  int32_t tile;                  /* 0: automatic (tuned plan or heuristic); 1..7 force a tile
+  int32_t tile;                  /* 0: automatic (tuned plan or heuristic); 1..8 force a tile
                                     of 128x128, 128x80, 128x64, 32x32, 128x160, 256x128
-                                    rows x columns, or 7: 128x128 with the products of
-                                    LNOCC_FP32_SPLIT (5..7 for LNOCC_FP32 operands only;
-                                    ignored otherwise) */
+                                    rows x columns, 7: 128x128 with the products of
+                                    LNOCC_FP32_SPLIT, 8: 160x160 (5..7 for LNOCC_FP32
+                                    operands only, 8 for LNOCC_FP64 only; ignored otherwise) */
 } lnocc_contract_t;
 
 int lnocc_contract(const lnocc_contract_t *desc, void *stream);

@@ -655,7 +655,7 @@ int lnocc_contract(const lnocc_contract_t *c, void *stream) {
   if (c->precision < 0 || c->precision > 3) return LNOCC_EINVAL;
   d.prec = (Prec)c->precision;
   d.c_type = 0;
-  if (c->tile < 0 || c->tile > 7) return LNOCC_EINVAL;
+  if (c->tile < 0 || c->tile > 8) return LNOCC_EINVAL;
   d.tile_hint = c->tile;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = gett(d, s);

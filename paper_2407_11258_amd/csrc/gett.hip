@@ -107,13 +107,23 @@ using Small = Cfg<32, 32, 1, 1>;
 // LDS slice to cover the load latency of the faster FP32 matrix cores.
 using Wide160 = Cfg<128, 160, 4, 1>; // 4 waves, 32 x 160 (2 x 10) each: N = 160
 using Tall = Cfg<256, 128, 4, 2>;    // 8 waves, 64 x 64 (4 x 4) each
+// FP64 only: 10 waves, 32 x 80 (2 x 5) each.  An ov x ov output (2560 x 2560 for
+// 16 occupied and 160 virtual orbitals) is exactly 256 of these tiles, one per
+// CU, where 128 x 128 tiles leave the second round of workgroups half empty.
+using Sq160 = Cfg<160, 160, 5, 2>;
 
 // Tile ids of the launcher and the autotuner (rows x columns per workgroup).
 // Id 6 is the 128 x 128 tile with FP32 products evaluated as split bf16
 // products (an arithmetic choice for FP32 contractions, same accuracy class).
-constexpr int kTileBM[7] = {128, 128, 128, 32, 128, 256, 128};
-constexpr int kTileBN[7] = {128, 80, 64, 32, 160, 128, 128};
-constexpr int kTileSplit = 6;
+constexpr int kTileBM[8] = {128, 128, 128, 32, 128, 256, 128, 160};
+constexpr int kTileBN[8] = {128, 80, 64, 32, 160, 128, 128, 160};
+constexpr int kTileSplit = 6, kTileSq160 = 7;
+// tiles 4..6 serve FP32 operands only, tile 7 FP64 only
+inline bool tile_valid(int t, Prec p) {
+  if (t < 0 || t > 7) return false;
+  if (t < 4) return true;
+  return t == kTileSq160 ? p == Prec::F64 : p == Prec::F32;
+}
 
 struct BatchIdx { int64_t i0, i1, i2; };
 
@@ -182,7 +192,11 @@ struct Slice {
   static constexpr int PER = R * BK / T;
   static constexpr int RG = R / 16;
   static constexpr int KG = PER >= RG ? PER / RG : 1;
-  static_assert(PER % RG == 0 || RG % PER == 0, "row groups must tile the thread share");
+  // When the thread share and the row groups do not tile each other (160-row
+  // tiles of 640 threads), the not-kfast layout is element s -> (row t % R,
+  // k t / R + s T / R): one row per thread, consecutive threads on consecutive rows.
+  static constexpr bool kWide = !(PER % RG == 0 || RG % PER == 0);
+  static_assert(!kWide || (T % R == 0 && (T / R) * PER == BK), "wide layout needs T = n R");
   static_assert(PER <= 32, "in-range flags are kept in one 32-bit mask");
   using E = typename M::T;
   int64_t roff[PER];
@@ -190,11 +204,15 @@ struct Slice {
 
   __device__ static int row_of(bool kfast, int s) {
     const int t = threadIdx.x;
-    return kfast ? t / BK + s * (T / BK) : t % 16 + 16 * (((t / 16) * PER + s) % RG);
+    if (kfast) return t / BK + s * (T / BK);
+    if constexpr (kWide) return t % R;
+    return t % 16 + 16 * (((t / 16) * PER + s) % RG);
   }
   __device__ static int k_of(bool kfast, int s) {
     const int t = threadIdx.x;
-    return kfast ? t % BK : ((t / 16) * PER + s) / RG;
+    if (kfast) return t % BK;
+    if constexpr (kWide) return t / R + s * (T / R);
+    return ((t / 16) * PER + s) / RG;
   }
   __device__ void init(const GOperand &op, const FastDiv &rdiv, bool kfast, int nrows, int row0) {
 #pragma unroll
@@ -215,6 +233,16 @@ struct Slice {
 #pragma unroll
       for (int s = 0; s < PER; ++s) {
         const bool ok = kok && rok[s];
+        okbits |= (uint32_t)ok << s;
+        reg[s] = base[ok ? roff[s] + ko : 0];
+      }
+    } else if constexpr (kWide) {
+#pragma unroll
+      for (int s = 0; s < PER; ++s) {
+        const int k = k0 + k_of(false, s);
+        const bool kin = k < K;
+        const int64_t ko = kin ? two_index_off(kdiv, (uint32_t)k, op.s_ko, op.s_ki) : 0;
+        const bool ok = kin && rok[s];
         okbits |= (uint32_t)ok << s;
         reg[s] = base[ok ? roff[s] + ko : 0];
       }
@@ -738,6 +766,10 @@ void launch_f32(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t 
   launch_kind<ModeF32, C>(d, grid, tiles_m, sps, stream);
 }
 template <class C>
+void launch_f64(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
+  launch_kind<ModeF64, C>(d, grid, tiles_m, sps, stream);
+}
+template <class C>
 void launch(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
   switch (d.prec) {
     case Prec::F32: launch_kind<ModeF32, C>(d, grid, tiles_m, sps, stream); break;
@@ -776,13 +808,14 @@ void install_splitk_scratch(double *p, size_t elems) {
 
 // ---------------------------------------------------------------- autotuning
 // Candidate c = (tile, split rule): tiles 128x128, 128x80, 128x64, 32x32 (and,
-// for FP32 products, 128x160, 256x128 and 128x128 with split bf16 products);
+// for FP32 products, 128x160, 256x128 and 128x128 with split bf16 products;
+// for FP64 products, 160x160);
 // split rules: the cost-model split, no split, twice the cost-model split.  While a
 // candidate is active every launch is timed with events under its shape key;
 // tune_commit() keeps, per key, the fastest candidate's (tile, split count),
 // which later launches of that shape use instead of the heuristic.
 namespace {
-constexpr int kTileCands = 7, kSplitRules = 3;
+constexpr int kTileCands = 8, kSplitRules = 3;
 struct TilePlan { int tile; int nsplit; };
 std::mutex g_plan_mu;
 std::map<std::string, TilePlan> g_plans;
@@ -962,8 +995,20 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   };
   // the ladder contraction (long K, large output) of the FP32 modes: split products
   if (d.prec == Prec::F32 && d.kind == Kind::LadderContract && tile != 3) tile = kTileSplit;
-  if (d.tile_hint > 0 && d.tile_hint <= kTileCands && (d.tile_hint <= 4 || d.prec == Prec::F32))
-    tile = d.tile_hint - 1;
+  // FP64 with 160 x 160 tiles when the cost model (rounds of one workgroup per
+  // CU x slices, plus partial sums) prefers them
+  auto model = [&](int t, int ns) {
+    const int bm = kTileBM[t], bn = kTileBN[t], sl = tile_slices(t);
+    const int64_t tiles = (int64_t)((d.M + bm - 1) / bm) * ((d.N + bn - 1) / bn) * d.batch;
+    const double t_slice = 2.0 * bm * bn * tile_bk(t) / (45e12 / kCUs);
+    return (double)((tiles * ns + kCUs - 1) / kCUs) * ((sl + ns - 1) / ns) * t_slice +
+           (ns > 1 ? 16.0 * ns * d.M * (double)d.N / 4e12 : 0.0);
+  };
+  if (d.prec == Prec::F64 && tile != 3 && d.M >= 160 && d.N >= 160 &&
+      d.kind != Kind::LadderBuild &&
+      model(kTileSq160, heuristic_split(kTileSq160)) < 0.95 * model(tile, heuristic_split(tile)))
+    tile = kTileSq160;
+  if (d.tile_hint > 0 && tile_valid(d.tile_hint - 1, d.prec)) tile = d.tile_hint - 1;
   int nsplit = heuristic_split(tile);
   // autotuning: a probe pass only collects keys; a candidate overrides the
   // choice (and is timed); otherwise a stored plan for this shape is used
@@ -979,7 +1024,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
     }
     // the FP32-only tiles stand in for the heuristic choice in other precisions
     auto set_tile = [&](int t) {
-      if (t >= 0 && t < kTileCands && (t < 4 || d.prec == Prec::F32)) tile = t;
+      if (tile_valid(t, d.prec)) tile = t;
     };
     if (g_cand >= 0) {
       cand = g_cand;
@@ -1030,6 +1075,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
     case 3: launch<Small>(d, grid, tiles_m, sps, stream); break;
     case 4: launch_f32<Wide160>(d, grid, tiles_m, sps, stream); break;
     case 5: launch_f32<Tall>(d, grid, tiles_m, sps, stream); break;
+    case kTileSq160: launch_f64<Sq160>(d, grid, tiles_m, sps, stream); break;
     case kTileSplit: {
       GemmDesc e = d;
       e.prec = Prec::F32S;

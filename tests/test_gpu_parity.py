@@ -157,34 +157,35 @@ def test_contract_low_precision(M, N, K):
     assert err < 2e-6 * np.sqrt(K), err
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_contract_every_tile(tile, precision):
     """Each tile shape of the launcher (forced) on a ragged, segmented, two-index
-    product, FP64 and FP32 operands (the 128x160 and 256x128 tiles and the split
-    bf16 products of tile 7 are for FP32 operands only; FP64 falls back to the
-    automatic choice)."""
+    product, FP64 and FP32 operands, both operands once contiguous along k and
+    once along their row index (the 128x160 and 256x128 tiles and the split bf16
+    products of tile 7 are for FP32 operands only, the 160x160 tile for FP64 only;
+    otherwise the automatic choice runs)."""
     say(f"contract tile {tile} precision {precision}")
     rng = np.random.default_rng(100 + tile)
     M, N, K1, K2 = 301, 263, 45, 19
     A1, B1 = rng.standard_normal((M, K1)), rng.standard_normal((N, K1))
-    A2, B2 = rng.standard_normal((K2, M)), rng.standard_normal((N, K2))
+    A2, B2 = rng.standard_normal((K2, M)), rng.standard_normal((K2, N))
     dt = np.float64 if precision == 0 else np.float32
     A1, B1, A2, B2 = (x.astype(dt) for x in (A1, B1, A2, B2))
     ref = (A1.astype(np.float64) @ B1.astype(np.float64).T
-           - 0.5 * A2.astype(np.float64).T @ B2.astype(np.float64).T)
+           - 0.5 * A2.astype(np.float64).T @ B2.astype(np.float64))
     c = torch.zeros((M, N), dtype=torch.float64, device=DEV)
     t = [torch.tensor(x, device=DEV) for x in (A1, B1, A2, B2)]
     _contract(M, 1, N, 1, c, (N, 0, 1, 0),
               [(K1, 1, 1.0, _operand(t[0], K1, 0, 1, 0), _operand(t[1], K1, 0, 1, 0)),
-               (K2, 1, -0.5, _operand(t[2], 1, 0, M, 0), _operand(t[3], K2, 0, 1, 0))],
+               (K2, 1, -0.5, _operand(t[2], 1, 0, M, 0), _operand(t[3], 1, 0, N, 0))],
               precision=precision, tile=tile)
     err = np.abs(host(c) - ref).max() / np.abs(ref).max()
     assert err < (1e-13 if precision == 0 else 2e-6 * np.sqrt(K1 + K2)), err
 
 
 @pytest.mark.parametrize("shift", [0, 1])
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_contract_column_major_output(tile, precision, shift):
     """Outputs whose row index is the contiguous one (C[e][n][mo][mi]), read and
