@@ -72,6 +72,7 @@ struct GemmDesc {
   int nseg;
   GSegment seg[kMaxSeg];
   void *c;                // output (element type c_type)
+  const void *c_src;      // nullptr, or the input of the beta term (C's layout): C = AB + beta c_src
   int64_t c_mo, c_mi, c_no, c_ni, c_b0, c_b1, c_b2, c_bid;
   double beta;            // 0: C is overwritten without being read
   int batch;              // number of batch entries (>= 1)

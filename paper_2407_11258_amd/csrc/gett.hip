@@ -371,26 +371,32 @@ __device__ inline void mma_slice_impl(const typename M::L *Ab, const typename M:
 template <int BK>
 __device__ inline int seg_slices(const GSegment &S) { return (S.K + BK - 1) / BK; }
 
-__device__ inline void store_out(const GemmDesc &d, void *base, int64_t off, double v) {
+// C[off] = v + beta * src[off]; src is C itself unless the descriptor names a
+// separate input (same layout), which saves copying it into C first.
+__device__ inline void store_out(const GemmDesc &d, void *base, const void *src, int64_t off,
+                                 double v) {
   if (d.c_type == 1) {
     float *p = (float *)base + off;
-    *p = (d.beta == 0.0) ? (float)v : (float)(v + d.beta * (double)*p);
+    *p = (d.beta == 0.0) ? (float)v : (float)(v + d.beta * (double)((const float *)src)[off]);
   } else if (d.c_type == 2) {
     uint16_t *p = (uint16_t *)base + off;
-    *p = f32_to_bf16((d.beta == 0.0) ? (float)v : (float)(v + d.beta * (double)bf16_to_f32(*p)));
+    *p = f32_to_bf16((d.beta == 0.0) ? (float)v
+                                     : (float)(v + d.beta * (double)bf16_to_f32(
+                                                         ((const uint16_t *)src)[off])));
   } else {
     double *p = (double *)base + off;
-    *p = (d.beta == 0.0) ? v : v + d.beta * *p;
+    *p = (d.beta == 0.0) ? v : v + d.beta * ((const double *)src)[off];
   }
 }
 
 // Four consecutive rows of one output column (the FP32 accumulator registers
 // of a lane), stored with one vector access; same rounding as store_out.
-__device__ inline void store_out4(const GemmDesc &d, void *base, int64_t off, float4_t v) {
+__device__ inline void store_out4(const GemmDesc &d, void *base, const void *src, int64_t off,
+                                  float4_t v) {
   if (d.c_type == 1) {
     float4_t *p = (float4_t *)((float *)base + off);
     if (d.beta != 0.0) {
-      const float4_t o = *p;
+      const float4_t o = *(const float4_t *)((const float *)src + off);
 #pragma unroll
       for (int r = 0; r < 4; ++r) v[r] = (float)((double)v[r] + d.beta * (double)o[r]);
     }
@@ -401,7 +407,7 @@ __device__ inline void store_out4(const GemmDesc &d, void *base, int64_t off, fl
 #pragma unroll
     for (int r = 0; r < 4; ++r) w[r] = (double)v[r];
     if (d.beta != 0.0) {
-      const double4_t o = *p;
+      const double4_t o = *(const double4_t *)((const double *)src + off);
 #pragma unroll
       for (int r = 0; r < 4; ++r) w[r] = w[r] + d.beta * o[r];
     }
@@ -409,10 +415,11 @@ __device__ inline void store_out4(const GemmDesc &d, void *base, int64_t off, fl
   }
 }
 
-__device__ inline void store_out4(const GemmDesc &d, void *base, int64_t off, double4_t w) {
+__device__ inline void store_out4(const GemmDesc &d, void *base, const void *src, int64_t off,
+                                  double4_t w) {
   double4_t *p = (double4_t *)((double *)base + off);
   if (d.beta != 0.0) {
-    const double4_t o = *p;
+    const double4_t o = *(const double4_t *)((const double *)src + off);
 #pragma unroll
     for (int r = 0; r < 4; ++r) w[r] = w[r] + d.beta * o[r];
   }
@@ -534,7 +541,9 @@ __global__ __launch_bounds__(C::T) void gett_kernel(GemmDesc d, int tiles_m, int
     return;
   }
   const int esz = d.c_type == 0 ? 8 : (d.c_type == 1 ? 4 : 2);
-  char *pc = (char *)d.c + (bi.i0 * d.c_b0 + bi.i1 * d.c_b1 + bi.i2 * d.c_b2 + id * d.c_bid) * esz;
+  const int64_t cbat = (bi.i0 * d.c_b0 + bi.i1 * d.c_b1 + bi.i2 * d.c_b2 + id * d.c_bid) * esz;
+  char *pc = (char *)d.c + cbat;
+  const char *ps = d.c_src ? (const char *)d.c_src + cbat : pc;
   int64_t coff[C::NI];
   bool cok[C::NI];
 #pragma unroll
@@ -555,9 +564,9 @@ __global__ __launch_bounds__(C::T) void gett_kernel(GemmDesc d, int tiles_m, int
       for (int j = 0; j < C::NI; ++j) {
         if constexpr (std::is_same<E, double>::value) {
           const double4_t w = regroup_rows_f64(acc[i][j], lane);   // whole wave
-          if (mok && cok[j]) store_out4(d, pc, moff + coff[j], w);
+          if (mok && cok[j]) store_out4(d, pc, ps, moff + coff[j], w);
         } else {
-          if (mok && cok[j]) store_out4(d, pc, moff + coff[j], acc[i][j]);
+          if (mok && cok[j]) store_out4(d, pc, ps, moff + coff[j], acc[i][j]);
         }
       }
     }
@@ -573,7 +582,7 @@ __global__ __launch_bounds__(C::T) void gett_kernel(GemmDesc d, int tiles_m, int
 #pragma unroll
       for (int j = 0; j < C::NI; ++j) {
         if (!cok[j]) continue;
-        store_out(d, pc, moff + coff[j], (double)acc[i][j][r]);
+        store_out(d, pc, ps, moff + coff[j], (double)acc[i][j][r]);
       }
     }
   }
@@ -584,7 +593,7 @@ __device__ inline void splitk_store(const GemmDesc &d, int64_t e, double acc) {
   const int m = (int)(e / d.N), n = (int)(e % d.N);
   const int64_t off = (int64_t)(m / d.Mi) * d.c_mo + (int64_t)(m % d.Mi) * d.c_mi +
                       (int64_t)(n / d.Ni) * d.c_no + (int64_t)(n % d.Ni) * d.c_ni;
-  store_out(d, d.c, off, acc);
+  store_out(d, d.c, d.c_src ? d.c_src : d.c, off, acc);
 }
 __global__ void splitk_reduce(GemmDesc d, int nsplit) {
   const int64_t total = (int64_t)d.M * d.N;
@@ -675,6 +684,7 @@ bool descriptor_ok(const GemmDesc &d, int nsplit) {
   add_term(c, bmax[2], d.c_b2);
   add_term(c, d.batch - 1, d.c_bid);
   if (!inside(d.c, c, d.c_type == 0 ? 8 : (d.c_type == 1 ? 4 : 2))) return false;
+  if (d.c_src && !inside(d.c_src, c, d.c_type == 0 ? 8 : (d.c_type == 1 ? 4 : 2))) return false;
   if (nsplit > 1 && !inside(d.splitk, Span{0, (int64_t)nsplit * d.M * d.N - 1}, sizeof(double)))
     return false;
   return true;
@@ -946,7 +956,8 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
     d.c_vec4 = (d.prec != Prec::F64 || d.c_type == 0) && d.c_type != 2 && rows && cols &&
                d.M % 4 == 0 &&
                d.c_b0 % 4 == 0 && d.c_b1 % 4 == 0 && d.c_b2 % 4 == 0 && d.c_bid % 4 == 0 &&
-               (reinterpret_cast<uintptr_t>(d.c) % (4 * esz)) == 0;
+               (reinterpret_cast<uintptr_t>(d.c) % (4 * esz)) == 0 &&
+               (reinterpret_cast<uintptr_t>(d.c_src) % (4 * esz)) == 0;
   }
   // Tile shape: the 32 x 32 single-wave tile for thin outputs; otherwise 128
   // rows by the N width (128, 80 or 64) that pads N least.

@@ -16,6 +16,20 @@ inline int ew_blocks(int64_t n) {
   return (int)b;
 }
 
+// (i, j, a, b) of the flat index e = ((i o + j) v + a) v + b.  Unsigned 32-bit
+// division (a few instructions) whenever o^2 v^2 fits, else 64-bit.
+__device__ inline void split4(int64_t e, int64_t o, int64_t v, int64_t &i, int64_t &j, int64_t &a,
+                              int64_t &b) {
+  if (o * o * v * v <= (int64_t)0xffffffffLL) {
+    const uint32_t ue = (uint32_t)e, uo = (uint32_t)o, uv = (uint32_t)v, uvv = uv * uv;
+    const uint32_t ij = ue / uvv, ab = ue - ij * uvv, ui = ij / uo, ua = ab / uv;
+    i = ui; j = ij - ui * uo; a = ua; b = ab - ua * uv;
+  } else {
+    const int64_t vv = v * v, ij = e / vv, ab = e % vv;
+    i = ij / o; j = ij % o; a = ab / v; b = ab % v;
+  }
+}
+
 __device__ inline double wave_sum(double x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
@@ -78,8 +92,9 @@ __global__ void k_make_u(const double *__restrict__ t2, int64_t o, int64_t v, do
   const int64_t vv = v * v, total = o * o * vv;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ij = e / vv, ab = e % vv, i = ij / o, j = ij % o;
-    u[e] = 2.0 * t2[e] - t2[(j * o + i) * vv + ab];
+    int64_t i, j, a, b;
+    split4(e, o, v, i, j, a, b);
+    u[e] = 2.0 * t2[e] - t2[(j * o + i) * vv + a * v + b];
   }
 }
 
@@ -116,17 +131,39 @@ __global__ void k_sub_oovv(const double *__restrict__ G, int64_t o, int64_t v, d
 }
 
 // R2 += S + S^P - 1/2 (X + X^P) - (Xs + Xs^P), with Y^P[i][j][a][b] = Y[j][i][b][a]
-// and Xs[i][j][a][b] = X[j][i][a][b].
+// and Xs[i][j][a][b] = X[j][i][a][b].  One block per (i, j) pair and 32 x 32 tile
+// of (a, b): the three operands read with a and b exchanged (S[j][i], X[j][i] and
+// X[i][j] at (b, a)) are staged through LDS so that every global access runs
+// along the contiguous index.
+constexpr int kCT = 32;
 __global__ void k_combine_r2(double *R2, const double *__restrict__ S, const double *__restrict__ Xc,
                              int64_t o, int64_t v) {
-  const int64_t vv = v * v, total = o * o * vv;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ij = e / vv, ab = e % vv, i = ij / o, j = ij % o, a = ab / v, b = ab % v;
-    const int64_t ji_ba = (j * o + i) * vv + b * v + a;
-    const int64_t ji_ab = (j * o + i) * vv + ab;
-    const int64_t ij_ba = ij * vv + b * v + a;
-    R2[e] += S[e] + S[ji_ba] - 0.5 * (Xc[e] + Xc[ji_ba]) - (Xc[ji_ab] + Xc[ij_ba]);
+  __shared__ double T[3][kCT][kCT + 1];   // [b - b0][a - a0] of S[j][i], X[j][i], X[i][j]
+  const int64_t vv = v * v;
+  const int tiles = (int)((v + kCT - 1) / kCT);
+  const int64_t a0 = (int64_t)(blockIdx.x / tiles) * kCT, b0 = (int64_t)(blockIdx.x % tiles) * kCT;
+  for (int64_t ij = blockIdx.y; ij < o * o; ij += gridDim.y) {
+    const int64_t i = ij / o, j = ij % o;
+    const double *Sji = S + (j * o + i) * vv, *Xji = Xc + (j * o + i) * vv, *Xij = Xc + ij * vv;
+    __syncthreads();   // the previous pair's reads of T are done
+    for (int e = threadIdx.x; e < kCT * kCT; e += blockDim.x) {
+      const int r = e / kCT, c = e % kCT;              // row b0 + r, column a0 + c
+      const int64_t b = b0 + r, a = a0 + c;
+      const bool in = a < v && b < v;
+      const int64_t off = b * v + a;
+      T[0][r][c] = in ? Sji[off] : 0.0;
+      T[1][r][c] = in ? Xji[off] : 0.0;
+      T[2][r][c] = in ? Xij[off] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kCT * kCT; e += blockDim.x) {
+      const int ra = e / kCT, cb = e % kCT;            // output (a0 + ra, b0 + cb)
+      const int64_t a = a0 + ra, b = b0 + cb;
+      if (a >= v || b >= v) continue;
+      const int64_t idx = ij * vv + a * v + b;
+      R2[idx] += S[idx] + T[0][cb][ra] - 0.5 * (Xc[idx] + T[1][cb][ra]) -
+                 (Xji[a * v + b] + T[2][cb][ra]);
+    }
   }
 }
 
@@ -138,7 +175,8 @@ __global__ void k_energy_partials(const double *__restrict__ Kov, const double *
   double acc = 0.0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ij = e / vv, ab = e % vv, i = ij / o, j = ij % o, a = ab / v, b = ab % v;
+    int64_t i, j, a, b;
+    split4(e, o, v, i, j, a, b);
     const double tau = t2[e] + t1[i * v + a] * t1[j * v + b];
     const double L = 2.0 * Kov[((i * v + a) * o + j) * v + b] - Kov[((i * v + b) * o + j) * v + a];
     acc += L * tau;
@@ -174,16 +212,17 @@ __global__ void k_jacobi(const double *__restrict__ t1, const double *__restrict
       r = R1[e];
       d = eo[i] - ev[a];
     } else {
-      const int64_t f = e - n1, ij = f / vv, ab = f % vv;
-      const int64_t i = ij / o, j = ij % o, a = ab / v, b = ab % v;
+      const int64_t f = e - n1;
+      int64_t i, j, a, b;
+      split4(f, o, v, i, j, a, b);
       told = t2[f];
       r = R2[f];
       d = eo[i] + eo[j] - ev[a] - ev[b];
     }
-    const double xn = told + r / (d - shift);
+    const double u = r / d;
+    const double xn = told + (shift == 0.0 ? u : r / (d - shift));
     x[e] = xn;
     err[e] = xn - told;
-    const double u = r / d;
     acc += u * u;
   }
   const double rr = block_sum(acc, sm);
@@ -198,8 +237,25 @@ __global__ void k_dot_partials(const double *__restrict__ E, int64_t stride, int
   double acc[kMaxDiis];
 #pragma unroll
   for (int i = 0; i < kMaxDiis; ++i) acc[i] = 0.0;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N;
-       e += (int64_t)gridDim.x * blockDim.x) {
+  // four grid strides per pass, so that 4 (m + 1) loads are in flight; each
+  // thread still adds its elements in increasing order
+  const int64_t G = (int64_t)gridDim.x * blockDim.x;
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (; e + 3 * G < N; e += 4 * G) {
+    double x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = enew[e + u * G];
+#pragma unroll
+    for (int i = 0; i < kMaxDiis; ++i)
+      if (i < m) {
+        double y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = E[i * stride + e + u * G];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[i] += x[u] * y[u];
+      }
+  }
+  for (; e < N; e += G) {
     const double x = enew[e];
 #pragma unroll
     for (int i = 0; i < kMaxDiis; ++i)
@@ -281,8 +337,10 @@ __global__ void k_pack_t(const double *__restrict__ t2, int64_t o, int64_t v, T 
   const int64_t vv = v * v, total = o * o * vv, op = o * (o + 1) / 2;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ij = e / vv, cd = e % vv, i = ij / o, j = ij % o, c = cd / v, d = cd % v;
+    int64_t i, j, c, d;
+    split4(e, o, v, i, j, c, d);
     if (i > j) continue;
+    const int64_t ij = i * o + j, cd = c * v + d;
     const double x = t2[e], y = t2[ij * vv + d * v + c];
     Tsa[tri(j, i) * vv + cd] = to_lp<T>(x + y);
     if (i < j) Tsa[(op + stri(j, i)) * vv + cd] = to_lp<T>(x - y);
@@ -300,7 +358,8 @@ __global__ void k_unpack_ladder(const double *__restrict__ SA, int64_t o, int64_
   const int64_t vv = v * v, total = o * o * vv, op = o * (o + 1) / 2;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t ij = e / vv, ab = e % vv, i = ij / o, j = ij % o, a = ab / v, b = ab % v;
+    int64_t i, j, a, b;
+    split4(e, o, v, i, j, a, b);
     const int64_t hi = (a >= b) ? a : b, lo = (a >= b) ? b : a;
     int64_t P;
     if (ca == 0) {
@@ -482,8 +541,11 @@ hipError_t sub_oovv_into_dint(const double *Goovv, int64_t o, int64_t v, double 
 hipError_t combine_r2(double *R2, const double *S, const double *Xc, int64_t o, int64_t v,
                       hipStream_t s) {
   if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(k_combine_r2, dim3(ew_blocks(o * o * v * v)), dim3(kEwThreads), 0, s, R2, S,
-                     Xc, o, v);
+  if (o == 0 || v == 0) return hipSuccess;
+  const int tiles = (int)((v + kCT - 1) / kCT);
+  const unsigned pairs = (unsigned)std::min<int64_t>(o * o, 65535);   // grid rows over (i, j)
+  hipLaunchKernelGGL(k_combine_r2, dim3(tiles * tiles, pairs), dim3(kEwThreads), 0, s, R2, S, Xc,
+                     o, v);
   return hipGetLastError();
 }
 hipError_t energy_partials(const double *Kov, const double *t1, const double *t2, int64_t o,

@@ -327,23 +327,23 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
   const int64_t ov = o * v, oo = o * o, vv = v * v, ovv = o * vv, vvv = vv * v, ooo = oo * o;
   const size_t B8 = sizeof(double);
   // --- T1 dressing of the DF factors
-  LN_TRY(dcopy(L.Btoo, L.Boo, X * oo * B8, s));
   {  // B~_ij = B_ij + sum_b B_ib t_j^b
     GemmDesc d = DESC(o, 1, o, 1, L.Btoo, o, 0, 1, 0, 1.0);
+    d.c_src = L.Boo;
     BATCH_Q(d, X, oo);
     SEG(d, v, 1, 1.0, OPB(OP(L.Bov, v, 0, 1, 0), ov, 0, 0), OP(t1, v, 0, 1, 0));
     LN_TRY(gett(d, s));
   }
-  LN_TRY(dcopy(L.Btvv, L.Bvv, X * vv * B8, s));
   {  // B~_ab = B_ab - sum_k t_k^a B_kb
     GemmDesc d = DESC(v, 1, v, 1, L.Btvv, v, 0, 1, 0, 1.0);
+    d.c_src = L.Bvv;
     BATCH_Q(d, X, vv);
     SEG(d, o, 1, -1.0, OP(t1, 1, 0, v, 0), OPB(OP(L.Bov, 1, 0, v, 0), ov, 0, 0));
     LN_TRY(gett(d, s));
   }
-  LN_TRY(dcopy(L.Btai, L.Bov, X * ov * B8, s));
   {  // B~_ai = B_ai + sum_b B_ab t_i^b - sum_k t_k^a B~_ki, stored [Q][i][a]
     GemmDesc d = DESC(o, 1, v, 1, L.Btai, v, 0, 1, 0, 1.0);
+    d.c_src = L.Bov;
     BATCH_Q(d, X, ov);
     SEG(d, v, 1, 1.0, OP(t1, v, 0, 1, 0), OPB(OP(L.Bvv, v, 0, 1, 0), vv, 0, 0));
     SEG(d, o, 1, -1.0, OPB(OP(L.Btoo, 1, 0, o, 0), oo, 0, 0), OP(t1, 1, 0, v, 0));
@@ -497,9 +497,9 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     LN_TRY(gett(d, s));
   }
   // exchange-type ring: Cint_kiac = (ki|ac)~ - 1/2 sum_ld t_li^ad (kd|lc); X_ijab = sum_kc t_kj^bc Cint_kiac
-  LN_TRY(dcopy(L.Cint, L.Goovv, oo * vv * B8, s));
   {
     GemmDesc d = DESC(ov, v, ov, v, L.Cint, vv, v, ovv, 1, 1.0);
+    d.c_src = L.Goovv;
     SEG(d, ov, v, -0.5, OP(t2, vv, v, ovv, 1), OP(L.Q2, ovv, v, vv, 1));
     d.kind = Kind::Ring;
     LN_TRY(gett(d, s));
