@@ -98,6 +98,7 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--level-shift", type=float, default=0.0)
     ap.add_argument("--diis-start", type=int, default=2)
+    ap.add_argument("--diis-space", type=int, default=16)
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--triples-reps", type=int, default=2,
                     help="timed repetitions of (T) alone on the converged amplitudes")
@@ -151,7 +152,8 @@ def run_single(args, L, torch) -> dict:
 
     def timed(precision: str, steps: int, warmup: int):
         opt = L.make_options(precision=precision, level_shift=args.level_shift,
-                             diis_start=args.diis_start, max_iter=args.max_iter,
+                             diis_start=args.diis_start, diis_space=args.diis_space,
+                             max_iter=args.max_iter,
                              autotune=bool(args.autotune))
         fs = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
         ws.attach([fs], opt)
@@ -182,6 +184,7 @@ def run_single(args, L, torch) -> dict:
            "config": {"workload": args.workload, "nocc": o, "nvir": v, "naux": X, "seed": seed,
                       "precision": args.precision, "conv_tol": args.conv_tol,
                       "level_shift": args.level_shift, "diis_start": args.diis_start,
+                      "diis_space": args.diis_space,
                       "autotune": bool(args.autotune), "ccsd_iterations": fs.n_iter,
                       "status": fs.status},
            "e_ccsd": fs.e_ccsd}
@@ -237,7 +240,7 @@ def run_batch(args, L, torch) -> dict:
     torch.cuda.synchronize()
     ws = L.Workspace("cuda:0")
     kw = dict(conv_tol=args.conv_tol, level_shift=args.level_shift, diis_start=args.diis_start,
-              max_iter=args.max_iter, workspace=ws)
+              diis_space=args.diis_space, max_iter=args.max_iter, workspace=ws)
     for w in range(args.warmup):   # a few fragments: library and kernels loaded
         L.solve_batch(dev[:4], precision=args.precision, batch_slots=args.batch_slots,
                       batch_streams=args.batch_streams, **kw)

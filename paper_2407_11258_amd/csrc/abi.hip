@@ -209,7 +209,7 @@ void lnocc_default_options(lnocc_options_t *opt) {
   opt->guess = LNOCC_GUESS_MP2;
   opt->do_triples = 1;
   opt->max_iter = 100;
-  opt->diis_space = 8;
+  opt->diis_space = 16;
   opt->diis_start = 2;
   opt->graphs = 1;
 }
