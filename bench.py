@@ -97,7 +97,7 @@ def parse_args():
     ap.add_argument("--conv-tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--level-shift", type=float, default=0.0)
-    ap.add_argument("--diis-start", type=int, default=2)
+    ap.add_argument("--diis-start", type=int, default=1)
     ap.add_argument("--diis-space", type=int, default=16)
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--triples-reps", type=int, default=2,

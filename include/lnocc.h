@@ -137,9 +137,10 @@ typedef struct lnocc_options_t {
 } lnocc_options_t;
 
 /* Fills *opt with defaults: FP64, MP2 guess, triples on, max_iter 100,
- * DIIS space 16 from iteration 2, graphs on, default stream, no workspace.
- * (16 stored vectors take 2 x 16 amplitude-sized arrays of the workspace and
- * save about a sixth of the iterations against 8 at 16/160/528.) */
+ * DIIS space 16 from iteration 1, graphs on, default stream, no workspace.
+ * (16 stored vectors take 2 x 16 amplitude-sized arrays of the workspace; with
+ * extrapolation from the first iteration they save about a quarter of the
+ * iterations against 8 vectors from the second at 16/160/528.) */
 void lnocc_default_options(lnocc_options_t *opt);
 
 /* Human-readable name of a status code; never NULL. */
@@ -225,11 +226,12 @@ typedef struct lnocc_contract_t {
   double beta;
   int32_t batch, nb1;
   int32_t precision;             /* lnocc_precision_t of the operands */
-  int32_t tile;                  /* 0: automatic (tuned plan or heuristic); 1..8 force a tile
+  int32_t tile;                  /* 0: automatic (tuned plan or heuristic); 1..9 force a tile
                                     of 128x128, 128x80, 128x64, 32x32, 128x160, 256x128
                                     rows x columns, 7: 128x128 with the products of
-                                    LNOCC_FP32_SPLIT, 8: 160x160 (5..7 for LNOCC_FP32
-                                    operands only, 8 for LNOCC_FP64 only; ignored otherwise) */
+                                    LNOCC_FP32_SPLIT, 8: 160x160, 9: 128x160 with split
+                                    products (5..7 and 9 for LNOCC_FP32 operands only, 8 for
+                                    LNOCC_FP64 only; ignored otherwise) */
 } lnocc_contract_t;
 
 int lnocc_contract(const lnocc_contract_t *desc, void *stream);

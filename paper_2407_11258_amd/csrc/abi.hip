@@ -210,7 +210,7 @@ void lnocc_default_options(lnocc_options_t *opt) {
   opt->do_triples = 1;
   opt->max_iter = 100;
   opt->diis_space = 16;
-  opt->diis_start = 2;
+  opt->diis_start = 1;
   opt->graphs = 1;
 }
 
@@ -655,7 +655,7 @@ int lnocc_contract(const lnocc_contract_t *c, void *stream) {
   if (c->precision < 0 || c->precision > 3) return LNOCC_EINVAL;
   d.prec = (Prec)c->precision;
   d.c_type = 0;
-  if (c->tile < 0 || c->tile > 8) return LNOCC_EINVAL;
+  if (c->tile < 0 || c->tile > 9) return LNOCC_EINVAL;
   d.tile_hint = c->tile;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = gett(d, s);

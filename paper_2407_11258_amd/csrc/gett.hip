@@ -111,16 +111,19 @@ using Tall = Cfg<256, 128, 4, 2>;    // 8 waves, 64 x 64 (4 x 4) each
 // 16 occupied and 160 virtual orbitals) is exactly 256 of these tiles, one per
 // CU, where 128 x 128 tiles leave the second round of workgroups half empty.
 using Sq160 = Cfg<160, 160, 5, 2>;
+// split bf16 products only: 8 waves, 32 x 80 (2 x 5) each; N = 160 (the c index
+// of W) in one tile
+using Wide160S = Cfg<128, 160, 4, 2>;
 
 // Tile ids of the launcher and the autotuner (rows x columns per workgroup).
 // Id 6 is the 128 x 128 tile with FP32 products evaluated as split bf16
 // products (an arithmetic choice for FP32 contractions, same accuracy class).
-constexpr int kTileBM[8] = {128, 128, 128, 32, 128, 256, 128, 160};
-constexpr int kTileBN[8] = {128, 80, 64, 32, 160, 128, 128, 160};
-constexpr int kTileSplit = 6, kTileSq160 = 7;
-// tiles 4..6 serve FP32 operands only, tile 7 FP64 only
+constexpr int kTileBM[9] = {128, 128, 128, 32, 128, 256, 128, 160, 128};
+constexpr int kTileBN[9] = {128, 80, 64, 32, 160, 128, 128, 160, 160};
+constexpr int kTileSplit = 6, kTileSq160 = 7, kTileSplit160 = 8;
+// tiles 4..6 and 8 serve FP32 operands only, tile 7 FP64 only
 inline bool tile_valid(int t, Prec p) {
-  if (t < 0 || t > 7) return false;
+  if (t < 0 || t > 8) return false;
   if (t < 4) return true;
   return t == kTileSq160 ? p == Prec::F64 : p == Prec::F32;
 }
@@ -818,14 +821,14 @@ void install_splitk_scratch(double *p, size_t elems) {
 
 // ---------------------------------------------------------------- autotuning
 // Candidate c = (tile, split rule): tiles 128x128, 128x80, 128x64, 32x32 (and,
-// for FP32 products, 128x160, 256x128 and 128x128 with split bf16 products;
+// for FP32 products, 128x160, 256x128, and 128x128 and 128x160 with split bf16 products;
 // for FP64 products, 160x160);
 // split rules: the cost-model split, no split, twice the cost-model split.  While a
 // candidate is active every launch is timed with events under its shape key;
 // tune_commit() keeps, per key, the fastest candidate's (tile, split count),
 // which later launches of that shape use instead of the heuristic.
 namespace {
-constexpr int kTileCands = 8, kSplitRules = 3;
+constexpr int kTileCands = 9, kSplitRules = 3;
 struct TilePlan { int tile; int nsplit; };
 std::mutex g_plan_mu;
 std::map<std::string, TilePlan> g_plans;
@@ -932,7 +935,8 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   if (d.Mi <= 0 || d.Ni <= 0 || d.nseg <= 0 || d.nseg > kMaxSeg) return hipErrorInvalidValue;
   // k per LDS slice: 32 for the bf16 matrix-core arithmetics, else 16
   auto tile_bk = [&](int t) {
-    return (d.prec == Prec::BF16 || d.prec == Prec::F32S || t == kTileSplit) ? 32 : 16;
+    return (d.prec == Prec::BF16 || d.prec == Prec::F32S || t == kTileSplit ||
+            t == kTileSplit160) ? 32 : 16;
   };
   int slices16 = 0, slices32 = 0;
   for (int s = 0; s < d.nseg; ++s) {
@@ -1093,6 +1097,12 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
       launch<Big>(e, grid, tiles_m, sps, stream);
       break;
     }
+    case kTileSplit160: {
+      GemmDesc e = d;
+      e.prec = Prec::F32S;
+      launch_kind<ModeF32S, Wide160S>(e, grid, tiles_m, sps, stream);
+      break;
+    }
     default: launch<Big>(d, grid, tiles_m, sps, stream); break;
   }
   hipError_t err = hipGetLastError();
@@ -1125,7 +1135,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
                     (long long)g.a.s_ki, (long long)g.b.s_ro, (long long)g.b.s_ri,
                     (long long)g.b.s_ko, (long long)g.b.s_ki, (long long)d.c_mo,
                     (long long)d.c_mi, (long long)d.c_no, (long long)d.c_ni, BMx, BNx,
-                    tile == kTileSplit ? " bf16-split" : "", nsplit);
+                    (tile == kTileSplit || tile == kTileSplit160) ? " bf16-split" : "", nsplit);
       shape = buf;
     }
     g_records.push_back(Record{d.kind, ev[0], ev[1], flops * d.batch, shape});

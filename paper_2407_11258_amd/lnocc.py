@@ -289,7 +289,7 @@ def make_fragment_struct(B, eps_occ, eps_vir, t1, t2, conv_tol: float) -> lnocc_
 
 
 def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int = 100,
-                 diis_space: int = 16, diis_start: int = 2, guess: int = LNOCC_GUESS_MP2,
+                 diis_space: int = 16, diis_start: int = 1, guess: int = LNOCC_GUESS_MP2,
                  ladder_chunk_bytes: int = 0, triples_batch: int = 0,
                  level_shift: float = 0.0, batch_slots: int = 0,
                  batch_streams: int = 0, mlp=None, ladder: str = "auto",

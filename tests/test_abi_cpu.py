@@ -65,7 +65,7 @@ def test_struct_layouts_match_the_header():
 def test_defaults_and_status_strings():
     opt = L.lnocc_default_options()
     assert (opt.precision, opt.guess, opt.do_triples, opt.max_iter, opt.diis_space,
-            opt.diis_start) == (L.LNOCC_FP64, L.LNOCC_GUESS_MP2, 1, 100, 16, 2)
+            opt.diis_start) == (L.LNOCC_FP64, L.LNOCC_GUESS_MP2, 1, 100, 16, 1)
     for st in (0, 1, -1, -2, -3, -4):
         assert L.lnocc_status_string(st).startswith("LNOCC")
     assert "unknown" in L.lnocc_status_string(42)

@@ -157,7 +157,7 @@ def test_contract_low_precision(M, N, K):
     assert err < 2e-6 * np.sqrt(K), err
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_contract_every_tile(tile, precision):
     """Each tile shape of the launcher (forced) on a ragged, segmented, two-index
@@ -185,7 +185,7 @@ def test_contract_every_tile(tile, precision):
 
 
 @pytest.mark.parametrize("shift", [0, 1])
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_contract_column_major_output(tile, precision, shift):
     """Outputs whose row index is the contiguous one (C[e][n][mo][mi]), read and
