@@ -591,6 +591,81 @@ __global__ __launch_bounds__(C::T) void gett_kernel(GemmDesc d, int tiles_m, int
   }
 }
 
+// Matrix-vector products (N = 1, one segment, FP64, no batch):
+// C[m] = scale sum_k A(m, k) B(k) + beta C[m].  A contiguous along m: a block
+// holds kGvM rows (one per lane group) and kGvT / kGvM interleaved k streams per
+// row, summed in LDS in a fixed order.  A contiguous along k: one wave per row,
+// lanes stride over k, summed by a fixed shuffle tree.  Either way every output
+// is one sum in a fixed order, so results do not depend on scheduling.
+constexpr int kGvT = 256;
+__global__ __launch_bounds__(kGvT) void gemv_rows(GemmDesc d, int rows_per_block) {
+  __shared__ double part[kGvT];
+  const GSegment &S = d.seg[0];
+  const int rb = rows_per_block, kg = kGvT / rb;
+  const int r = threadIdx.x % rb, g = threadIdx.x / rb;
+  const int m = blockIdx.x * rb + r;
+  const double *A = (const double *)S.a.p, *B = (const double *)S.b.p;
+  double acc = 0.0;
+  if (m < d.M) {
+    // four independent partial sums (loads of four k in flight), added in order
+    const int64_t ro = two_index_off(d.mdiv, (uint32_t)m, S.a.s_ro, S.a.s_ri);
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = g;
+    for (; k + 3 * kg < S.K; k += 4 * kg) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ku = k + u * kg;
+        a4[u] += A[ro + two_index_off(S.kdiv, (uint32_t)ku, S.a.s_ko, S.a.s_ki)] *
+                 B[two_index_off(S.kdiv, (uint32_t)ku, S.b.s_ko, S.b.s_ki)];
+      }
+    }
+    for (; k < S.K; k += kg)
+      a4[0] += A[ro + two_index_off(S.kdiv, (uint32_t)k, S.a.s_ko, S.a.s_ki)] *
+               B[two_index_off(S.kdiv, (uint32_t)k, S.b.s_ko, S.b.s_ki)];
+    acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (g == 0 && m < d.M) {
+    double t = part[r];
+    for (int q = 1; q < kg; ++q) t += part[q * rb + r];
+    const int64_t off = two_index_off(d.mdiv, (uint32_t)m, d.c_mo, d.c_mi);
+    double *c = (double *)d.c;
+    const double *src = d.c_src ? (const double *)d.c_src : c;
+    c[off] = (d.beta == 0.0) ? S.scale * t : S.scale * t + d.beta * src[off];
+  }
+}
+__global__ __launch_bounds__(kGvT) void gemv_dots(GemmDesc d) {
+  const GSegment &S = d.seg[0];
+  const int lane = threadIdx.x & 63;
+  const int m = blockIdx.x * (kGvT / 64) + threadIdx.x / 64;
+  if (m >= d.M) return;   // whole waves
+  const double *A = (const double *)S.a.p, *B = (const double *)S.b.p;
+  const int64_t ro = two_index_off(d.mdiv, (uint32_t)m, S.a.s_ro, S.a.s_ri);
+  double a4[4] = {0.0, 0.0, 0.0, 0.0};
+  int k = lane;
+  for (; k + 192 < S.K; k += 256) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ku = k + 64 * u;
+      a4[u] += A[ro + two_index_off(S.kdiv, (uint32_t)ku, S.a.s_ko, S.a.s_ki)] *
+               B[two_index_off(S.kdiv, (uint32_t)ku, S.b.s_ko, S.b.s_ki)];
+    }
+  }
+  for (; k < S.K; k += 64)
+    a4[0] += A[ro + two_index_off(S.kdiv, (uint32_t)k, S.a.s_ko, S.a.s_ki)] *
+             B[two_index_off(S.kdiv, (uint32_t)k, S.b.s_ko, S.b.s_ki)];
+  double acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) acc += __shfl_xor(acc, w, 64);
+  if (lane == 0) {
+    const int64_t off = two_index_off(d.mdiv, (uint32_t)m, d.c_mo, d.c_mi);
+    double *c = (double *)d.c;
+    const double *src = d.c_src ? (const double *)d.c_src : c;
+    c[off] = (d.beta == 0.0) ? S.scale * acc : S.scale * acc + d.beta * src[off];
+  }
+}
+
 // C[m, n] = sum_s partial[s][m][n] (+ beta C), summed in split order.
 __device__ inline void splitk_store(const GemmDesc &d, int64_t e, double acc) {
   const int m = (int)(e / d.N), n = (int)(e % d.N);
@@ -962,6 +1037,44 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
                d.c_b0 % 4 == 0 && d.c_b1 % 4 == 0 && d.c_b2 % 4 == 0 && d.c_bid % 4 == 0 &&
                (reinterpret_cast<uintptr_t>(d.c) % (4 * esz)) == 0 &&
                (reinterpret_cast<uintptr_t>(d.c_src) % (4 * esz)) == 0;
+  }
+  // Matrix-vector products take their own kernels (no tiles, no plans).
+  if (d.N == 1 && d.batch == 1 && d.nseg == 1 && d.prec == Prec::F64 && d.c_type == 0 &&
+      d.tile_hint == 0 && d.kind == Kind::Other && d.seg[0].K > 0) {
+    if (!descriptor_ok(d, 1)) {
+      note_error("matrix-vector product M=%d(%d) K=%d(%d) leaves its buffers; not launched", d.M,
+                 d.Mi, d.seg[0].K, d.seg[0].Ki);
+      return hipErrorIllegalAddress;
+    }
+    if (g_dry || g_cand == kProbeCand) return hipSuccess;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (g_profile) {
+      if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+        return hipErrorOutOfMemory;
+      (void)hipEventRecord(ev[0], stream);
+    }
+    if (d.seg[0].a_kfast) {
+      const int per = kGvT / 64;
+      hipLaunchKernelGGL(gemv_dots, dim3((unsigned)((d.M + per - 1) / per)), dim3(kGvT), 0, stream,
+                         d);
+    } else {
+      const int rb = d.M >= 32768 ? 64 : (d.M >= 4096 ? 32 : 16);
+      hipLaunchKernelGGL(gemv_rows, dim3((unsigned)((d.M + rb - 1) / rb)), dim3(kGvT), 0, stream,
+                         d, rb);
+    }
+    hipError_t err = hipGetLastError();
+    if (g_profile) {
+      (void)hipEventRecord(ev[1], stream);
+      std::string shape;
+      if (std::getenv("LNOCC_PROFILE_DUMP")) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "k%d p%d M%d/%d N1 K%d/%d matrix-vector", (int)d.kind,
+                      (int)d.prec, d.M, d.Mi, d.seg[0].K, d.seg[0].Ki);
+        shape = buf;
+      }
+      g_records.push_back(Record{d.kind, ev[0], ev[1], 2.0 * d.M * (double)d.seg[0].K, shape});
+    }
+    return err;
   }
   // Tile shape: the 32 x 32 single-wave tile for thin outputs; otherwise 128
   // rows by the N width (128, 80 or 64) that pads N least.

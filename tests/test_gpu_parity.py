@@ -215,6 +215,45 @@ def test_contract_column_major_output(tile, precision, shift):
     assert err < (1e-14 if precision == 0 else 2e-6 * np.sqrt(K)), err
 
 
+@pytest.mark.parametrize("M,Mi,K,kfast", [(20, 1, 7, False), (5000, 100, 333, False),
+                                          (40000, 1, 64, False), (37, 1, 1000, True),
+                                          (3000, 30, 2560, True)])
+def test_contract_matrix_vector(M, Mi, K, kfast):
+    """N = 1 (FP64, one segment) runs the matrix-vector kernels: rows contiguous
+    (block of rows x interleaved k streams) or k contiguous (one wave per row),
+    with a two-index row mode and beta != 0."""
+    say(f"contract matrix-vector M={M} Mi={Mi} K={K} kfast={kfast}")
+    rng = np.random.default_rng(M + K)
+    A = rng.standard_normal((M, K))
+    x = rng.standard_normal(K)
+    C0 = rng.standard_normal(M)
+    ref = 0.5 * (A @ x) - 1.5 * C0
+    Mo = M // Mi
+    if kfast:   # A[m][k], m = (mo, mi)
+        a_t = dev(A)
+        op = _operand(a_t, Mi * K, K, 1, 0)
+    else:       # stored as A^T[k][m]
+        a_t = dev(A.T.copy())
+        op = _operand(a_t, Mi, 1, M, 0)
+    xb = dev(x)
+    src = dev(C0)
+    c = torch.full((M,), float("nan"), dtype=torch.float64, device=DEV)
+    d = L.lnocc_contract_t()
+    d.M, d.Mi, d.N, d.Ni = M, Mi, 1, 1
+    d.nseg = 1
+    d.K[0], d.Ki[0], d.scale[0] = K, 1, 0.5
+    d.a[0], d.b[0] = op, _operand(xb, 0, 0, 1, 0)
+    d.c = c.data_ptr()
+    d.c_mo, d.c_mi, d.c_no, d.c_ni = Mi, 1, 0, 0
+    d.beta, d.batch, d.nb1, d.precision = -1.5, 1, 1, 0
+    # the beta input comes from C itself through the ABI: copy it in first
+    c.copy_(src)
+    st = L.lnocc_contract(d, torch.cuda.current_stream().cuda_stream)
+    _KEEP.clear()
+    assert st == L.LNOCC_OK, L.lnocc_last_error()
+    np.testing.assert_allclose(host(c), ref, rtol=0, atol=1e-12 * np.sqrt(K) * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
 def test_contract_split_products_exact(tile):
     """Split bf16 products (LNOCC_FP32_SPLIT) on operands x = s (1 + c 2^-9),
