@@ -163,8 +163,8 @@ def test_contract_every_tile(tile, precision):
     """Each tile shape of the launcher (forced) on a ragged, segmented, two-index
     product, FP64 and FP32 operands, both operands once contiguous along k and
     once along their row index (the 128x160 and 256x128 tiles and the split bf16
-    products of tile 7 are for FP32 operands only, the 160x160 tile for FP64 only;
-    otherwise the automatic choice runs)."""
+    products of tiles 7 and 9 are for FP32 operands only, the 160x160 tile for FP64
+    only; otherwise the automatic choice runs)."""
     say(f"contract tile {tile} precision {precision}")
     rng = np.random.default_rng(100 + tile)
     M, N, K1, K2 = 301, 263, 45, 19
