@@ -451,8 +451,17 @@ __device__ inline double4_t regroup_rows_f64(const double4_t &a, int lane) {
   return out;
 }
 
+// Workgroups per CU the register allocation must allow: two for the 8-wave FP64
+// tiles (at most 128 VGPRs: a few row offsets spill), so that one workgroup's
+// barrier and LDS stage overlap the other's matrix ops.  Measured: the FP64 matrix
+// pipe was busy 55 % of the time with one such workgroup per CU; the K = naux
+// products went 42 -> 48 TFLOP/s.
+template <class M, class C>
+constexpr int kMinBlocks = (std::is_same<M, ModeF64>::value && C::T == 512) ? 2 : 1;
+
 template <class M, class C, int KIND>
-__global__ __launch_bounds__(C::T) void gett_kernel(GemmDesc d, int tiles_m, int slices_per_split) {
+__global__ __launch_bounds__(C::T) __attribute__((amdgpu_waves_per_eu(kMinBlocks<M, C> * C::T / 256)))
+void gett_kernel(GemmDesc d, int tiles_m, int slices_per_split) {
   using E = typename M::T;
   constexpr int BK = M::BK;
   // [k][row] tiles pad the row (conflict-free 16-lane reads); [row][k] tiles pad
