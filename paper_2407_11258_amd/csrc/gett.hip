@@ -1,14 +1,18 @@
-// Generic batched contraction on gfx950 matrix cores (FP64 path).
+// Generic batched contraction on gfx950 matrix cores (FP64, FP32, BF16 and
+// split-bf16 FP32 products), plus matrix-vector kernels for N = 1.
 //
 // Tiles: 128 x 128 outputs per workgroup of 8 wave64s (4 x 2, 32 x 64 per wave
-// = 2 x 4 blocks of v_mfma_f64_16x16x4f64; two waves share each SIMD, which
-// the FP64 matrix pipe needs to approach its rate), or 32 x 32 per single-wave
-// workgroup for thin outputs.  K is staged through double-buffered LDS in
-// slices of 16, k-major ([k][row]) so that the 16 lanes of one MFMA operand row
-// read 128 contiguous bytes; the next slice is fetched into registers while the
-// current one is multiplied (one barrier per slice).  Thin outputs with long K
-// are split over K across workgroups; the partial tiles are summed in a fixed
-// order by a second kernel, so results do not depend on scheduling.
+// = 2 x 4 blocks of 16 x 16 matrix ops; the FP64 one is register-limited so that
+// two workgroups share a CU), 128 x 80 and 128 x 64 (4 waves), 160 x 160 (FP64,
+// 10 waves: an ov x ov output is one round of 256 tiles), 32 x 32 single-wave
+// tiles for thin outputs, and FP32-only 128 x 160 / 256 x 128 and split-bf16
+// tiles.  K is staged through double-buffered LDS in slices (16 for FP64/FP32,
+// k-major [k][row] so that the 16 lanes of one operand row read 128 contiguous
+// bytes; 32 for the bf16 modes, [row][k]); the next slice is fetched into
+// registers while the current one is multiplied (one barrier per slice).  Thin
+// outputs with long K are split over K across workgroups; the partial tiles are
+// summed in a fixed order by a second kernel, so results do not depend on
+// scheduling.
 //
 // MFMA 16x16x4 (f64) operand layout, lane l of a wave64:
 //   A: A[l % 16][l / 16]      B: B[l / 16][l % 16]
