@@ -83,6 +83,10 @@ def test_argument_errors_need_no_device():
     bad = L.lnocc_default_options()
     bad.diis_space = 0
     assert L.lnocc_workspace_bytes([f], bad)[0] == L.LNOCC_EINVAL
+    bad.diis_space = 17
+    assert L.lnocc_workspace_bytes([f], bad)[0] == L.LNOCC_EINVAL
+    bad.diis_space = 16
+    assert L.lnocc_workspace_bytes([f], bad)[0] == L.LNOCC_OK
     bad = L.lnocc_default_options()
     bad.precision = 7
     assert L.lnocc_workspace_bytes([f], bad)[0] == L.LNOCC_EINVAL
