@@ -2,9 +2,11 @@
 
 Runs only the FP64 oracle (oracle/) on the seeded synthetic inputs (synth/)
 and stores energies, iteration counts, amplitude norms and a seeded sample of
-amplitude elements as JSON next to this script.  Usage:
+amplitude elements as JSON next to this script.  A name with the suffix
+":mp2" stores only the MP2 energy and the MP1 amplitudes (sample and norm), which
+the oracle computes in seconds even at the large workload's full size.  Usage:
 
-    python tests/golden/make_golden.py single_small single_realistic
+    python tests/golden/make_golden.py single_small single_realistic large:mp2
 """
 from __future__ import annotations
 
@@ -50,10 +52,36 @@ def golden(name: str) -> dict:
     }
 
 
+def golden_mp2(name: str) -> dict:
+    """MP1 amplitudes (Eq. 21 with every occupied orbital) and the MP2 energy
+    (Eq. 7 at T1 = 0) of one workload."""
+    o, v, X, seed = CONFIG_SHAPES[name]
+    f = make_fragment(o, v, X, seed)
+    t0 = time.time()
+    t2, e_mp2 = occ.mp2(f.B, f.eps_occ, f.eps_vir)
+    t_mp2 = time.time() - t0
+    rng = np.random.default_rng(12345)
+    idx2 = np.stack([rng.integers(0, o, NSAMPLE), rng.integers(0, o, NSAMPLE),
+                     rng.integers(0, v, NSAMPLE), rng.integers(0, v, NSAMPLE)], axis=1)
+    return {
+        "workload": name, "nocc": o, "nvir": v, "naux": X, "seed": seed,
+        "input_sha256": f.sha256(), "e_mp2": e_mp2,
+        "t2_norm": float(np.linalg.norm(t2)),
+        "t2_index": idx2.tolist(), "t2_value": [float(t2[tuple(i)]) for i in idx2],
+        "oracle_seconds": {"mp2": t_mp2},
+    }
+
+
 if __name__ == "__main__":
-    for name in sys.argv[1:] or ["single_small"]:
-        g = golden(name)
-        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}.json")
+    for arg in sys.argv[1:] or ["single_small"]:
+        name, _, part = arg.partition(":")
+        here = os.path.dirname(os.path.abspath(__file__))
+        if part == "mp2":
+            g = golden_mp2(name)
+            path = os.path.join(here, f"{name}_mp2.json")
+        else:
+            g = golden(name)
+            path = os.path.join(here, f"{name}.json")
         with open(path, "w") as fh:
             json.dump(g, fh, indent=1)
-        print(name, g["e_mp2"], g["e_ccsd"], g["e_t"], g["n_iter"], g["oracle_seconds"], flush=True)
+        print(arg, {k: g[k] for k in ("e_mp2", "oracle_seconds")}, flush=True)

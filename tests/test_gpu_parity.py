@@ -443,6 +443,50 @@ def test_realistic_fragment_against_stored_oracle(precision, tol_e):
     assert abs(np.linalg.norm(T2) - g["t2_norm"]) < 1e-7 * g["t2_norm"] * (1 if precision == "fp64" else 10)
 
 
+def test_large_fragment_at_full_size():
+    """The large workload (nocc=32, nvir=400, naux=1300: the ladder is formed on
+    the fly, no v^4 storage) at full size.  The MP2 energy and a seeded sample of
+    the MP1 amplitudes against oracle values stored by tests/golden/make_golden.py
+    (large:mp2); the energy of that start (T1 = 0, so equal to E_MP2); and one full
+    residual evaluation at those amplitudes, which must be finite and keep the
+    pair symmetry R_ij^ab = R_ji^ba of the closed-shell equations."""
+    g = _golden("large_mp2")
+    say("large fragment at full size: MP2 start and one residual")
+    f = make_fragment(g["nocc"], g["nvir"], g["naux"], g["seed"])
+    assert f.sha256() == g["input_sha256"]
+    o, v = f.nocc, f.nvir
+    B, eo, ev = _fragment_on_device(f)
+    del f
+    t1 = torch.empty((o, v), dtype=torch.float64, device=DEV)
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=DEV)
+    st, fs = _call(L.lnocc_fragment_ccsd, None, B, eo, ev, t1, t2, max_iter=0,
+                   do_triples=False)
+    say(f"  dE_mp2={fs.e_mp2 - g['e_mp2']:.2e} ladder on the fly")
+    assert st == L.LNOCC_OK
+    assert abs(fs.e_mp2 - g["e_mp2"]) < 1e-10
+    assert abs(fs.e_ccsd - fs.e_mp2) < 1e-12
+    idx = np.array(g["t2_index"])
+    got = host(t2[idx[:, 0], idx[:, 1], idx[:, 2], idx[:, 3]])
+    np.testing.assert_allclose(got, g["t2_value"], rtol=0, atol=1e-13)
+    assert abs(float(torch.linalg.vector_norm(t2)) - g["t2_norm"]) < 1e-12 * g["t2_norm"]
+    assert float(t1.abs().max()) == 0.0
+    r1 = torch.empty((o, v), dtype=torch.float64, device=DEV)
+    r2 = torch.empty((o, o, v, v), dtype=torch.float64, device=DEV)
+    opt = L.make_options()
+    fr = L.make_fragment_struct(B, eo, ev, t1, t2, 1e-8)
+    ws = L.Workspace(DEV)
+    ws.attach([fr], opt)
+    st = L.lnocc_ccsd_residuals(fr, opt, r1.data_ptr(), r2.data_ptr())
+    assert st == L.LNOCC_OK, L.lnocc_last_error()
+    assert bool(torch.isfinite(r1).all()) and bool(torch.isfinite(r2).all())
+    scale = float(r2.abs().max())
+    asym = float((r2 - r2.permute(1, 0, 3, 2)).abs().max())
+    say(f"  |R2| max {scale:.3e}, pair asymmetry {asym:.1e}")
+    assert scale > 0.0 and asym <= 1e-12 * scale
+    del r2, t2, B, ws
+    torch.cuda.empty_cache()
+
+
 def test_solve_is_bitwise_reproducible():
     say("determinism o=4 v=20")
     f = make_fragment(4, 20, 72, 0)
