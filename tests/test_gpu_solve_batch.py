@@ -82,3 +82,40 @@ def test_batch_reports_per_fragment_errors():
     assert [r.status for r in res] == [L.LNOCC_OK, L.LNOCC_EINVAL, L.LNOCC_OK]
     one = L.solve(*dev[2], conv_tol=1e-8, do_triples=False)
     assert res[2].e_ccsd == one.e_ccsd and res[2].e_t == 0.0
+
+
+def test_batch_workload_start_at_full_size():
+    """The 64 fragments of the batched workload (nocc 6..24, nvir 60..220,
+    naux = 3 (nocc + nvir)) through lnocc_batch_solve in the launch configuration
+    the benchmark times (FP32 mode, 4 slots on 4 streams, graphs) with
+    max_iter = 0: every fragment's MP2 energy (Eq. 7 at the MP1 amplitudes of
+    Eq. 21), the energy of that start, the MP1 amplitude norm and 8 sampled
+    amplitudes against oracle values stored by tests/golden/make_golden.py
+    (batch:mp2)."""
+    import json
+    import pathlib
+    path = pathlib.Path(__file__).resolve().parent / "golden" / "batch_mp2.json"
+    if not path.exists():
+        pytest.skip(f"{path.name} not generated")
+    frs = json.loads(path.read_text())["fragments"]
+    say(f"batch workload at full size: {len(frs)} fragments, MP2 start")
+    dev = []
+    for x in frs:
+        f = make_fragment(*x["shape"])
+        assert f.sha256() == x["input_sha256"]
+        dev.append(_on_device(f))
+    res = L.solve_batch(dev, precision="fp32", batch_slots=4, batch_streams=4, max_iter=0,
+                        do_triples=False)
+    worst = 0.0
+    for k, (r, x) in enumerate(zip(res, frs)):
+        assert r.status == L.LNOCC_OK, (k, x["shape"], L.lnocc_last_error())
+        worst = max(worst, abs(r.e_mp2 - x["e_mp2"]))
+        assert abs(r.e_mp2 - x["e_mp2"]) < 1e-10, (k, x["shape"])
+        assert abs(r.e_ccsd - r.e_mp2) < 1e-12
+        idx = np.array(x["t2_index"])
+        got = r.t2[idx[:, 0], idx[:, 1], idx[:, 2], idx[:, 3]].cpu().numpy()
+        np.testing.assert_allclose(got, x["t2_value"], rtol=0, atol=1e-13)
+        assert abs(float(torch.linalg.vector_norm(r.t2)) - x["t2_norm"]) < 1e-12 * x["t2_norm"]
+    say(f"  worst |dE_mp2| {worst:.1e}")
+    del dev, res
+    torch.cuda.empty_cache()
