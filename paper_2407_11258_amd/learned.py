@@ -3,16 +3,20 @@ bookkeeping only: features, network, loss, gradients and Adam run in the
 library's kernels through the lnocc_mlp_* calls).
 
     python -m paper_2407_11258_amd.learned --train 64 --eval 16 --out model.pt
+    python -m paper_2407_11258_amd.learned --load model.pt --eval 512
 
 solves `train` synthetic fragments of the realistic shape (nocc=16, nvir=160,
 naux=528; seeds 100000 + k), samples amplitudes of each converged T2 as
-(features, t_CCSD - t_MP1) pairs, trains the network, then solves `eval`
-held-out fragments (seeds 200000 + k) from the MP2 start and from the learned
-start and prints one JSON line: iterations, times and energy differences.
+(features, t_CCSD - t_MP1) pairs, trains the network (or loads one with
+--load), then solves `eval` held-out fragments (seeds 200000 + k) from the MP2
+start and from the learned start and prints one JSON line: iterations, times
+and energy differences.  Fragments are generated on the host in a thread pool
+ahead of the device work.
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import sys
 import time
@@ -154,37 +158,60 @@ def main() -> int:
     ap.add_argument("--conv-tol", type=float, default=1e-7)
     ap.add_argument("--shape", default="16,160,528")
     ap.add_argument("--out", default="")
+    ap.add_argument("--load", default="", help="model file written by --out: skips the "
+                    "training data and the training")
     args = ap.parse_args()
     torch = _torch()
     from synth import make_fragment
     o, v, X_ = (int(x) for x in args.shape.split(","))
     log = lambda m: print(f"[learned] {m}", file=sys.stderr, flush=True)   # noqa: E731
+    # host-side fragment generation runs ahead of the device in a thread pool
+    pool = cf.ThreadPoolExecutor(max_workers=8)
 
-    t0 = time.perf_counter()
-    X, Y = [], []
-    for c0 in range(0, args.train, 16):   # 16 fragments resident at a time
-        frags = [fragment_tensors(make_fragment(o, v, X_, 100000 + k))
-                 for k in range(c0, min(args.train, c0 + 16))]
-        x, y, _ = collect_samples(frags, args.per_fragment, seed=300000 + c0)
-        X.append(x)
-        Y.append(y)
-        log(f"training data: {min(args.train, c0 + 16)}/{args.train} fragments")
-        del frags
-    X, Y = torch.cat(X), torch.cat(Y)
-    t_data = time.perf_counter() - t0
+    def ahead(seeds):
+        return [pool.submit(make_fragment, o, v, X_, s) for s in seeds]
+
     model = LearnedGuess("cuda")
-    model.init(X, Y, seed=0)
-    t0 = time.perf_counter()
-    losses = model.train(X, Y, args.steps, batch=args.batch, lr=args.lr, lr_final=args.lr_final,
-                         log_every=500)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
+    t_data = t_train = 0.0
+    losses = []
+    nsamples = 0
+    if args.load:
+        model.load(args.load)
+    else:
+        t0 = time.perf_counter()
+        X, Y = [], []
+        chunks = list(range(0, args.train, 16))   # 16 fragments resident at a time
+        nxt = ahead(100000 + k for k in range(0, min(args.train, 16)))
+        for c0 in chunks:
+            cur = nxt
+            c1 = c0 + 16
+            nxt = ahead(100000 + k for k in range(c1, min(args.train, c1 + 16)))
+            frags = [fragment_tensors(f.result()) for f in cur]
+            x, y, _ = collect_samples(frags, args.per_fragment, seed=300000 + c0)
+            X.append(x)
+            Y.append(y)
+            log(f"training data: {min(args.train, c1)}/{args.train} fragments")
+            del frags
+        X, Y = torch.cat(X), torch.cat(Y)
+        nsamples = int(Y.numel())
+        t_data = time.perf_counter() - t0
+        model.init(X, Y, seed=0)
+        t0 = time.perf_counter()
+        losses = model.train(X, Y, args.steps, batch=args.batch, lr=args.lr,
+                             lr_final=args.lr_final, log_every=500)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        del X, Y
     if args.out:
         model.save(args.out)
 
     rows = []
+    window = 8   # held-out fragments generated ahead (about 130 MB of host memory each)
+    held = ahead(200000 + k for k in range(min(window, args.eval)))
     for k in range(args.eval):
-        d = fragment_tensors(make_fragment(o, v, X_, 200000 + k))
+        d = fragment_tensors(held.pop(0).result())
+        if k + window < args.eval:
+            held += ahead([200000 + k + window])
         out = {}
         for name, kw in (("mp2", {}), ("mlp", {"guess": L.LNOCC_GUESS_MLP, "mlp": model.blob})):
             torch.cuda.synchronize()
@@ -198,16 +225,19 @@ def main() -> int:
                      "d_e_ccsd": b.e_ccsd - a.e_ccsd, "status": [a.status, b.status]})
         log(f"held-out {k}: iterations {a.n_iter} (MP2 start) vs {b.n_iter} (learned), "
             f"dE {b.e_ccsd - a.e_ccsd:.1e}")
+    pool.shutdown()
+    mean = lambda key: float(np.mean([r[key] for r in rows])) if rows else None   # noqa: E731
     summary = {
-        "shape": [o, v, X_], "conv_tol": args.conv_tol, "train_fragments": args.train, "eval_fragments": args.eval,
-        "samples": int(Y.numel()), "steps": args.steps, "batch": args.batch,
+        "shape": [o, v, X_], "conv_tol": args.conv_tol,
+        "train_fragments": 0 if args.load else args.train, "model": args.load or None,
+        "eval_fragments": args.eval,
+        "samples": nsamples, "steps": 0 if args.load else args.steps, "batch": args.batch,
         "data_seconds": t_data, "train_seconds": t_train,
-        "loss_first": losses[0], "loss_last": float(np.mean(losses[-50:])),
-        "mean_iters_mp2": float(np.mean([r["iters_mp2"] for r in rows])),
-        "mean_iters_mlp": float(np.mean([r["iters_mlp"] for r in rows])),
-        "mean_seconds_mp2": float(np.mean([r["s_mp2"] for r in rows])),
-        "mean_seconds_mlp": float(np.mean([r["s_mlp"] for r in rows])),
-        "max_abs_d_e_ccsd": float(max(abs(r["d_e_ccsd"]) for r in rows)),
+        "loss_first": losses[0] if losses else None,
+        "loss_last": float(np.mean(losses[-50:])) if losses else None,
+        "mean_iters_mp2": mean("iters_mp2"), "mean_iters_mlp": mean("iters_mlp"),
+        "mean_seconds_mp2": mean("s_mp2"), "mean_seconds_mlp": mean("s_mlp"),
+        "max_abs_d_e_ccsd": float(max(abs(r["d_e_ccsd"]) for r in rows)) if rows else None,
         "fallbacks": int(sum(r["guess_used"] != L.LNOCC_GUESS_MLP for r in rows)),
         "rows": rows,
     }
