@@ -10,7 +10,14 @@ namespace lnocc {
 // FP64 energy and norm) is independent of timing and bitwise reproducible.
 constexpr int kRedBlocks = 512;
 constexpr int kRedThreads = 256;
-constexpr int kTriplesBlocks = 128;   // (T) energy blocks per triple (grid-stride over cube tiles)
+constexpr int kTriplesBlocks = 128;   // (T) energy blocks per triple (grid-stride over cube tiles),
+constexpr int kTriplesGrid = 4096;    // raised so that one launch has at least this many blocks
+// Blocks per triple of a (T) energy launch over nb triples (before the cap at the
+// number of cube-tile orbits; the partial-sum buffer holds nb times this many).
+inline int64_t triples_blocks_per_entry(int64_t nb) {
+  const int64_t fill = (kTriplesGrid + nb - 1) / nb;
+  return fill > kTriplesBlocks ? fill : kTriplesBlocks;
+}
 
 hipError_t split_B(const double *B, int64_t X, int64_t o, int64_t v,
                    double *Boo, double *Bov, double *Bvv, hipStream_t s);

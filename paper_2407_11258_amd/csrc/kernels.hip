@@ -647,7 +647,9 @@ hipError_t triples_energy(const void *W, int wtype, const int *table, int nb, co
                           int64_t v, double *partials, int64_t *nparts, hipStream_t s) {
   const int tpd = (int)((v + TT - 1) / TT);
   const int64_t orbits = (int64_t)tpd * (tpd + 1) * (tpd + 2) / 6;
-  const int per_entry = orbits < kTriplesBlocks ? (int)orbits : kTriplesBlocks;
+  // small batches (large v) get more blocks per triple, so the launch fills the chip
+  const int64_t want = triples_blocks_per_entry(nb);
+  const int per_entry = (int)(orbits < want ? orbits : want);
   *nparts = (int64_t)per_entry * nb;
   if (dry_run()) return hipSuccess;
   if (wtype == 1)

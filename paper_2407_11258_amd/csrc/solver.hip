@@ -177,7 +177,7 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.Gt = A.d(ov * vv); L.Jt = A.d(oo * ov);
   L.W = A.d(nb * vvv);
   L.t2_lp = (L.lp != Prec::F64) ? A.d(oovv) : nullptr;
-  L.tpart = A.d(nb * kTriplesBlocks);
+  L.tpart = A.d(nb * triples_blocks_per_entry(nb));
   L.table = A.i(3 * std::max<int64_t>(nt, 1));
   const size_t t_end = A.off;
   L.bytes = std::max(ccsd_end, t_end) + 256;
