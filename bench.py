@@ -8,14 +8,26 @@ naux=528, seed 1), in the mixed mode (ladder and (T) products in FP32 on the
 matrix cores, everything else FP64) and, for comparison, in plain FP64.
 Inputs are resident in HBM before the timed region.
 
---workload batch instead solves the 64 uneven fragments of the batch workload
-with lnocc_batch_solve (one step = the whole batch) and, with --compare-fp64,
-the same 64 fragments one at a time in FP64.
+The timed steps run the library's default path (the residual evaluation of
+each iteration replayed from a captured HIP graph, no per-launch events).  One
+further solve, outside the timed region, runs with per-launch HIP events on
+the solve's stream; it gives the per-class kernel times and the roofline
+position of the dominant contraction kernel.
+
+Two further legs are added to the same JSON line (each can be switched off):
+  large_triples  (T) at the large fragment's full size (nocc=32, nvir=400,
+                 naux=1300, seed 4) on the MP1 amplitudes, mixed and FP64, with
+                 the algorithmic rate 2 o^3 v^4 + 2 o^4 v^3 over the wall time;
+  batch          the 64 uneven fragments of the batched workload through
+                 lnocc_batch_solve in the mixed mode against the same fragments
+                 solved one at a time in FP64, with parity against the stored
+                 oracle values of a subset.
+
+--workload batch times the batched workload alone (one step = the whole batch).
 
 Prints one JSON line with solves/s, the (T) contraction rate, the roofline
-position of the dominant contraction kernel (timed with HIP events on its own
-stream inside the timed region) and the FP64 CPU oracle timed on a bounded
-sample on the host cores.
+position of the dominant contraction kernel and the FP64 CPU oracle timed on a
+bounded sample on the host cores.
 """
 from __future__ import annotations
 
@@ -82,8 +94,8 @@ def cpu_baseline(frag, n_iter: int, budget_triples: int = 4) -> dict:
 def parse_args():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="single_realistic")
     ap.add_argument("--precision", default="fp32", choices=sorted(PEAKS_TFLOPS))
     ap.add_argument("--compare-fp64", type=int, default=1,
@@ -102,6 +114,10 @@ def parse_args():
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--triples-reps", type=int, default=2,
                     help="timed repetitions of (T) alone on the converged amplitudes")
+    ap.add_argument("--large-triples", type=int, default=1,
+                    help="add the large-fragment (T) leg (mixed and FP64, about 90 s)")
+    ap.add_argument("--batch-leg", type=int, default=1,
+                    help="add the batched-workload leg (mixed batch vs sequential FP64)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a plain copy of known size "
                          "that scales hardware byte counters)")
@@ -168,15 +184,20 @@ def run_single(args, L, torch) -> dict:
             log(f"{precision} warmup {w + 1}/{warmup}: {fs.n_iter} iterations, "
                 f"E_CCSD={fs.e_ccsd:.10f}")
         torch.cuda.synchronize()
-        L.lnocc_profile_enable(True)
         t0 = time.perf_counter()
         for k in range(steps):
             step()
             log(f"{precision} step {k + 1}/{steps} done")
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
+        # per-class launch times: one more solve with HIP events around every
+        # contraction (this switches the graph replay off), outside the timed steps
+        L.lnocc_profile_enable(True)
+        step()
+        torch.cuda.synchronize()
         L.lnocc_profile_enable(False)
         prof = L.lnocc_profile_collect()
+        log(f"{precision} profiled solve done")
         return fs, opt, elapsed, prof
 
     fs, opt, elapsed, prof = timed(args.precision, args.steps, args.warmup)
@@ -225,13 +246,75 @@ def run_single(args, L, torch) -> dict:
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         res["cpu_baseline"] = cpu_baseline(frag, fs.n_iter)
+    del ws
+    torch.cuda.empty_cache()
+    if args.large_triples:
+        res["large_triples"] = run_large_triples(args, L, torch)
+        torch.cuda.empty_cache()
+    if args.batch_leg:
+        res["batch"] = run_batch(args, L, torch, leg=True)
+        torch.cuda.empty_cache()
     return res
 
 
-def run_batch(args, L, torch) -> dict:
+def run_large_triples(args, L, torch) -> dict:
+    """(T) at the large fragment's full size on its MP1 amplitudes (T1 = 0), mixed
+    and FP64.  CCSD itself does not converge on this synthetic input, so the
+    amplitudes are the starting ones; the cost of (T) does not depend on them."""
+    from synth import CONFIG_SHAPES, make_fragment
+    o, v, X, seed = CONFIG_SHAPES["large"]
+    log(f"large (T) leg: nocc={o} nvir={v} naux={X} seed={seed}")
+    frag = make_fragment(o, v, X, seed)
+    dev = torch.device("cuda:0")
+    B = torch.tensor(frag.B, device=dev)
+    eo = torch.tensor(frag.eps_occ, device=dev)
+    ev = torch.tensor(frag.eps_vir, device=dev)
+    t1 = torch.empty((o, v), dtype=torch.float64, device=dev)
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=dev)
+    ws = L.Workspace(dev)
+    opt0 = L.make_options(precision="fp64", do_triples=False, max_iter=0)
+    f0 = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
+    ws.attach([f0], opt0)
+    st = L.lnocc_fragment_ccsd(f0, opt0)   # MP1 amplitudes and E_MP2
+    if st < 0:
+        raise RuntimeError(f"{L.lnocc_status_string(st)}: {L.lnocc_last_error()}")
+    del ws
+    torch.cuda.empty_cache()
+    f_t = 2.0 * o ** 3 * v ** 4 + 2.0 * o ** 4 * v ** 3
+    out = {"workload": "large", "nocc": o, "nvir": v, "naux": X, "seed": seed,
+           "amplitudes": "MP1 (T1 = 0)", "e_mp2": f0.e_mp2, "flops": f_t}
+    for prec in ("fp32", "fp64"):
+        ws = L.Workspace(dev)
+        opt = L.make_options(precision=prec, autotune=bool(args.autotune))
+        ft = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
+        ws.attach([ft], opt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = L.lnocc_fragment_triples(ft, opt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        if st < 0:
+            raise RuntimeError(f"{L.lnocc_status_string(st)}: {L.lnocc_last_error()}")
+        rate = f_t / el / 1e12
+        out[prec] = {"seconds": el, "tflops": rate, "peak": PEAKS_TFLOPS[prec],
+                     "frac": rate / PEAKS_TFLOPS[prec], "e_t": ft.e_t}
+        log(f"large (T) {prec}: {el:.1f} s, {rate:.1f} TFLOP/s, E_(T)={ft.e_t:.12f}")
+        del ws
+        torch.cuda.empty_cache()
+    out["d_e_t_mixed_vs_fp64"] = out["fp32"]["e_t"] - out["fp64"]["e_t"]
+    return out
+
+
+def run_batch(args, L, torch, leg: bool = False) -> dict:
+    """The 64-fragment batched workload: mixed-precision lnocc_batch_solve against
+    the same fragments solved one at a time in FP64.  Contraction plans come from
+    the built-in heuristics (the autotuner is not run on the 64 distinct shapes)."""
     from synth import batch_shapes, make_fragment
     shapes = batch_shapes()
     log(f"batch workload: {len(shapes)} fragments")
+    precision = "fp32" if leg else args.precision
+    steps = 1 if leg else args.steps
+    warmup = 1 if leg else args.warmup
     dev = []
     for s in shapes:
         f = make_fragment(*s)
@@ -241,30 +324,41 @@ def run_batch(args, L, torch) -> dict:
     ws = L.Workspace("cuda:0")
     kw = dict(conv_tol=args.conv_tol, level_shift=args.level_shift, diis_start=args.diis_start,
               diis_space=args.diis_space, max_iter=args.max_iter, workspace=ws)
-    for w in range(args.warmup):   # a few fragments: library and kernels loaded
-        L.solve_batch(dev[:4], precision=args.precision, batch_slots=args.batch_slots,
+    for w in range(warmup):   # a few fragments: library and kernels loaded
+        L.solve_batch(dev[:4], precision=precision, batch_slots=args.batch_slots,
                       batch_streams=args.batch_streams, **kw)
-        log(f"warmup {w + 1}/{args.warmup} done")
+        log(f"warmup {w + 1}/{warmup} done")
     torch.cuda.synchronize()
-    L.lnocc_profile_enable(True)
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        res = L.solve_batch(dev, precision=args.precision, batch_slots=args.batch_slots,
+    for k in range(steps):
+        res = L.solve_batch(dev, precision=precision, batch_slots=args.batch_slots,
                             batch_streams=args.batch_streams, **kw)
-        log(f"batch step {k + 1}/{args.steps} done")
+        log(f"batch step {k + 1}/{steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    L.lnocc_profile_enable(False)
-    prof = L.lnocc_profile_collect()
     n = len(shapes)
-    out = {"value": n * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
-           "config": {"workload": "batch", "fragments": n, "precision": args.precision,
+    out = {"value": n * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+           "config": {"workload": "batch", "fragments": n, "precision": precision,
                       "conv_tol": args.conv_tol, "batch_slots": args.batch_slots,
-                      "batch_streams": args.batch_streams,
+                      "batch_streams": args.batch_streams, "plans": "heuristic (not tuned)",
                       "ccsd_iterations": sum(r.n_iter for r in res),
                       "statuses": {str(st): sum(r.status == st for r in res)
-                                   for st in sorted({r.status for r in res})}},
-           "kernels": kernel_table(prof), "roofline": roofline(prof, args.precision, "batch")}
+                                   for st in sorted({r.status for r in res})}}}
+    if leg:
+        out["unit"] = "fragments/s"
+        out["seconds"] = elapsed
+    gpath = ROOT / "tests" / "golden" / "batch_ccsd.json"
+    if gpath.exists():
+        gold = json.loads(gpath.read_text())
+        dcc, dt = [], []
+        for g in gold["fragments"]:
+            k = g["index"]
+            if shapes[k][3] == g["seed"]:
+                dcc.append(abs(res[k].e_ccsd - g["e_ccsd"]))
+                dt.append(abs(res[k].e_t - g["e_t"]))
+        if dcc:
+            out["parity_vs_oracle"] = {"fragments": len(dcc), "max_abs_d_e_ccsd": max(dcc),
+                                       "max_abs_d_e_t": max(dt)}
     if args.compare_fp64:
         t0 = time.perf_counter()
         seq = []
@@ -279,6 +373,16 @@ def run_batch(args, L, torch) -> dict:
         out["fp64_sequential"] = {"value": n / el, "unit": "solves/s", "seconds": el,
                                   "max_abs_d_e_ccsd": max(de), "max_abs_d_e_t": max(dt)}
         out["speedup_vs_fp64_sequential"] = out["value"] / out["fp64_sequential"]["value"]
+    if not leg:
+        # per-class launch times from one more (untimed) batch with HIP events
+        L.lnocc_profile_enable(True)
+        L.solve_batch(dev, precision=precision, batch_slots=args.batch_slots,
+                      batch_streams=args.batch_streams, **kw)
+        torch.cuda.synchronize()
+        L.lnocc_profile_enable(False)
+        prof = L.lnocc_profile_collect()
+        out["kernels"] = kernel_table(prof)
+        out["roofline"] = roofline(prof, precision, "batch")
     return out
 
 

@@ -121,6 +121,21 @@ def dressed_fock(B: np.ndarray, Bt: np.ndarray, eps: np.ndarray, nocc: int,
 
 
 # ---------------------------------------------------------------- residuals
+def ladder(Bvv: np.ndarray, t2: np.ndarray, block: int = 8) -> np.ndarray:
+    """Particle-particle ladder sum_cd t_ij^cd (ac|bd)~ as an [i,j,a,b] array.
+
+    (ac|bd)~ = sum_Q B~[Q,a,c] B~[Q,b,d] is formed for a few values of a at a
+    time, so that no v^4 array is held; the sum itself is the plain one.
+    """
+    nocc, nvir = t2.shape[0], t2.shape[2]
+    R = np.zeros((nocc, nocc, nvir, nvir))
+    for a0 in range(0, nvir, block):
+        a1 = min(nvir, a0 + block)
+        g = eri(Bvv[:, a0:a1, :], Bvv)                     # (ac|bd)~ [a,c,b,d]
+        R[:, :, a0:a1, :] = np.einsum("ijcd,acbd->ijab", t2, g, optimize=True)
+    return R
+
+
 def residuals(B: np.ndarray, eps_occ: np.ndarray, eps_vir: np.ndarray,
               t1: np.ndarray, t2: np.ndarray):
     """CCSD residuals R1[i,a], R2[i,j,a,b] (see module docstring)."""
@@ -133,7 +148,6 @@ def residuals(B: np.ndarray, eps_occ: np.ndarray, eps_vir: np.ndarray,
     Boo, Bov, Bvo, Bvv = Bt[:, o, o], Bt[:, o, v], Bt[:, v, o], Bt[:, v, v]
 
     g_vovo = eri(Bvo, Bvo)      # (ai|bj)~
-    g_vvvv = eri(Bvv, Bvv)      # (ac|bd)~
     g_oooo = eri(Boo, Boo)      # (ki|lj)~
     g_ovov = eri(Bov, Bov)      # (kc|ld)   (the ov block is not dressed)
     g_oovv = eri(Boo, Bvv)      # (ki|ac)~
@@ -152,7 +166,7 @@ def residuals(B: np.ndarray, eps_occ: np.ndarray, eps_vir: np.ndarray,
 
     # doubles: bare coupling and particle-particle ladder
     R2 = g_vovo.transpose(1, 3, 0, 2).copy()
-    R2 += np.einsum("ijcd,acbd->ijab", t2, g_vvvv, optimize=True)
+    R2 += ladder(Bvv, t2)
     # hole-hole ladder
     Wkl = g_oooo.transpose(0, 2, 1, 3) + np.einsum("ijcd,kcld->klij", t2, g_ovov,
                                                    optimize=True)

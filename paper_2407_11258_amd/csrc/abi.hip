@@ -168,7 +168,8 @@ int advance(Slot &q, const lnocc_options_t *opt) {
   int st = LNOCC_OK;
   switch (q.stage) {
     case Slot::Stage::Begin:
-      r.after_begin();
+      st = r.after_begin();
+      if (st) return st;
       if (r.phase == CcsdRun::Phase::Converged) {
         st = r.enqueue_final();
         q.stage = Slot::Stage::Final;

@@ -20,6 +20,7 @@
 #include "gett.h"
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 #include <map>
 #include <mutex>
@@ -782,10 +783,12 @@ bool descriptor_ok(const GemmDesc &d, int nsplit) {
 }
 }  // namespace
 
-static bool g_dry = false;
+// Process-wide switches (atomic: read by every launching thread).
+static std::atomic<bool> g_dry{false};
 
 struct Record { Kind kind; hipEvent_t start, stop; double flops; std::string shape; };
-static bool g_profile = false;
+static std::atomic<bool> g_profile{false};
+static std::mutex g_records_mu;        // launch records of every thread
 static std::vector<Record> g_records;
 
 void profile_enable(bool on) { g_profile = on; }
@@ -797,6 +800,7 @@ void profile_collect(KindStats out[(int)Kind::Count]) {
   for (int k = 0; k < (int)Kind::Count; ++k) out[k] = KindStats{0, 0.0, 0.0};
   const bool dump = std::getenv("LNOCC_PROFILE_DUMP") != nullptr;
   std::map<std::string, KindStats> by_shape;
+  std::lock_guard<std::mutex> lock(g_records_mu);
   for (const Record &r : g_records) {
     float ms = 0.f;
     (void)hipEventSynchronize(r.stop);
@@ -920,6 +924,7 @@ constexpr int kTileCands = 9, kSplitRules = 3;
 struct TilePlan { int tile; int nsplit; };
 std::mutex g_plan_mu;
 std::map<std::string, TilePlan> g_plans;
+std::atomic<bool> g_have_plans{false};   // !g_plans.empty(), readable without the lock
 thread_local int g_cand = -1;          // -1 off, kProbeCand: keys only
 constexpr int kProbeCand = 1 << 20;
 thread_local int g_unplanned = 0;      // keys seen by a probe pass without a plan
@@ -980,6 +985,7 @@ int tune_commit() {
       if (best < 0 || c.second.first < best) { best = c.second.first; plan = c.second.second; }
     g_plans[kv.first] = plan;
   }
+  g_have_plans = !g_plans.empty();
   return (int)t.size();
 }
 
@@ -1007,6 +1013,7 @@ int tune_load(const char *path) {
     g_plans[key] = TilePlan{tile, ns};
     ++n;
   }
+  g_have_plans = !g_plans.empty();
   std::fclose(f);
   return n;
 }
@@ -1014,6 +1021,7 @@ int tune_load(const char *path) {
 void tune_clear() {
   std::lock_guard<std::mutex> lock(g_plan_mu);
   g_plans.clear();
+  g_have_plans = false;
 }
 
 hipError_t gett(const GemmDesc &din, hipStream_t stream) {
@@ -1085,6 +1093,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
                       (int)d.prec, d.M, d.Mi, d.seg[0].K, d.seg[0].Ki);
         shape = buf;
       }
+      std::lock_guard<std::mutex> lock(g_records_mu);
       g_records.push_back(Record{d.kind, ev[0], ev[1], 2.0 * d.M * (double)d.seg[0].K, shape});
     }
     return err;
@@ -1156,7 +1165,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   std::string key;
   int cand = -1;
   if (!g_dry && d.kind != Kind::LadderBuild && d.tile_hint == 0 &&
-      (g_cand >= 0 || !g_plans.empty())) {
+      (g_cand >= 0 || g_have_plans.load())) {
     key = plan_key(d);
     if (g_cand == kProbeCand) {
       std::lock_guard<std::mutex> lock(g_plan_mu);
@@ -1264,6 +1273,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
                     (tile == kTileSplit || tile == kTileSplit160) ? " bf16-split" : "", nsplit);
       shape = buf;
     }
+    std::lock_guard<std::mutex> lock(g_records_mu);
     g_records.push_back(Record{d.kind, ev[0], ev[1], flops * d.batch, shape});
   }
   return err;

@@ -18,6 +18,12 @@ inline int64_t triples_blocks_per_entry(int64_t nb) {
   const int64_t fill = (kTriplesGrid + nb - 1) / nb;
   return fill > kTriplesBlocks ? fill : kTriplesBlocks;
 }
+// Partial sums any launch over b <= nb triples can write: b * max(128, ceil(4096 / b))
+// is at most max(128 nb, 4096 + b - 1).
+inline int64_t triples_partials_capacity(int64_t nb) {
+  const int64_t a = nb * kTriplesBlocks, b = kTriplesGrid + nb;
+  return a > b ? a : b;
+}
 
 hipError_t split_B(const double *B, int64_t X, int64_t o, int64_t v,
                    double *Boo, double *Bov, double *Bvv, hipStream_t s);
@@ -69,8 +75,11 @@ hipError_t triples_table(int *table, int64_t o, hipStream_t s);
 // (T) energy of a batch of unique triples whose W tensors sit in W[nb][v][v][v].
 // table holds (i, j, k) per entry, i <= j <= k; partials[nb * tiles] per tile.
 // W element type: 0 double, 1 float
+// capacity: length of partials; a launch that would write more is refused
+// (hipErrorInvalidValue, also in validation mode).
 hipError_t triples_energy(const void *W, int wtype, const int *table, int nb, const double *Kov,
                           const double *t1, const double *eo, const double *ev, int64_t o,
-                          int64_t v, double *partials, int64_t *nparts, hipStream_t s);
+                          int64_t v, double *partials, int64_t capacity, int64_t *nparts,
+                          hipStream_t s);
 
 }  // namespace lnocc

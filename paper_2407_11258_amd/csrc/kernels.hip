@@ -644,13 +644,19 @@ hipError_t triples_table(int *table, int64_t o, hipStream_t s) {
 }
 hipError_t triples_energy(const void *W, int wtype, const int *table, int nb, const double *Kov,
                           const double *t1, const double *eo, const double *ev, int64_t o,
-                          int64_t v, double *partials, int64_t *nparts, hipStream_t s) {
+                          int64_t v, double *partials, int64_t capacity, int64_t *nparts,
+                          hipStream_t s) {
   const int tpd = (int)((v + TT - 1) / TT);
   const int64_t orbits = (int64_t)tpd * (tpd + 1) * (tpd + 2) / 6;
   // small batches (large v) get more blocks per triple, so the launch fills the chip
   const int64_t want = triples_blocks_per_entry(nb);
   const int per_entry = (int)(orbits < want ? orbits : want);
   *nparts = (int64_t)per_entry * nb;
+  if (*nparts > capacity) {
+    note_error("(T) energy partials: %lld needed, %lld allocated", (long long)*nparts,
+               (long long)capacity);
+    return hipErrorInvalidValue;
+  }
   if (dry_run()) return hipSuccess;
   if (wtype == 1)
     hipLaunchKernelGGL(k_triples_energy<float>, dim3(per_entry, nb), dim3(kRedThreads), 0, s,

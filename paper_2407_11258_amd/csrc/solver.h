@@ -54,6 +54,7 @@ struct Layout {
   int64_t nunique = 0;              // amplitudes with i <= j: o (o + 1) / 2 v^2
   // (T)
   double *Gt, *Jt, *W, *tpart;      // (ai|bd) [i][a][b][d], (ck|jl) [j][k][c][l], W [nb][v][v][v]
+  int64_t tpart_elems = 0;          // capacity of tpart (energy partial sums)
   int *table;
   int nb;
   int64_t ntriples;

@@ -177,7 +177,8 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.Gt = A.d(ov * vv); L.Jt = A.d(oo * ov);
   L.W = A.d(nb * vvv);
   L.t2_lp = (L.lp != Prec::F64) ? A.d(oovv) : nullptr;
-  L.tpart = A.d(nb * triples_blocks_per_entry(nb));
+  L.tpart_elems = triples_partials_capacity(nb);
+  L.tpart = A.d(L.tpart_elems);
   L.table = A.i(3 * std::max<int64_t>(nt, 1));
   const size_t t_end = A.off;
   L.bytes = std::max(ccsd_end, t_end) + 256;
@@ -919,7 +920,8 @@ int run_ccsd(const Layout &L, const Inputs &in, const lnocc_options_t &opt, Outp
   int st = r.begin();
   if (st) return st;
   LN_TRY(r.wait());
-  r.after_begin();
+  st = r.after_begin();
+  if (st) { out = r.out; return st; }
   while (r.phase != CcsdRun::Phase::Converged && r.phase != CcsdRun::Phase::Exhausted) {
     st = r.enqueue_iteration();
     if (st) return st;
@@ -1028,7 +1030,8 @@ int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s, bool autot
       std::fflush(stderr);
     }
     int64_t nparts = 0;
-    LN_TRY(triples_energy(L.W, wtype, table, nb, L.Kov, t1, in.eo, in.ev, o, v, L.tpart, &nparts, s));
+    LN_TRY(triples_energy(L.W, wtype, table, nb, L.Kov, t1, in.eo, in.ev, o, v, L.tpart,
+                          L.tpart_elems, &nparts, s));
     LN_TRY(reduce_partials(L.tpart, nparts, acc, 1, s));
   }
   return LNOCC_OK;

@@ -9,6 +9,10 @@ from .fragments import (
     make_fragment,
     batch_shapes,
     CONFIG_SHAPES,
+    random_amplitudes,
+    BATCH_ORACLE_SUBSET,
+    LARGE_TRIPLES_SHAPE,
 )
 
-__all__ = ["Fragment", "make_fragment", "batch_shapes", "CONFIG_SHAPES"]
+__all__ = ["Fragment", "make_fragment", "batch_shapes", "CONFIG_SHAPES", "random_amplitudes",
+           "BATCH_ORACLE_SUBSET", "LARGE_TRIPLES_SHAPE"]

@@ -78,3 +78,29 @@ def batch_shapes(nfrag: int = 64, seed: int = 3):
     v = rng.integers(60, 221, size=nfrag)
     return [(int(o[f]), int(v[f]), int(3 * (o[f] + v[f])), 1000 * seed + f)
             for f in range(nfrag)]
+
+
+def random_amplitudes(nocc: int, nvir: int, seed: int, scale1: float = 5e-3,
+                      scale2: float = 1e-2):
+    """Seeded amplitudes (t1[o,v], t2[o,o,v,v]) with t2[i,j,a,b] = t2[j,i,b,a].
+
+    rng = default_rng(seed); t1 = scale1 N(0,1) drawn first, then
+    Z = scale2 N(0,1) of shape (o,o,v,v) and t2 = (Z + Z^T_(ij)(ab)) / 2.
+    """
+    rng = np.random.default_rng(seed)
+    t1 = scale1 * rng.standard_normal((nocc, nvir))
+    z = scale2 * rng.standard_normal((nocc, nocc, nvir, nvir))
+    t2 = 0.5 * (z + z.transpose(1, 0, 3, 2))
+    return t1, np.ascontiguousarray(t2)
+
+
+# Fragments of the batched workload (indices into batch_shapes()) that carry
+# full oracle CCSD and (T) values: they span nocc 6..24 and nvir 60..214,
+# including the largest fragment of the batch.
+BATCH_ORACLE_SUBSET = (20, 48, 31, 51, 53, 4, 49, 26)
+
+# (T) at the virtual and auxiliary size of the large workload with few
+# occupied orbitals, on seeded amplitudes: (nocc, nvir, naux, fragment seed,
+# amplitude seed).
+LARGE_TRIPLES_SHAPE = (6, 400, 1300, 4, 44)
+

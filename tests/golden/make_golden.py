@@ -5,9 +5,14 @@ and stores energies, iteration counts, amplitude norms and a seeded sample of
 amplitude elements as JSON next to this script.  A name with the suffix
 ":mp2" stores only the MP2 energy and the MP1 amplitudes (sample and norm), which
 the oracle computes in seconds even at the large workload's full size ("batch:mp2":
-each of the 64 fragments of the batched workload).  Usage:
+each of the 64 fragments of the batched workload).  "batch:ccsd" stores
+converged CCSD and (T) values for the fragments of the batched workload listed in
+synth.BATCH_ORACLE_SUBSET (written after each fragment), and "large:triples" the (T)
+energy at the large workload's virtual and auxiliary size with few occupied
+orbitals on seeded amplitudes (synth.LARGE_TRIPLES_SHAPE).  Usage:
 
-    python tests/golden/make_golden.py single_small single_realistic large:mp2 batch:mp2
+    python tests/golden/make_golden.py single_small single_realistic large:mp2 batch:mp2 \
+        batch:ccsd large:triples
 """
 from __future__ import annotations
 
@@ -22,7 +27,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from oracle import ccsd as occ, triples as otr  # noqa: E402
-from synth import CONFIG_SHAPES, batch_shapes, make_fragment  # noqa: E402
+from synth import (BATCH_ORACLE_SUBSET, CONFIG_SHAPES, LARGE_TRIPLES_SHAPE,  # noqa: E402
+                   batch_shapes, make_fragment, random_amplitudes)
 
 CONV_TOL = 1e-10
 NSAMPLE = 256
@@ -30,6 +36,11 @@ NSAMPLE = 256
 
 def golden(name: str) -> dict:
     o, v, X, seed = CONFIG_SHAPES[name]
+    return solve_and_sample(name, o, v, X, seed)
+
+
+def solve_and_sample(name: str, o: int, v: int, X: int, seed: int) -> dict:
+    """Converged oracle CCSD and (T) of one synthetic fragment, with samples."""
     f = make_fragment(o, v, X, seed)
     t0 = time.time()
     r = occ.ccsd(f.B, f.eps_occ, f.eps_vir, conv_tol=CONV_TOL, max_iter=200)
@@ -91,10 +102,57 @@ def golden_batch_mp2() -> dict:
             "oracle_seconds": {"mp2": time.time() - t0}}
 
 
+def golden_batch_ccsd(path: str) -> dict:
+    """Converged CCSD and (T) of the subset of batched-workload fragments; the
+    file is rewritten after each fragment (smallest first)."""
+    shapes = batch_shapes()
+    subset = sorted(BATCH_ORACLE_SUBSET,
+                    key=lambda k: shapes[k][0] ** 3 * shapes[k][1] ** 4)
+    out = {"workload": "batch", "subset": list(subset), "fragments": []}
+    for k in subset:
+        o, v, X, seed = shapes[k]
+        g = solve_and_sample(f"batch[{k}]", o, v, X, seed)
+        g["index"] = k
+        out["fragments"].append(g)
+        with open(path, "w") as fh:
+            json.dump(out, fh, indent=1)
+        print(f"batch[{k}] {o} {v} {X}: iters {g['n_iter']} E_CCSD {g['e_ccsd']:.12f} "
+              f"E_T {g['e_t']:.12f} {g['oracle_seconds']}", flush=True)
+    return out
+
+
+def golden_large_triples() -> dict:
+    """(T) (restricted and, as a check, nothing else) on seeded amplitudes at the
+    large workload's virtual and auxiliary size."""
+    o, v, X, seed, aseed = LARGE_TRIPLES_SHAPE
+    f = make_fragment(o, v, X, seed)
+    t1, t2 = random_amplitudes(o, v, aseed)
+    t0 = time.time()
+    e_t = otr.e_triples_restricted(f.B, f.eps_occ, f.eps_vir, t1, t2)
+    h = __import__("hashlib").sha256()
+    h.update(t1.tobytes())
+    h.update(t2.tobytes())
+    return {"workload": "large_triples", "nocc": o, "nvir": v, "naux": X, "seed": seed,
+            "amplitude_seed": aseed, "input_sha256": f.sha256(),
+            "amplitude_sha256": h.hexdigest(), "e_t": e_t,
+            "oracle_seconds": {"triples": time.time() - t0}}
+
+
 if __name__ == "__main__":
     for arg in sys.argv[1:] or ["single_small"]:
         name, _, part = arg.partition(":")
         here = os.path.dirname(os.path.abspath(__file__))
+        if part == "ccsd" and name == "batch":
+            path = os.path.join(here, "batch_ccsd.json")
+            golden_batch_ccsd(path)
+            continue
+        if part == "triples" and name == "large":
+            g = golden_large_triples()
+            path = os.path.join(here, "large_triples.json")
+            with open(path, "w") as fh:
+                json.dump(g, fh, indent=1)
+            print(arg, g["e_t"], g["oracle_seconds"], flush=True)
+            continue
         if part == "mp2":
             g = golden_batch_mp2() if name == "batch" else golden_mp2(name)
             path = os.path.join(here, f"{name}_mp2.json")

@@ -145,6 +145,24 @@ def test_small_ladder_blocks_and_triple_batches(validation_mode):
     assert L.lnocc_fragment_ccsd(f, opt) == L.LNOCC_OK
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_triples_partials_fit_every_batch(validation_mode, precision):
+    """The (T) energy launch of every batch of triples, the short last one
+    included, writes no more partial sums than the workspace holds (the launcher
+    refuses one that would)."""
+    shapes = [s[:3] for s in batch_shapes()] + [(9, 202, 633), (13, 207, 660), (18, 214, 696),
+                                                 (5, 30, 60), (40, 40, 240)]
+    for (o, v, X) in shapes:
+        for nb in (0, 3, 7, 31):
+            opt = L.make_options(precision=precision, triples_batch=nb)
+            f = _fake_fragment(o, v, X)
+            st, nbytes = L.lnocc_workspace_bytes([f], opt)
+            assert st == L.LNOCC_OK
+            opt.workspace, opt.workspace_bytes = 1 << 45, nbytes
+            assert L.lnocc_fragment_triples(f, opt) == L.LNOCC_OK, (o, v, X, nb,
+                                                                    L.lnocc_last_error())
+
+
 def _batch(shapes):
     arr = (L.lnocc_fragment_t * len(shapes))()
     for k, (o, v, X) in enumerate(shapes):
