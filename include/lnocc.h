@@ -321,7 +321,10 @@ int lnocc_mlp_loss_grad(const float *blob, const float *X, const float *Y, int64
 
 /* nsteps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8; step numbers step0 + 1,
  * ...) on the trainable part of blob, each on `batch` rows of (X, Y) drawn by a
- * counter-based generator keyed by (seed, step); adam: device float
+ * counter-based generator keyed by (seed, step): row k of step t is
+ * splitmix64(seed XOR splitmix64(t * 2^32 + k)) mod n, where splitmix64(z) is
+ * the output function of the splitmix64 generator (Steele, Lea and Flood 2014)
+ * at counter value z; adam: device float
  * [2 LNOCC_MLP_PARAMS] moments, zero before the first step.  losses (host, may be
  * NULL) receives the minibatch loss before each step. */
 int lnocc_mlp_train(float *blob, float *adam, int64_t step0, int32_t nsteps, const float *X,

@@ -203,3 +203,52 @@ def adam_step(p: np.ndarray, g: np.ndarray, m1: np.ndarray, m2: np.ndarray, step
     mh = m1 / (1 - beta1 ** step)
     vh = m2 / (1 - beta2 ** step)
     p -= lr * mh / (np.sqrt(vh) + eps)
+
+
+# ---------------------------------------------------------------- training
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64(z: int) -> int:
+    """Output function of splitmix64 (Steele, Lea and Flood, OOPSLA 2014) at
+    counter value z: add the golden-gamma increment, then two xor-shift-multiply
+    rounds and a final xor-shift, all modulo 2^64."""
+    z = (z + 0x9E3779B97F4A7C15) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def minibatch_rows(seed: int, step: int, batch: int, n: int) -> np.ndarray:
+    """Rows of the minibatch of Adam step `step` (counted from 1): row k is
+    splitmix64(seed XOR splitmix64(step * 2^32 + k)) mod n."""
+    return np.array([splitmix64((seed ^ splitmix64(((step << 32) | k) & MASK64)) & MASK64) % n
+                     for k in range(batch)], dtype=np.int64)
+
+
+def gradient_vector(m: Model, g: Model) -> np.ndarray:
+    """Trainable part of the blob layout holding the gradient fields of g."""
+    return pack(dataclasses.replace(g, mu=m.mu, inv_sigma=m.inv_sigma, y_mu=m.y_mu,
+                                    y_sigma=m.y_sigma))[HEADER:]
+
+
+def train(blob: np.ndarray, X: np.ndarray, Y: np.ndarray, step0: int, nsteps: int, batch: int,
+          lr: float, seed: int, m1: np.ndarray | None = None, m2: np.ndarray | None = None):
+    """nsteps Adam steps on the trainable part of blob (FP64 copy), each on the
+    minibatch drawn by minibatch_rows; returns (blob, m1, m2, losses)."""
+    b = np.array(blob, dtype=np.float64)
+    H = 256
+    P = n_params(H)
+    m1 = np.zeros(P) if m1 is None else np.array(m1, dtype=np.float64)
+    m2 = np.zeros(P) if m2 is None else np.array(m2, dtype=np.float64)
+    losses = []
+    for k in range(nsteps):
+        t = step0 + k + 1
+        rows = minibatch_rows(seed, t, batch, X.shape[0])
+        m = unpack(b, H)
+        L, g = loss_and_grad(m, X[rows], Y[rows])
+        losses.append(L)
+        p = b[HEADER:]
+        adam_step(p, gradient_vector(m, g), m1, m2, t, lr)
+        b[HEADER:] = p
+    return b, m1, m2, losses

@@ -91,6 +91,69 @@ def test_adam_first_step_is_lr_times_sign():
     np.testing.assert_allclose(p, [0.99, -1.99, 2.99], rtol=0, atol=1e-15)
 
 
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With the same gradient at every step the bias-corrected moments are
+    exactly g and g^2, so each Adam step moves every parameter by lr against
+    the sign of its gradient (eps = 0), whatever the gradient's size.  A wrong
+    bias-correction exponent or decay rate breaks this from step 2 on."""
+    p0 = np.array([1.0, -2.0, 3.0, 0.5, -0.25])
+    g = np.array([0.5, -4.0, 1e-3, 7e2, -3e-5])
+    p = p0.copy()
+    m1, m2 = np.zeros(5), np.zeros(5)
+    lr = 0.01
+    for t in range(1, 8):
+        mlp.adam_step(p, g, m1, m2, step=t, lr=lr, eps=0.0)
+        np.testing.assert_allclose(p, p0 - t * lr * np.sign(g), rtol=0, atol=1e-13)
+        np.testing.assert_allclose(m1 / (1 - 0.9 ** t), g, rtol=1e-13)
+        np.testing.assert_allclose(m2 / (1 - 0.999 ** t), g * g, rtol=1e-12)
+
+
+def test_adam_alternating_gradient_closed_form():
+    """Gradient +g, -g, +g, ...: m1_t = (1 - b1) g sum_s b1^(t-s) (-1)^(s-1)
+    = (1 - b1) g (b1^t - (-1)^t) / (b1 + 1) (geometric series) and m2_t = g^2 (1 - b2^t)."""
+    b1, b2, lr, eps = 0.9, 0.999, 1e-3, 1e-8
+    g0 = np.array([0.3, -2.0, 5e-4])
+    p = np.zeros(3)
+    m1, m2 = np.zeros(3), np.zeros(3)
+    expect = np.zeros(3)
+    for t in range(1, 7):
+        mlp.adam_step(p, g0 * (-1) ** (t - 1), m1, m2, step=t, lr=lr)
+        m1t = (1 - b1) * g0 * (b1 ** t - (-1) ** t) / (b1 + 1)
+        m2t = g0 * g0 * (1 - b2 ** t)
+        expect -= lr * (m1t / (1 - b1 ** t)) / (np.sqrt(m2t / (1 - b2 ** t)) + eps)
+        np.testing.assert_allclose(p, expect, rtol=1e-12, atol=1e-18)
+
+
+def test_splitmix64_reference_outputs():
+    """First outputs of the splitmix64 generator started from state 0 (the
+    published reference sequence): the state advances by the golden gamma
+    0x9E3779B97F4A7C15 and each output is the mixing function of the state."""
+    gamma = 0x9E3779B97F4A7C15
+    out = [mlp.splitmix64((k * gamma) & mlp.MASK64) for k in range(4)]
+    assert out == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F,
+                   0xF88BB8A8724C81EC]
+    rows = mlp.minibatch_rows(seed=7, step=3, batch=1000, n=37)
+    assert rows.min() >= 0 and rows.max() < 37 and len(set(rows.tolist())) == 37
+
+
+def test_first_training_step_is_lr_times_gradient_sign():
+    """Step 1 of the oracle's training loop moves each parameter by
+    -lr g / (|g| + eps), with g the gradient on the rows minibatch_rows draws."""
+    rng = np.random.default_rng(8)
+    m = _random_model(256, rng, scale=0.05)
+    blob = mlp.pack(m)
+    X = rng.normal(size=(300, 16))
+    Y = rng.normal(size=300) * 0.1
+    b1, _, _, losses = mlp.train(blob, X, Y, step0=0, nsteps=1, batch=64, lr=1e-3, seed=5)
+    rows = mlp.minibatch_rows(5, 1, 64, 300)
+    L, g = mlp.loss_and_grad(m, X[rows], Y[rows])
+    gv = mlp.gradient_vector(m, g)
+    np.testing.assert_allclose(b1[mlp.HEADER:] - blob[mlp.HEADER:], -1e-3 * gv / (np.abs(gv) + 1e-8),
+                               rtol=1e-9, atol=1e-15)
+    assert abs(losses[0] - L) < 1e-15
+    np.testing.assert_array_equal(b1[:mlp.HEADER], blob[:mlp.HEADER])
+
+
 def test_features_from_their_definitions():
     f = make_fragment(3, 7, 20, 11)
     o, v = 3, 7
