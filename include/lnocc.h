@@ -18,7 +18,9 @@
  *  - t1[i][a] = t_i^a; t2[i][j][a][b] = t_ij^ab (= t_iajb of the paper),
  *    which satisfies t2[i][j][a][b] = t2[j][i][b][a].
  *  - The caller owns every buffer.  The library allocates no device memory:
- *    all scratch comes from the workspace the caller passes in options.
+ *    all scratch comes from the workspace the caller passes in options
+ *    (lnocc_fragment_ccsd_static alone uses a static device array of the
+ *    library instead).
  *  - Work is enqueued on options.stream (a hipStream_t; NULL = default
  *    stream).  Every entry point returns after that stream has completed the
  *    work, so host-side outputs are valid on return.
@@ -168,6 +170,22 @@ int lnocc_workspace_bytes(const lnocc_fragment_t *f, int32_t nfrag,
  * iterations in a row, or rises 1000-fold above the best one, restarts the
  * DIIS subspace. */
 int lnocc_fragment_ccsd(lnocc_fragment_t *f, const lnocc_options_t *opt);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as lnocc_fragment_ccsd (same kernels and results), with its scratch in
+ * a static device array of the library (LNOCC_STATIC_SCRATCH_BYTES per GPU,
+ * held until the process ends) instead of opt->workspace, which is ignored.
+ * The call makes no device or pinned-host allocation: no graph capture, no
+ * autotuning (opt->graphs and opt->autotune are ignored), readbacks go through
+ * a static host buffer with stream synchronization.  A fragment whose scratch
+ * need (lnocc_workspace_bytes) exceeds the array gets LNOCC_ENOMEM and a
+ * message in lnocc_last_error(); nothing runs.  The array keeps the last
+ * call's contents; the solver initializes everything it reads.  Calls on one
+ * GPU share its array: calls from threads of this process are serialized by a
+ * lock per device; calls that overlap in any other way race. */
+#define LNOCC_STATIC_SCRATCH_BYTES (64u << 20)
+int lnocc_fragment_ccsd_static(lnocc_fragment_t *f, const lnocc_options_t *opt);
 
 /* (T) energy (Eq. 16 at i = i' summed over i; W, V and Delta of SI Sec. S1)
  * of the amplitudes already in f->t1 / f->t2.  Writes f->e_t and returns the

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <vector>
@@ -124,6 +125,63 @@ int finish(lnocc_fragment_t *f, int st) {
   if (f) f->status = st;
   return st;
 }
+
+}  // namespace
+
+// ------------------------------------------------------------------ static scratch
+// Device scratch of lnocc_fragment_ccsd_static: one array per GPU, held until
+// the process ends.  In host code its name is not a device address; the
+// address of each device's copy comes from hipGetSymbolAddress, taken once per
+// device with that device current.
+namespace {
+constexpr size_t kStaticScratchBytes = (size_t)LNOCC_STATIC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+std::mutex g_static_mu;                       // guards the address table
+void *g_static_ptr[kMaxDevices] = {};
+std::mutex g_static_use[kMaxDevices];         // one call at a time per device
+double g_static_host[kMaxDevices][kReadbackDoubles];   // readbacks of that call
+
+// Holds this device's array (and its host readback buffer) for one call.
+struct StaticScratch {
+  void *ptr = nullptr;
+  double *host = nullptr;
+  std::unique_lock<std::mutex> hold;
+  int acquire() {
+    if (dry_run()) {   // validation mode: a stand-in address, never dereferenced
+      ptr = (void *)((uintptr_t)1 << 47);
+      static double dry_host[kReadbackDoubles];
+      host = dry_host;
+      return LNOCC_OK;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+      note_error("hipGetDevice failed (%s)", hipGetErrorString(e));
+      return LNOCC_EDEVICE;
+    }
+    {
+      std::lock_guard<std::mutex> lock(g_static_mu);
+      if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+          note_error("hipGetSymbolAddress of the static scratch failed (%s)",
+                     hipGetErrorString(e));
+          return LNOCC_EDEVICE;
+        }
+        g_static_ptr[dev] = p;
+      }
+      ptr = g_static_ptr[dev];
+    }
+    hold = std::unique_lock<std::mutex>(g_static_use[dev]);
+    host = g_static_host[dev];
+    return LNOCC_OK;
+  }
+};
 
 // ------------------------------------------------------------------ batch
 constexpr int kDefaultBatchSlots = 4;
@@ -264,6 +322,54 @@ int lnocc_fragment_ccsd(lnocc_fragment_t *f, const lnocc_options_t *opt) {
   f->e_mp2 = out.e_mp2;
   f->e_ccsd = out.e_ccsd;
   f->e_t = opt->do_triples ? out.e_t : 0.0;
+  f->residual = out.residual;
+  f->n_iter = out.n_iter;
+  f->guess_used = out.guess_used;
+  return finish(f, st);
+}
+
+int lnocc_fragment_ccsd_static(lnocc_fragment_t *f, const lnocc_options_t *opt_in) {
+  clear_error();
+  if (!opt_in) return finish(f, LNOCC_EINVAL);
+  StaticScratch sc;
+  int st = sc.acquire();
+  if (st) return finish(f, st);
+  // the library's own device array replaces the caller's workspace; no graph
+  // capture and no tuning (both create runtime objects)
+  lnocc_options_t opt = *opt_in;
+  opt.workspace = sc.ptr;
+  opt.workspace_bytes = kStaticScratchBytes;
+  opt.graphs = 0;
+  opt.autotune = 0;
+  Layout L;
+  st = check_sizes(f);
+  if (!st) st = check_options(&opt);
+  if (!st) {
+    plan_layout(dims_of(f), opt, nullptr, L);
+    if (L.bytes > kStaticScratchBytes) {
+      note_error("fragment (%d, %d, %d) needs %zu bytes of scratch; the static array holds %zu",
+                 f->nocc, f->nvir, f->naux, L.bytes, kStaticScratchBytes);
+      st = LNOCC_ENOMEM;
+    }
+  }
+  if (st) return finish(f, st);
+  st = prepare(f, &opt, opt.guess == LNOCC_GUESS_USER, true, L);
+  if (st) return finish(f, st);
+  hipStream_t s = (hipStream_t)opt.stream;
+  Guard guard(f, &opt, L);
+  Inputs in{f->B, f->eps_occ, f->eps_vir, f->t1 ? f->t1 : L.t1w, f->t2 ? f->t2 : L.t2w,
+            f->conv_tol};
+  Outputs out;
+  Readback rb(sc.host);
+  st = run_ccsd(L, in, opt, out, s, &rb);
+  if (st >= 0 && opt.do_triples) {
+    const int st2 = run_triples(L, in, out, s, false, sc.host + kReadbackDoubles - 1);
+    if (st2 < 0) st = st2;
+  }
+  if (st < 0) dsync(s);
+  f->e_mp2 = out.e_mp2;
+  f->e_ccsd = out.e_ccsd;
+  f->e_t = opt.do_triples ? out.e_t : 0.0;
   f->residual = out.residual;
   f->n_iter = out.n_iter;
   f->guess_used = out.guess_used;

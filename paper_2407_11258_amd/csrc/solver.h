@@ -100,20 +100,30 @@ int setup_fragment(const Layout &L, const double *B, const double *eo, const dou
 int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s);
 int tune_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s);
 int energy(const Layout &L, const double *t1, const double *t2, double *dev_out, hipStream_t s);
+struct Readback;
+// rb: readback buffer to use (nullptr: a pinned one made for the call).
 int run_ccsd(const Layout &L, const Inputs &in, const lnocc_options_t &opt, Outputs &out,
-             hipStream_t s);
+             hipStream_t s, Readback *rb = nullptr);
+// host: one double of host memory for the energy readback (nullptr: pinned, made
+// for the call).
 int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s,
-                bool autotune = false);
+                bool autotune = false, double *host = nullptr);
 int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s, bool autotune = false);
 
 // Pinned host buffer for the small readbacks of one solve ([0] energy,
 // [1..16] DIIS overlaps, [32] step norm, [33] step norm from the MP2 start,
 // [34] its DIIS error norm, [40] (T) energy) and the event that
 // marks their arrival.  Owned by the caller of CcsdRun; reused across solves.
+// With an external buffer (caller-owned host memory of at least kReadbackDoubles
+// doubles) nothing is allocated and no event is made: arrival is then awaited
+// by synchronizing the stream.
+constexpr int kReadbackDoubles = 64;
 struct Readback {
   double *host = nullptr;
   hipEvent_t ev = nullptr;
+  bool external = false;
   Readback();
+  explicit Readback(double *buffer);
   ~Readback();
   Readback(const Readback &) = delete;
   Readback &operator=(const Readback &) = delete;

@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "gett.h"
@@ -615,7 +616,10 @@ Readback::Readback() {
   }
 }
 
+Readback::Readback(double *buffer) : host(buffer), ev(nullptr), external(true) {}
+
 Readback::~Readback() {
+  if (external) return;
   if (dry_run()) {
     std::free(host);
     return;
@@ -624,7 +628,9 @@ Readback::~Readback() {
   if (ev) (void)hipEventDestroy(ev);
 }
 
-bool Readback::ok() const { return host != nullptr && (dry_run() || ev != nullptr); }
+bool Readback::ok() const {
+  return host != nullptr && (dry_run() || external || ev != nullptr);
+}
 
 CcsdRun::CcsdRun(const Layout &L_, const Inputs &in_, const lnocc_options_t &opt_, hipStream_t s_,
                  Readback &rb_)
@@ -669,18 +675,23 @@ int CcsdRun::residuals() {
   return LNOCC_OK;
 }
 
-hipError_t CcsdRun::mark() { return dry_run() ? hipSuccess : hipEventRecord(rb->ev, s); }
+hipError_t CcsdRun::mark() {
+  return (dry_run() || !rb->ev) ? hipSuccess : hipEventRecord(rb->ev, s);
+}
 
 int CcsdRun::poll() const {
   if (dry_run()) return (++polls % 3 == 0) ? 1 : 0;   // exercises the pending state
-  const hipError_t e = hipEventQuery(rb->ev);
+  const hipError_t e = rb->ev ? hipEventQuery(rb->ev) : hipStreamQuery(s);
   if (e == hipSuccess) return 1;
   if (e == hipErrorNotReady) return 0;
   note_error("hipEventQuery failed (%s)", hipGetErrorString(e));
   return LNOCC_EDEVICE;
 }
 
-hipError_t CcsdRun::wait() const { return dry_run() ? hipSuccess : hipEventSynchronize(rb->ev); }
+hipError_t CcsdRun::wait() const {
+  if (dry_run()) return hipSuccess;
+  return rb->ev ? hipEventSynchronize(rb->ev) : hipStreamSynchronize(s);
+}
 
 // Learned start: first the residual at the MP2 start, whose Jacobi step and
 // error become the first DIIS pair (slot 0; also the fallback) and whose step
@@ -913,10 +924,14 @@ int CcsdRun::after_t() {
 }
 
 int run_ccsd(const Layout &L, const Inputs &in, const lnocc_options_t &opt, Outputs &out,
-             hipStream_t s) {
-  Readback rb;
-  if (!rb.ok()) return LNOCC_EDEVICE;
-  CcsdRun r(L, in, opt, s, rb);
+             hipStream_t s, Readback *rbx) {
+  std::unique_ptr<Readback> own;
+  if (!rbx) {
+    own.reset(new Readback());
+    rbx = own.get();
+  }
+  if (!rbx->ok()) return LNOCC_EDEVICE;
+  CcsdRun r(L, in, opt, s, *rbx);
   int st = r.begin();
   if (st) return st;
   LN_TRY(r.wait());
@@ -1038,20 +1053,20 @@ int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s, bool autot
 }
 
 int run_triples(const Layout &L, const Inputs &in, Outputs &out, hipStream_t s,
-                bool autotune) {
+                bool autotune, double *hostx) {
   int st = enqueue_triples(L, in, s, autotune);
   if (st) return st;
-  double *host = nullptr;
+  double *host = hostx;
   if (dry_run()) {
     out.e_t = 0.0;
     return LNOCC_OK;
   }
-  if (hipHostMalloc((void **)&host, sizeof(double), hipHostMallocDefault) != hipSuccess)
+  if (!host && hipHostMalloc((void **)&host, sizeof(double), hipHostMallocDefault) != hipSuccess)
     return LNOCC_EDEVICE;
   hipError_t e = d2h(host, L.scal + 40, 8, s);
   if (e == hipSuccess) e = dsync(s);
   out.e_t = *host;
-  (void)hipHostFree(host);
+  if (!hostx) (void)hipHostFree(host);
   if (e != hipSuccess) return LNOCC_EDEVICE;
   if (!std::isfinite(out.e_t)) return LNOCC_ENUMERIC;
   return LNOCC_OK;

@@ -83,7 +83,8 @@ KERNEL_CLASS_NAMES = ("other", "ladder_build", "ladder_contract", "triples_w", "
 
 EXPORTS = ("lnocc_default_options", "lnocc_status_string", "lnocc_last_error",
            "lnocc_workspace_bytes",
-           "lnocc_fragment_ccsd", "lnocc_fragment_triples", "lnocc_ccsd_residuals",
+           "lnocc_fragment_ccsd", "lnocc_fragment_ccsd_static", "lnocc_fragment_triples",
+           "lnocc_ccsd_residuals",
            "lnocc_batch_solve", "lnocc_contract", "lnocc_profile_enable",
            "lnocc_profile_collect", "lnocc_set_validation_mode", "lnocc_mlp_workspace_bytes",
            "lnocc_mlp_samples", "lnocc_mlp_init", "lnocc_mlp_predict", "lnocc_mlp_loss_grad",
@@ -110,7 +111,7 @@ def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
     lib.lnocc_last_error.restype = C.c_char_p
     lib.lnocc_workspace_bytes.argtypes = [FP, C.c_int32, OP, C.POINTER(C.c_size_t)]
     lib.lnocc_workspace_bytes.restype = C.c_int
-    for name in ("lnocc_fragment_ccsd", "lnocc_fragment_triples"):
+    for name in ("lnocc_fragment_ccsd", "lnocc_fragment_ccsd_static", "lnocc_fragment_triples"):
         getattr(lib, name).argtypes = [FP, OP]
         getattr(lib, name).restype = C.c_int
     lib.lnocc_ccsd_residuals.argtypes = [FP, OP, C.c_void_p, C.c_void_p]
@@ -184,6 +185,13 @@ def lnocc_workspace_bytes(frags, opt: lnocc_options_t) -> tuple[int, int]:
 
 def lnocc_fragment_ccsd(frag: lnocc_fragment_t, opt: lnocc_options_t) -> int:
     return _lib.lnocc_fragment_ccsd(C.byref(frag), C.byref(opt))
+
+
+LNOCC_STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def lnocc_fragment_ccsd_static(frag: lnocc_fragment_t, opt: lnocc_options_t) -> int:
+    return _lib.lnocc_fragment_ccsd_static(C.byref(frag), C.byref(opt))
 
 
 def lnocc_fragment_triples(frag: lnocc_fragment_t, opt: lnocc_options_t) -> int:

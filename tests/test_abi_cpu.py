@@ -163,6 +163,26 @@ def test_triples_partials_fit_every_batch(validation_mode, precision):
                                                                     L.lnocc_last_error())
 
 
+def test_static_scratch_entry_point(validation_mode):
+    """The no-allocation variant ignores the caller's workspace, runs the same
+    launch sequence inside its static array and refuses a fragment that needs
+    more than the array holds, naming the sizes."""
+    opt = L.make_options(precision="fp64")
+    opt.workspace, opt.workspace_bytes = 0, 0
+    for shp in [(4, 20, 72), (3, 14, 50), (6, 30, 100)]:
+        f = _fake_fragment(*shp)
+        need = L.lnocc_workspace_bytes([f], opt)[1]
+        assert need <= L.LNOCC_STATIC_SCRATCH_BYTES
+        assert L.lnocc_fragment_ccsd_static(f, opt) == L.LNOCC_OK, L.lnocc_last_error()
+    f = _fake_fragment(16, 160, 528)
+    assert L.lnocc_fragment_ccsd_static(f, opt) == L.LNOCC_ENOMEM
+    assert "static array" in L.lnocc_last_error()
+    assert f.status == L.LNOCC_ENOMEM
+    f = _fake_fragment(4, 20, 72)
+    f.conv_tol = 0.0
+    assert L.lnocc_fragment_ccsd_static(f, opt) == L.LNOCC_EINVAL
+
+
 def _batch(shapes):
     arr = (L.lnocc_fragment_t * len(shapes))()
     for k, (o, v, X) in enumerate(shapes):
