@@ -100,12 +100,22 @@ void profile_enable(bool on);
 bool profile_enabled();
 void profile_collect(KindStats out[(int)Kind::Count]);   // also clears
 
+// Launch timing of kernels launched outside gett(): while profiling is on,
+// begin() records an event before the launch and end() one after it, filed
+// under `kind` with the launch's algorithmic flops.  Both are no-ops otherwise.
+struct LaunchTimer { hipEvent_t start = nullptr, stop = nullptr; };
+LaunchTimer profile_begin(hipStream_t s);
+void profile_end(LaunchTimer &t, hipStream_t s, Kind kind, double flops);
+
 // Address guard.  While a region list is installed (per host thread), gett()
 // refuses to launch a contraction unless every address it can touch lies
 // inside one listed region.  The solver installs the workspace and the
 // caller's arrays; a descriptor mistake then becomes an error, not a fault.
 struct Region { const void *p; size_t bytes; };
 void install_regions(const Region *r, int n);   // n = 0 removes the list
+// For kernels launched outside gett(): [p, p + bytes) lies inside an installed
+// region (always true while none is installed).
+bool region_ok(const void *p, size_t bytes);
 
 // Validation mode: launches are checked against the guard and then skipped,
 // copies and synchronizations become no-ops and readbacks return zeros.  Lets

@@ -756,6 +756,14 @@ bool operand_ok(const GemmDesc &d, const GOperand &op, int64_t rows, int64_t Ri,
   return inside(op.p, s, esz);
 }
 
+}  // namespace
+
+bool region_ok(const void *p, size_t bytes) {
+  if (!g_regions || bytes == 0) return true;
+  return inside(p, Span{0, (int64_t)bytes - 1}, 1);
+}
+
+namespace {
 bool descriptor_ok(const GemmDesc &d, int nsplit) {
   if (!g_regions) return true;
   int64_t bmax[3];
@@ -792,6 +800,26 @@ static std::mutex g_records_mu;        // launch records of every thread
 static std::vector<Record> g_records;
 
 void profile_enable(bool on) { g_profile = on; }
+
+LaunchTimer profile_begin(hipStream_t s) {
+  LaunchTimer t;
+  if (!g_profile || g_dry) return t;
+  if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) {
+    if (t.start) (void)hipEventDestroy(t.start);
+    t.start = t.stop = nullptr;
+    return t;
+  }
+  (void)hipEventRecord(t.start, s);
+  return t;
+}
+
+void profile_end(LaunchTimer &t, hipStream_t s, Kind kind, double flops) {
+  if (!t.start) return;
+  (void)hipEventRecord(t.stop, s);
+  std::lock_guard<std::mutex> lock(g_records_mu);
+  g_records.push_back(Record{kind, t.start, t.stop, flops, std::string()});
+  t.start = t.stop = nullptr;
+}
 bool profile_enabled() { return g_profile; }
 
 // LNOCC_PROFILE_DUMP=1: profile_collect also prints every contraction shape

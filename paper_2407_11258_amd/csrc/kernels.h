@@ -69,7 +69,9 @@ hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, int64_t ca, int
                          double *R2, hipStream_t s);
 
 // table[3 n + {0,1,2}] <- (i, j, k) of the n-th unique triple i <= j <= k, not
-// all equal, in lexicographic order (o (o + 1) (o + 2) / 6 - o entries).
+// all equal (o (o + 1) (o + 2) / 6 - o entries): first the o (o - 1) (o - 2) / 6
+// with i < j < k, then the o (o - 1) / 2 with i = j < k, then the o (o - 1) / 2
+// with i < j = k, each group in lexicographic order.
 hipError_t triples_table(int *table, int64_t o, hipStream_t s);
 
 // (T) energy of a batch of unique triples whose W tensors sit in W[nb][v][v][v].

@@ -622,15 +622,18 @@ hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, int64_t ca, int
                      o, v, ca, ld, R2);
   return hipGetLastError();
 }
-// Unique triples i <= j <= k (not all equal) in lexicographic order; one
-// thread, once per (T) computation.
+// Unique triples i <= j <= k (not all equal) in three groups, each in
+// lexicographic order: i < j < k, then i = j < k, then i < j = k; one thread,
+// once per (T) computation.
 __global__ void k_triples_table(int *table, int o) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int64_t n = 0;
-  for (int i = 0; i < o; ++i)
-    for (int j = i; j < o; ++j)
-      for (int k = j; k < o; ++k)
-        if (!(i == j && j == k)) {
+  for (int g = 0; g < 3; ++g)
+    for (int i = 0; i < o; ++i)
+      for (int j = i; j < o; ++j)
+        for (int k = j; k < o; ++k) {
+          const int grp = (i < j && j < k) ? 0 : (i == j && j < k) ? 1 : (i < j && j == k) ? 2 : 3;
+          if (grp != g) continue;
           table[3 * n] = i;
           table[3 * n + 1] = j;
           table[3 * n + 2] = k;

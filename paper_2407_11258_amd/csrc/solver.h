@@ -43,7 +43,8 @@ struct Layout {
   double *Gkc = nullptr;            // (kc|bd) [k][c][b][d]
   double *Zl = nullptr, *Yl = nullptr, *Wl = nullptr;   // [ij][k][b], [ij][k][b], [ij][k][l]
   double *Bvv_lp = nullptr;         // bare B_vv in the ladder precision
-  double *t2_lp;                    // t2 in the precision of the (T) products
+  double *t2_lp;                    // t2 for (T): [o][o][v][vp] in the (T) element type
+  bool t_f32 = false;               // (T) products and W in FP32
   Prec lp;                          // precision of the ladder and (T) products
   int lpt;                          // its element type: 0 double, 1 float, 2 bf16
   double *dx, *de;                  // DIIS vectors and errors [m][namp]

@@ -21,6 +21,7 @@
 
 #include "gett.h"
 #include "kernels.h"
+#include "triples.h"
 
 namespace lnocc {
 
@@ -170,14 +171,19 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   // (T) phase (aliases the CCSD scratch)
   A.off = phase;
   const int64_t nt = unique_triples(o);
+  // (T) runs FP32 products in the FP32 and BF16 modes, FP64 products otherwise;
+  // G and T carry the contracted index padded to vp (zeros beyond v)
+  L.t_f32 = L.lp != Prec::F64;
+  const int64_t tes = L.t_f32 ? 4 : 8, vp = triples_pad(v);
+  auto dwords = [](int64_t bytes) { return (bytes + 7) / 8; };
   int64_t nb = opt.triples_batch;
-  if (nb <= 0) nb = std::max<int64_t>(1, ((int64_t)2 << 30) / (8 * vvv));
+  if (nb <= 0) nb = std::max<int64_t>(1, ((int64_t)2 << 30) / (tes * vvv));
   nb = std::max<int64_t>(1, std::min<int64_t>({nb, std::max<int64_t>(nt, 1), 4096}));
   L.nb = (int)nb;
   L.ntriples = nt;
-  L.Gt = A.d(ov * vv); L.Jt = A.d(oo * ov);
-  L.W = A.d(nb * vvv);
-  L.t2_lp = (L.lp != Prec::F64) ? A.d(oovv) : nullptr;
+  L.Gt = A.d(dwords(ov * v * vp * tes)); L.Jt = A.d(dwords(oo * ov * tes));
+  L.W = A.d(dwords(nb * vvv * tes));
+  L.t2_lp = A.d(dwords(oo * v * vp * tes));
   L.tpart_elems = triples_partials_capacity(nb);
   L.tpart = A.d(L.tpart_elems);
   L.table = A.i(3 * std::max<int64_t>(nt, 1));
@@ -964,91 +970,71 @@ int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s, bool autot
   LN_TRY(dzero(acc, 8, s));
   if (L.ntriples == 0) return LNOCC_OK;
   // In the FP32 / BF16 modes the integrals and amplitudes entering W are
-  // stored in that precision and W itself in FP32; the energy sum is FP64.
-  {  // Gt[i][a][b][d] = (ai|bd)
-    GemmDesc d = DESC(ov, 1, vv, 1, L.Gt, vv, 0, 1, 0, 0.0);
-    SEG(d, X, 1, 1.0, OP(L.Bov, 1, 0, ov, 0), OP(L.Bvv, 1, 0, vv, 0));
-    d.c_type = L.lpt;
+  // stored as FP32 and W itself is FP32; the energy sum is FP64.
+  const int64_t vp = triples_pad(v), tes = L.t_f32 ? 4 : 8;
+  if (v * v * vp * tes >= ((int64_t)1 << 32) || o * v * vp >= ((int64_t)1 << 32)) {
+    note_error("(T): nvir %lld is beyond the 32-bit offsets of the W kernel", (long long)v);
+    return LNOCC_EINVAL;
+  }
+  const int ttype = L.t_f32 ? 1 : 0;
+  if (vp > v) LN_TRY(dzero(L.Gt, (size_t)(ov * v * vp * tes), s));
+  {  // Gt[i][a][b][d] = (ai|bd), d padded to vp
+    GemmDesc d = DESC(ov, 1, vv, v, L.Gt, v * vp, 0, vp, 1, 0.0);
+    SEG(d, X, 1, 1.0, OP(L.Bov, 1, 0, ov, 0), OP(L.Bvv, v, 1, vv, 0));
+    d.c_type = ttype;
     LN_TRY(gett(d, s));
   }
   {  // Jt[j][k][c][l] = (ck|jl)
     GemmDesc d = DESC(ov, v, oo, o, L.Jt, vo, o, ovo, 1, 0.0);
     SEG(d, X, 1, 1.0, OP(L.Bov, v, 1, ov, 0), OP(L.Boo, o, 1, oo, 0));
-    d.c_type = L.lpt;
+    d.c_type = ttype;
     LN_TRY(gett(d, s));
   }
-  const double *t2w = t2;
-  if (L.lp != Prec::F64) {
-    LN_TRY(convert(t2, oo * vv, L.t2_lp, L.lpt, s));
-    t2w = L.t2_lp;
-  }
-  const int wtype = L.lp == Prec::F64 ? 0 : 1;
+  LN_TRY(triples_pad_t2(t2, o, v, L.t2_lp, ttype, s));
+  const int wtype = ttype;
   LN_TRY(triples_table(L.table, o, s));
-  for (int64_t t0 = 0; t0 < L.ntriples; t0 += L.nb) {
-    const int nb = (int)std::min<int64_t>(L.nb, L.ntriples - t0);
-    const int *table = L.table + 3 * t0;
-    auto finish = [&](GemmDesc &d) {
-      d.batch = nb; d.table = table; d.c_bid = vvv; d.kind = Kind::TriplesW;
-      d.prec = L.lp; d.c_type = wtype;
-      d.tmax[0] = d.tmax[1] = d.tmax[2] = (int)(o - 1);
-    };
-    auto w_launches = [&]() -> int {
-      {  // rows (a,b), column c: P1, P3, H1, H3
-        GemmDesc d = DESC(vv, v, v, 1, L.W, vv, v, 1, 0, 0.0);
-        SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), vvv, 0, 0), OPB(OP(t2w, v, 0, 1, 0), 0, vv, ovv));
-        SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, vvv, 0), OPB(OP(t2w, v, 0, 1, 0), vv, 0, ovv));
-        SEG(d, o, 1, -1.0, OPB(OP(t2w, v, 1, vv, 0), ovv, 0, 0), OPB(OP(L.Jt, o, 0, 1, 0), 0, ovo, vo));
-        SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, ovv, 0), OPB(OP(L.Jt, o, 0, 1, 0), ovo, 0, vo));
-        finish(d);
-        LN_TRY(gett(d, s));
+  (void)autotune;
+  (void)ovv;
+  // Triples with three distinct labels take all twelve terms of W (three
+  // orientations of four).  With i = j, W is symmetric under a <-> b: the second
+  // particle and hole terms of orientation 0 are the first ones with a and b
+  // exchanged, and orientation 2 is orientation 1 with a and b exchanged, so
+  // W = Z + Z(a <-> b) with Z = the first two terms of orientation 0 plus
+  // orientation 1: half the products.  Likewise with j = k (b <-> c):
+  // Z = orientation 0 plus the first two terms of orientation 2.
+  const int64_t n0 = o * (o - 1) * (o - 2) / 6, n1 = o * (o - 1) / 2;
+  const int64_t gstart[3] = {0, n0, n0 + n1}, gcount[3] = {n0, n1, n1};
+  for (int g = 0; g < 3; ++g)
+    for (int64_t t0 = gstart[g]; t0 < gstart[g] + gcount[g]; t0 += L.nb) {
+      const int nb = (int)std::min<int64_t>(L.nb, gstart[g] + gcount[g] - t0);
+      const int *table = L.table + 3 * t0;
+      auto w = [&](int ori, int accumulate, int nterms) {
+        return triples_w(L.Gt, L.t2_lp, L.Jt, L.W, table, nb, o, v, ori, ttype, accumulate,
+                         nterms, s);
+      };
+      if (g == 0) {
+        LN_TRY(w(0, 0, 2));
+        LN_TRY(w(1, 1, 2));
+        LN_TRY(w(2, 1, 2));
+      } else if (g == 1) {
+        LN_TRY(w(0, 0, 1));
+        LN_TRY(w(1, 1, 2));
+        LN_TRY(triples_symmetrize(L.W, nb, v, 0, ttype, s));
+      } else {
+        LN_TRY(w(0, 0, 2));
+        LN_TRY(w(2, 1, 1));
+        LN_TRY(triples_symmetrize(L.W, nb, v, 1, ttype, s));
       }
-      {  // rows (a,c), column b: P2, P5, H2, H5
-        GemmDesc d = DESC(vv, v, v, 1, L.W, vv, 1, v, 0, 1.0);
-        SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), vvv, 0, 0), OPB(OP(t2w, v, 0, 1, 0), 0, ovv, vv));
-        SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, 0, vvv), OPB(OP(t2w, v, 0, 1, 0), vv, ovv, 0));
-        SEG(d, o, 1, -1.0, OPB(OP(t2w, v, 1, vv, 0), ovv, 0, 0), OPB(OP(L.Jt, o, 0, 1, 0), 0, vo, ovo));
-        SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), ovo, vo, 0));
-        finish(d);
-        LN_TRY(gett(d, s));
+      if (log_enabled() && ((t0 - gstart[g]) / L.nb) % 8 == 0) {
+        std::fprintf(stderr, "lnocc: (T) group %d triples %lld..%lld of %lld\n", g,
+                     (long long)t0, (long long)(t0 + nb), (long long)L.ntriples);
+        std::fflush(stderr);
       }
-      {  // rows (b,c), column a: P4, P6, H4, H6
-        GemmDesc d = DESC(vv, v, v, 1, L.W, v, 1, vv, 0, 1.0);
-        SEG(d, v, 1, 1.0, OPB(OP(L.Gt, vv, v, 1, 0), 0, vvv, 0), OPB(OP(t2w, v, 0, 1, 0), ovv, 0, vv));
-        SEG(d, v, 1, 1.0, OPB(OP(L.Gt, v, vv, 1, 0), 0, 0, vvv), OPB(OP(t2w, v, 0, 1, 0), ovv, vv, 0));
-        SEG(d, o, 1, -1.0, OPB(OP(t2w, v, 1, vv, 0), 0, ovv, 0), OPB(OP(L.Jt, o, 0, 1, 0), vo, 0, ovo));
-        SEG(d, o, 1, -1.0, OPB(OP(t2w, 1, v, vv, 0), 0, 0, ovv), OPB(OP(L.Jt, o, 0, 1, 0), vo, ovo, 0));
-        finish(d);
-        LN_TRY(gett(d, s));
-      }
-        return LNOCC_OK;
-    };
-    if (autotune && t0 == 0 && !dry_run()) {   // tune the W launches on the first batch
-      tune_probe_begin();
-      int st = w_launches();
-      if (tune_probe_end() > 0 && !st) {
-        for (int c = 0; c < tune_candidates() && !st; ++c) {
-          tune_candidate(c);
-          st = w_launches();
-        }
-        tune_candidate(-1);
-        tune_commit();
-      }
-      if (st) return st;
+      int64_t nparts = 0;
+      LN_TRY(triples_energy(L.W, wtype, table, nb, L.Kov, t1, in.eo, in.ev, o, v, L.tpart,
+                            L.tpart_elems, &nparts, s));
+      LN_TRY(reduce_partials(L.tpart, nparts, acc, 1, s));
     }
-    {
-      const int st = w_launches();
-      if (st) return st;
-    }
-    if (log_enabled() && (t0 / L.nb) % 8 == 0) {
-      std::fprintf(stderr, "lnocc: (T) triples %lld..%lld of %lld\n", (long long)t0,
-                   (long long)(t0 + nb), (long long)L.ntriples);
-      std::fflush(stderr);
-    }
-    int64_t nparts = 0;
-    LN_TRY(triples_energy(L.W, wtype, table, nb, L.Kov, t1, in.eo, in.ev, o, v, L.tpart,
-                          L.tpart_elems, &nparts, s));
-    LN_TRY(reduce_partials(L.tpart, nparts, acc, 1, s));
-  }
   return LNOCC_OK;
 }
 
