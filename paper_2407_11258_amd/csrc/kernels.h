@@ -77,11 +77,12 @@ hipError_t triples_table(int *table, int64_t o, hipStream_t s);
 // (T) energy of a batch of unique triples whose W tensors sit in W[nb][v][v][v].
 // table holds (i, j, k) per entry, i <= j <= k; partials[nb * tiles] per tile.
 // W element type: 0 double, 1 float
-// capacity: length of partials; a launch that would write more is refused
-// (hipErrorInvalidValue, also in validation mode).
-hipError_t triples_energy(const void *W, int wtype, const int *table, int nb, const double *Kov,
-                          const double *t1, const double *eo, const double *ev, int64_t o,
-                          int64_t v, double *partials, int64_t capacity, int64_t *nparts,
-                          hipStream_t s);
+// sym = 0: W holds W itself; sym = 1 (2): W holds Z with W(a,b,c) = Z(a,b,c) +
+// Z(b,a,c) (Z(a,b,c) + Z(a,c,b)).  capacity: length of partials; a launch that
+// would write more is refused (hipErrorInvalidValue, also in validation mode).
+hipError_t triples_energy(const void *W, int wtype, int sym, const int *table, int nb,
+                          const double *Kov, const double *t1, const double *eo,
+                          const double *ev, int64_t o, int64_t v, double *partials,
+                          int64_t capacity, int64_t *nparts, hipStream_t s);
 
 }  // namespace lnocc

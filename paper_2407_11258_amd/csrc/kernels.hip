@@ -399,7 +399,7 @@ template <typename TW>
 __global__ void k_triples_energy(const TW *__restrict__ Wall, const int *__restrict__ table,
                                  const double *__restrict__ Kov, const double *__restrict__ t1,
                                  const double *__restrict__ eo, const double *__restrict__ ev,
-                                 int64_t o, int64_t v, int tpd, double *partials) {
+                                 int64_t o, int64_t v, int tpd, int sym, double *partials) {
   __shared__ double L[6][TT * TT * TP];
   __shared__ double sm[kRedThreads / 64];
   constexpr int P[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
@@ -468,12 +468,22 @@ __global__ void k_triples_energy(const TW *__restrict__ Wall, const int *__restr
         const int x = e / (TT * TT), y = (e / TT) % TT, z = e % TT;
         const int64_t a = a0 + x, b = b0 + y, cc = c0 + z;
         if (a >= v || b >= v || cc >= v) continue;
-        const double w = Labc[(x * TT + y) * TP + z];
-        const double wbca = Lbca[(y * TT + z) * TP + x];
-        const double wcab = Lcab[(z * TT + x) * TP + y];
-        const double wacb = Lacb[(x * TT + z) * TP + y];
-        const double wbac = Lbac[(y * TT + x) * TP + z];
-        const double wcba = Lcba[(z * TT + y) * TP + x];
+        const double zabc = Labc[(x * TT + y) * TP + z];
+        const double zbca = Lbca[(y * TT + z) * TP + x];
+        const double zcab = Lcab[(z * TT + x) * TP + y];
+        const double zacb = Lacb[(x * TT + z) * TP + y];
+        const double zbac = Lbac[(y * TT + x) * TP + z];
+        const double zcba = Lcba[(z * TT + y) * TP + x];
+        // sym 1: W(a,b,c) = Z(a,b,c) + Z(b,a,c); sym 2: W(a,b,c) = Z(a,b,c) + Z(a,c,b);
+        // the six permuted values of W are then sums of the six permuted values of Z
+        double w = zabc, wbca = zbca, wcab = zcab, wacb = zacb, wbac = zbac, wcba = zcba;
+        if (sym == 1) {
+          w = zabc + zbac; wbca = zbca + zcba; wcab = zcab + zacb;
+          wacb = zacb + zcab; wbac = zbac + zabc; wcba = zcba + zbca;
+        } else if (sym == 2) {
+          w = zabc + zacb; wbca = zbca + zbac; wcab = zcab + zcba;
+          wacb = zacb + zabc; wbac = zbac + zbca; wcba = zcba + zcab;
+        }
         const double V = w + Kov[((i * v + a) * o + j) * v + b] * t1[k * v + cc] +
                          Kov[((i * v + a) * o + k) * v + cc] * t1[j * v + b] +
                          Kov[((j * v + b) * o + k) * v + cc] * t1[i * v + a];
@@ -645,10 +655,10 @@ hipError_t triples_table(int *table, int64_t o, hipStream_t s) {
   hipLaunchKernelGGL(k_triples_table, dim3(1), dim3(64), 0, s, table, (int)o);
   return hipGetLastError();
 }
-hipError_t triples_energy(const void *W, int wtype, const int *table, int nb, const double *Kov,
-                          const double *t1, const double *eo, const double *ev, int64_t o,
-                          int64_t v, double *partials, int64_t capacity, int64_t *nparts,
-                          hipStream_t s) {
+hipError_t triples_energy(const void *W, int wtype, int sym, const int *table, int nb,
+                          const double *Kov, const double *t1, const double *eo,
+                          const double *ev, int64_t o, int64_t v, double *partials,
+                          int64_t capacity, int64_t *nparts, hipStream_t s) {
   const int tpd = (int)((v + TT - 1) / TT);
   const int64_t orbits = (int64_t)tpd * (tpd + 1) * (tpd + 2) / 6;
   // small batches (large v) get more blocks per triple, so the launch fills the chip
@@ -663,10 +673,10 @@ hipError_t triples_energy(const void *W, int wtype, const int *table, int nb, co
   if (dry_run()) return hipSuccess;
   if (wtype == 1)
     hipLaunchKernelGGL(k_triples_energy<float>, dim3(per_entry, nb), dim3(kRedThreads), 0, s,
-                       (const float *)W, table, Kov, t1, eo, ev, o, v, tpd, partials);
+                       (const float *)W, table, Kov, t1, eo, ev, o, v, tpd, sym, partials);
   else
     hipLaunchKernelGGL(k_triples_energy<double>, dim3(per_entry, nb), dim3(kRedThreads), 0, s,
-                       (const double *)W, table, Kov, t1, eo, ev, o, v, tpd, partials);
+                       (const double *)W, table, Kov, t1, eo, ev, o, v, tpd, sym, partials);
   return hipGetLastError();
 }
 

@@ -1001,7 +1001,8 @@ int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s, bool autot
   // exchanged, and orientation 2 is orientation 1 with a and b exchanged, so
   // W = Z + Z(a <-> b) with Z = the first two terms of orientation 0 plus
   // orientation 1: half the products.  Likewise with j = k (b <-> c):
-  // Z = orientation 0 plus the first two terms of orientation 2.
+  // Z = orientation 0 plus the first two terms of orientation 2.  Z is what
+  // goes to memory; the energy kernel forms W from it as it reads.
   const int64_t n0 = o * (o - 1) * (o - 2) / 6, n1 = o * (o - 1) / 2;
   const int64_t gstart[3] = {0, n0, n0 + n1}, gcount[3] = {n0, n1, n1};
   for (int g = 0; g < 3; ++g)
@@ -1019,11 +1020,9 @@ int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s, bool autot
       } else if (g == 1) {
         LN_TRY(w(0, 0, 1));
         LN_TRY(w(1, 1, 2));
-        LN_TRY(triples_symmetrize(L.W, nb, v, 0, ttype, s));
       } else {
         LN_TRY(w(0, 0, 2));
         LN_TRY(w(2, 1, 1));
-        LN_TRY(triples_symmetrize(L.W, nb, v, 1, ttype, s));
       }
       if (log_enabled() && ((t0 - gstart[g]) / L.nb) % 8 == 0) {
         std::fprintf(stderr, "lnocc: (T) group %d triples %lld..%lld of %lld\n", g,
@@ -1031,7 +1030,8 @@ int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s, bool autot
         std::fflush(stderr);
       }
       int64_t nparts = 0;
-      LN_TRY(triples_energy(L.W, wtype, table, nb, L.Kov, t1, in.eo, in.ev, o, v, L.tpart,
+      // groups 1 and 2 leave Z in L.W; the energy kernel adds the exchanged partner
+      LN_TRY(triples_energy(L.W, wtype, g, table, nb, L.Kov, t1, in.eo, in.ev, o, v, L.tpart,
                             L.tpart_elems, &nparts, s));
       LN_TRY(reduce_partials(L.tpart, nparts, acc, 1, s));
     }

@@ -26,8 +26,4 @@ hipError_t triples_w(const void *G, const void *T, const void *J, void *W, const
                      int nb, int64_t o, int64_t v, int ori, int f32, int accumulate, int nterms,
                      hipStream_t s);
 
-// W[e] <- Z[e] + Z[e'] in place, e' = e with a <-> b (pair 0) or b <-> c (pair 1)
-// exchanged, for nb tensors [v][v][v].
-hipError_t triples_symmetrize(void *W, int nb, int64_t v, int pair, int f32, hipStream_t s);
-
 }  // namespace lnocc

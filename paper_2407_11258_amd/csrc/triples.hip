@@ -437,40 +437,4 @@ hipError_t triples_w(const void *G, const void *T, const void *J, void *W, const
   return e;
 }
 
-// W <- Z + Z with two virtual labels exchanged (pair = 0: a <-> b, 1: b <-> c),
-// in place, for nb tensors [v][v][v].  Each unordered pair of positions is
-// handled by one thread.
-template <typename E>
-__global__ void k_pair_symmetrize(E *W, int64_t v, int pair) {
-  E *Z = W + (int64_t)blockIdx.y * v * v * v;
-  const int64_t n = v * v * v;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = e % v, b = (e / v) % v, a = e / (v * v);
-    int64_t x, y;   // the two exchanged labels of this position
-    int64_t f;      // offset of the partner position
-    if (pair == 0) { x = a; y = b; f = (b * v + a) * v + c; }
-    else { x = b; y = c; f = (a * v + c) * v + b; }
-    if (x > y) continue;
-    if (x == y) { Z[e] = Z[e] + Z[e]; continue; }
-    const E s = Z[e] + Z[f];
-    Z[e] = s;
-    Z[f] = s;
-  }
-}
-
-hipError_t triples_symmetrize(void *W, int nb, int64_t v, int pair, int f32, hipStream_t s) {
-  if (nb < 1 || nb > 65535 || (pair != 0 && pair != 1)) return hipErrorInvalidValue;
-  if (!region_ok(W, (size_t)(nb * v * v * v * (f32 ? 4 : 8)))) {
-    note_error("(T) symmetrization leaves its buffer; not launched");
-    return hipErrorInvalidValue;
-  }
-  if (dry_run()) return hipSuccess;
-  const int64_t n = v * v * v;
-  const dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 2048), (unsigned)nb);
-  if (f32) hipLaunchKernelGGL(k_pair_symmetrize<float>, grid, dim3(256), 0, s, (float *)W, v, pair);
-  else hipLaunchKernelGGL(k_pair_symmetrize<double>, grid, dim3(256), 0, s, (double *)W, v, pair);
-  return hipGetLastError();
-}
-
 }  // namespace lnocc
