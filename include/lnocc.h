@@ -192,6 +192,33 @@ int lnocc_fragment_ccsd_static(lnocc_fragment_t *f, const lnocc_options_t *opt);
  * status. */
 int lnocc_fragment_triples(lnocc_fragment_t *f, const lnocc_options_t *opt);
 
+/* ---- fragment pair energies and their projection (Sec. II.B) ---------------
+ * From the amplitudes in f->t1 / f->t2 (normally a converged lnocc_fragment_ccsd
+ * solve), the occupied pair matrices of the fragment energy
+ *   pair_ccsd[i][i'] = sum_{j a b} tau_ij^ab (2 (i'a|jb) - (i'b|ja)),
+ *                      tau = t2 + t1 t1                                  (Eqs. 9, 13)
+ *   pair_t[i][i']    = -1/3 sum_{j k a b c} (4 w_ijk^abc + w_ijk^bca + w_ijk^cab)
+ *                                           (v_i'jk^abc - v_i'jk^cba)    (Eq. 16)
+ * with w = W / sqrt(-Delta_ijk), v_i'jk = V_i'jk / sqrt(-Delta_i'jk) and W, V,
+ * Delta of SI Sec. S1, and, when U != NULL, the projected energy of each of the
+ * nlo localized orbitals alpha:
+ *   proj[alpha] = sum_{i i'} U[i][alpha] E[i][i'] U[i'][alpha]           (Eqs. 12, 15)
+ * so that the fragment energy is the sum of proj over the fragment's LOs.  All
+ * arrays are device FP64: pair_ccsd, pair_t [nocc][nocc] (out; pair_t = NULL
+ * skips the triples part), U [nocc][nlo] (in, row i = occupied orbital i),
+ * proj_ccsd, proj_t [nlo] (out).  The traces (the canonical energies of Eq. 7
+ * and of Eq. 16 summed at i = i') go to f->e_ccsd and f->e_t.  Every product
+ * runs in FP64 whatever opt->precision says.  The pair (T) part forms the W
+ * tensors of all o ordered triples (i, j, k) for each pair j <= k, about three
+ * times the work of lnocc_fragment_triples.  The workspace must hold
+ * lnocc_pair_workspace_bytes() bytes (about 3 nocc nvir^3 doubles more than
+ * the solve's). */
+int lnocc_pair_workspace_bytes(const lnocc_fragment_t *f, const lnocc_options_t *opt,
+                               size_t *bytes);
+int lnocc_fragment_pair_energies(lnocc_fragment_t *f, const lnocc_options_t *opt,
+                                 double *pair_ccsd, double *pair_t, const double *U, int32_t nlo,
+                                 double *proj_ccsd, double *proj_t);
+
 /* CCSD residuals R1[i][a] = <Phi_i^a| e^{-T} H e^{T} |HF> and
  * R2[i][j][a][b] = <Phi_{i alpha j beta}^{a alpha b beta}| e^{-T} H e^{T} |HF>
  * of the fragment Hamiltonian (Eq. 10) at the amplitudes in f->t1 / f->t2,

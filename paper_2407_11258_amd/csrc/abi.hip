@@ -16,6 +16,7 @@
 #include "gett.h"
 #include "solver.h"
 #include "mlp.h"
+#include "pairs.h"
 
 using namespace lnocc;
 
@@ -373,6 +374,83 @@ int lnocc_fragment_ccsd_static(lnocc_fragment_t *f, const lnocc_options_t *opt_i
   f->residual = out.residual;
   f->n_iter = out.n_iter;
   f->guess_used = out.guess_used;
+  return finish(f, st);
+}
+
+int lnocc_pair_workspace_bytes(const lnocc_fragment_t *f, const lnocc_options_t *opt,
+                               size_t *bytes) {
+  if (bytes) *bytes = 0;
+  if (!f || !bytes) return LNOCC_EINVAL;
+  int st = check_options(opt);
+  if (!st) st = check_sizes(f);
+  if (st) return st;
+  lnocc_options_t o64 = *opt;
+  o64.precision = LNOCC_FP64;
+  Layout L;
+  plan_layout(dims_of(f), o64, nullptr, L);
+  plan_pair_layout(dims_of(f), nullptr, L, *bytes);
+  return LNOCC_OK;
+}
+
+int lnocc_fragment_pair_energies(lnocc_fragment_t *f, const lnocc_options_t *opt,
+                                 double *pair_ccsd, double *pair_t, const double *U, int32_t nlo,
+                                 double *proj_ccsd, double *proj_t) {
+  clear_error();
+  if (!f || !opt) return LNOCC_EINVAL;
+  int st = check_sizes(f);
+  if (!st) st = check_options(opt);
+  if (!st) st = check_pointers(f, true);
+  if (!st && !pair_ccsd) st = LNOCC_EINVAL;
+  if (!st && U && (nlo < 1 || !proj_ccsd || (pair_t && !proj_t))) st = LNOCC_EINVAL;
+  if (st) return finish(f, st);
+  lnocc_options_t o64 = *opt;
+  o64.precision = LNOCC_FP64;
+  Layout L;
+  size_t need = 0;
+  plan_layout(dims_of(f), o64, nullptr, L);
+  plan_pair_layout(dims_of(f), nullptr, L, need);
+  if (!opt->workspace) return finish(f, LNOCC_ENOMEM);
+  if (((uintptr_t)opt->workspace) % 256) return finish(f, LNOCC_EINVAL);
+  if (opt->workspace_bytes < need) return finish(f, LNOCC_ENOMEM);
+  plan_layout(dims_of(f), o64, (char *)opt->workspace, L);
+  plan_pair_layout(dims_of(f), (char *)opt->workspace, L, need);
+  hipStream_t s = (hipStream_t)opt->stream;
+  st = check_spectrum(f, s);
+  if (st) return finish(f, st);
+  const size_t o = f->nocc, v = f->nvir, X = f->naux, n = o + v;
+  std::vector<Region> regions{
+      Region{opt->workspace, opt->workspace_bytes}, Region{f->B, X * n * n * 8},
+      Region{f->eps_occ, o * 8}, Region{f->eps_vir, v * 8}, Region{f->t1, o * v * 8},
+      Region{f->t2, o * o * v * v * 8}, Region{pair_ccsd, o * o * 8},
+      Region{pair_t, pair_t ? o * o * 8 : 0}, Region{U, U ? o * (size_t)nlo * 8 : 0},
+      Region{proj_ccsd, U ? (size_t)nlo * 8 : 0}, Region{proj_t, U && pair_t ? (size_t)nlo * 8 : 0}};
+  install_regions(regions.data(), (int)regions.size());
+  install_splitk_scratch(L.splitk, (size_t)L.splitk_elems);
+  st = setup_fragment(L, f->B, f->eps_occ, f->eps_vir, false, s);
+  if (!st)
+    st = pair_energies(L, f->t1, f->t2, f->eps_occ, f->eps_vir, pair_ccsd, pair_t, U, nlo,
+                       proj_ccsd, proj_t, s);
+  // traces (the canonical energies, Eq. 7 and Eq. 16 at i = i') for the host outputs
+  if (!st && !dry_run()) {
+    std::vector<double> h(o * o);
+    if (hipMemcpyAsync(h.data(), pair_ccsd, o * o * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      st = LNOCC_EDEVICE;
+    double tr = 0.0;
+    for (size_t i = 0; i < o; ++i) tr += h[i * o + i];
+    f->e_ccsd = tr;
+    if (!st && pair_t) {
+      if (hipMemcpyAsync(h.data(), pair_t, o * o * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        st = LNOCC_EDEVICE;
+      tr = 0.0;
+      for (size_t i = 0; i < o; ++i) tr += h[i * o + i];
+      f->e_t = tr;
+    }
+  }
+  if (dsync(s) != hipSuccess && !st) st = LNOCC_EDEVICE;
+  install_regions(nullptr, 0);
+  install_splitk_scratch(nullptr, 0);
   return finish(f, st);
 }
 

@@ -14,6 +14,14 @@ namespace lnocc {
 
 struct Dims { int64_t o, v, X; };
 
+// Scratch of the pair energies (pairs.hip), FP64.
+struct PairLayout {
+  double *Gt = nullptr, *Jt = nullptr, *T = nullptr;   // (ai|bd), (ck|jl), t2 for the W kernel
+  int *table = nullptr;             // (i, j, k) for every i and pair j <= k
+  double *W = nullptr, *Y = nullptr, *Z = nullptr;     // [o][v][v][v] for one pair (j, k)
+  double *tau = nullptr, *Lx = nullptr;                // [o][o][v][v]
+};
+
 // Device buffers carved out of the caller's workspace.  The (T) buffers alias
 // the CCSD scratch, which is dead once the amplitudes have converged.
 struct Layout {
@@ -60,6 +68,8 @@ struct Layout {
   int nb;
   int64_t ntriples;
   size_t bytes;
+  size_t phase_off = 0;             // end of the common part (start of the phase scratch)
+  PairLayout pairs;
 };
 
 struct Inputs {

@@ -117,6 +117,7 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L.splitk_elems = std::max<int64_t>({(int64_t)1 << 22, 64 * vv, 4 * oovv});
   L.splitk = A.d(L.splitk_elems);
   const size_t phase = A.off;
+  L.phase_off = phase;
   // CCSD phase
   L.diis_m = std::max(1, (int)opt.diis_space);
   const int64_t N = ov + oovv;

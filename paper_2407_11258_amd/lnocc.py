@@ -84,7 +84,7 @@ KERNEL_CLASS_NAMES = ("other", "ladder_build", "ladder_contract", "triples_w", "
 EXPORTS = ("lnocc_default_options", "lnocc_status_string", "lnocc_last_error",
            "lnocc_workspace_bytes",
            "lnocc_fragment_ccsd", "lnocc_fragment_ccsd_static", "lnocc_fragment_triples",
-           "lnocc_ccsd_residuals",
+           "lnocc_ccsd_residuals", "lnocc_pair_workspace_bytes", "lnocc_fragment_pair_energies",
            "lnocc_batch_solve", "lnocc_contract", "lnocc_profile_enable",
            "lnocc_profile_collect", "lnocc_set_validation_mode", "lnocc_mlp_workspace_bytes",
            "lnocc_mlp_samples", "lnocc_mlp_init", "lnocc_mlp_predict", "lnocc_mlp_loss_grad",
@@ -114,6 +114,11 @@ def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
     for name in ("lnocc_fragment_ccsd", "lnocc_fragment_ccsd_static", "lnocc_fragment_triples"):
         getattr(lib, name).argtypes = [FP, OP]
         getattr(lib, name).restype = C.c_int
+    lib.lnocc_pair_workspace_bytes.argtypes = [FP, OP, C.POINTER(C.c_size_t)]
+    lib.lnocc_pair_workspace_bytes.restype = C.c_int
+    lib.lnocc_fragment_pair_energies.argtypes = [FP, OP, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                 C.c_int32, C.c_void_p, C.c_void_p]
+    lib.lnocc_fragment_pair_energies.restype = C.c_int
     lib.lnocc_ccsd_residuals.argtypes = [FP, OP, C.c_void_p, C.c_void_p]
     lib.lnocc_ccsd_residuals.restype = C.c_int
     lib.lnocc_batch_solve.argtypes = [FP, C.c_int32, OP]
@@ -192,6 +197,19 @@ LNOCC_STATIC_SCRATCH_BYTES = 64 << 20
 
 def lnocc_fragment_ccsd_static(frag: lnocc_fragment_t, opt: lnocc_options_t) -> int:
     return _lib.lnocc_fragment_ccsd_static(C.byref(frag), C.byref(opt))
+
+
+def lnocc_pair_workspace_bytes(frag: lnocc_fragment_t, opt: lnocc_options_t) -> tuple[int, int]:
+    out = C.c_size_t(0)
+    st = _lib.lnocc_pair_workspace_bytes(C.byref(frag), C.byref(opt), C.byref(out))
+    return st, out.value
+
+
+def lnocc_fragment_pair_energies(frag: lnocc_fragment_t, opt: lnocc_options_t, pair_ccsd: int,
+                                 pair_t: int | None, U: int | None, nlo: int,
+                                 proj_ccsd: int | None, proj_t: int | None) -> int:
+    return _lib.lnocc_fragment_pair_energies(C.byref(frag), C.byref(opt), pair_ccsd, pair_t, U,
+                                             nlo, proj_ccsd, proj_t)
 
 
 def lnocc_fragment_triples(frag: lnocc_fragment_t, opt: lnocc_options_t) -> int:

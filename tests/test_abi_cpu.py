@@ -163,6 +163,28 @@ def test_triples_partials_fit_every_batch(validation_mode, precision):
                                                                     L.lnocc_last_error())
 
 
+@pytest.mark.parametrize("o,v,X", [(4, 20, 72), (3, 13, 40), (6, 45, 100), (1, 5, 9)])
+def test_pair_energy_launches_stay_in_bounds(validation_mode, o, v, X):
+    """Every launch of the pair energies (CCSD and (T) pair matrices, projection)
+    stays inside the workspace and the caller's arrays; a workspace one byte short
+    is refused before anything runs."""
+    opt = L.make_options()
+    f = _fake_fragment(o, v, X)
+    st, nbytes = L.lnocc_pair_workspace_bytes(f, opt)
+    assert st == L.LNOCC_OK
+    assert nbytes >= L.lnocc_workspace_bytes([f], opt)[1]
+    opt.workspace, opt.workspace_bytes = 1 << 45, nbytes
+    out = 1 << 46
+    nlo = o + 2
+    args = (out, out + (1 << 30), out + (2 << 30), nlo, out + (3 << 30), out + (4 << 30))
+    assert L.lnocc_fragment_pair_energies(f, opt, *args) == L.LNOCC_OK, L.lnocc_last_error()
+    assert L.lnocc_fragment_pair_energies(f, opt, out, None, None, 0, None, None) == L.LNOCC_OK
+    opt.workspace_bytes = nbytes - 1
+    assert L.lnocc_fragment_pair_energies(f, opt, *args) == L.LNOCC_ENOMEM
+    opt.workspace_bytes = nbytes
+    assert L.lnocc_fragment_pair_energies(f, opt, out, None, out + (2 << 30), 0, out, None) == L.LNOCC_EINVAL
+
+
 def test_static_scratch_entry_point(validation_mode):
     """The no-allocation variant ignores the caller's workspace, runs the same
     launch sequence inside its static array and refuses a fragment that needs

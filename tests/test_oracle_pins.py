@@ -173,3 +173,94 @@ def test_pins_catch_planted_mistakes(monkeypatch):
         m.setattr(tr, "_perm", lambda X, src: X)            # permutations of P_ijk^abc dropped
         eb = brute.triples_energy(B, f.eps_occ, f.eps_vir, t1, t2)
         assert abs(tr.e_triples_full(B, f.eps_occ, f.eps_vir, t1, t2) - eb) > 1e-4
+
+
+# ------------------------------------------------------------ pair energies
+from oracle import pairs as opr  # noqa: E402
+
+
+def _separable_union(sA, sB, scale=3.0):
+    """Two non-interacting fragments as one: block-diagonal DF factors over
+    disjoint orbital and auxiliary blocks (occupied orbitals of both first)."""
+    fA, fB = make_fragment(*sA), make_fragment(*sB)
+    oA, vA, XA = sA[:3]
+    oB, vB, XB = sB[:3]
+    o, v, X = oA + oB, vA + vB, XA + XB
+    n = o + v
+    idxA = list(range(oA)) + [o + a for a in range(vA)]
+    idxB = [oA + i for i in range(oB)] + [o + vA + a for a in range(vB)]
+    B = np.zeros((X, n, n))
+    B[np.ix_(range(XA), idxA, idxA)] = scale * fA.B
+    B[np.ix_(range(XA, X), idxB, idxB)] = scale * fB.B
+    eo = np.concatenate([fA.eps_occ, fB.eps_occ])
+    ev = np.concatenate([fA.eps_vir, fB.eps_vir])
+    return B, eo, ev, (scale * fA.B, fA.eps_occ, fA.eps_vir), (scale * fB.B, fB.eps_occ, fB.eps_vir)
+
+
+def test_pair_matrix_traces_are_the_energies():
+    """Tr E = Eq. 7 energy and Tr E_T = the (T) energy of the triples module (both
+    pinned above by the determinant-space definitions)."""
+    f = make_fragment(3, 5, 16, 41)
+    B = 3.0 * f.B
+    t1, t2 = _random_amplitudes(3, 5, 42)
+    E = opr.ccsd_pair_matrix(B, 3, t1, t2)
+    assert abs(np.trace(E) - cc.energy(B, 3, t1, t2)) < 1e-13
+    ET = opr.triples_pair_matrix(B, f.eps_occ, f.eps_vir, t1, t2)
+    assert abs(np.trace(ET) - tr.e_triples_full(B, f.eps_occ, f.eps_vir, t1, t2)) < 1e-13
+    # both pair matrices have off-diagonal weight (the projection is not the trace)
+    assert np.abs(E - np.diag(np.diag(E))).max() > 1e-3 * np.abs(E).max()
+    assert np.abs(ET - np.diag(np.diag(ET))).max() > 1e-3 * np.abs(ET).max()
+
+
+def test_projection_over_all_fragments_is_exact():
+    """With LOs spanning the occupied space (a random orthogonal U, Eq. 5), the
+    projected energies summed over every fragment of any partition equal the
+    canonical energy (the exactness of Eqs. 7-9 and 14-15)."""
+    f = make_fragment(4, 5, 18, 43)
+    B = 3.0 * f.B
+    t1, t2 = _random_amplitudes(4, 5, 44)
+    rng = np.random.default_rng(45)
+    U, _ = np.linalg.qr(rng.standard_normal((4, 4)))
+    E = opr.ccsd_pair_matrix(B, 4, t1, t2)
+    ET = opr.triples_pair_matrix(B, f.eps_occ, f.eps_vir, t1, t2)
+    for frags in ([[0, 1], [2, 3]], [[0], [1, 2, 3]], [[3, 1], [0], [2]]):
+        eF = [opr.project(E, U)[F].sum() for F in frags]
+        tF = [opr.project(ET, U)[F].sum() for F in frags]
+        assert abs(sum(eF) - cc.energy(B, 4, t1, t2)) < 1e-13
+        assert abs(sum(tF) - tr.e_triples_full(B, f.eps_occ, f.eps_vir, t1, t2)) < 1e-13
+    # a fragment alone is not the whole: the projection depends on U
+    assert abs(opr.project(E, U)[0] - E[0, 0]) > 1e-6
+
+
+def test_pair_matrices_of_non_interacting_fragments():
+    """Two non-interacting fragments solved as one system: the converged
+    amplitudes do not couple them, so the pair matrices are block diagonal and
+    each block is the pair matrix of the fragment solved alone."""
+    B, eo, ev, fa, fb = _separable_union((2, 3, 10, 51), (2, 4, 12, 52))
+    r = cc.ccsd(B, eo, ev, conv_tol=1e-11)
+    ra = cc.ccsd(*fa, conv_tol=1e-11)
+    rb = cc.ccsd(*fb, conv_tol=1e-11)
+    assert r.converged and ra.converged and rb.converged
+    E = opr.ccsd_pair_matrix(B, 4, r.t1, r.t2)
+    ET = opr.triples_pair_matrix(B, eo, ev, r.t1, r.t2)
+    EA = opr.ccsd_pair_matrix(fa[0], 2, ra.t1, ra.t2)
+    EB = opr.ccsd_pair_matrix(fb[0], 2, rb.t1, rb.t2)
+    ETA = opr.triples_pair_matrix(*fa, ra.t1, ra.t2)
+    ETB = opr.triples_pair_matrix(*fb, rb.t1, rb.t2)
+    for M, MA, MB in ((E, EA, EB), (ET, ETA, ETB)):
+        assert np.abs(M[:2, 2:]).max() < 1e-10 and np.abs(M[2:, :2]).max() < 1e-10
+        np.testing.assert_allclose(M[:2, :2], MA, atol=1e-10)
+        np.testing.assert_allclose(M[2:, 2:], MB, atol=1e-10)
+    assert np.abs(EA - np.diag(np.diag(EA))).max() > 1e-8
+
+
+def test_pair_pins_catch_planted_mistakes():
+    """A swapped exchange sign or a dropped scaling of v by Delta_i'jk breaks the
+    pins above."""
+    f = make_fragment(3, 5, 16, 41)
+    B = 3.0 * f.B
+    t1, t2 = _random_amplitudes(3, 5, 42)
+    g = cc.ovov(B, 3)
+    tau = t2 + np.einsum("ia,jb->ijab", t1, t1)
+    wrong = np.einsum("ijab,kajb->ik", tau, 2.0 * g + g.transpose(0, 3, 2, 1))
+    assert abs(np.trace(wrong) - cc.energy(B, 3, t1, t2)) > 1e-6
