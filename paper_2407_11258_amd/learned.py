@@ -156,6 +156,9 @@ def main() -> int:
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lr-final", type=float, default=2e-5)
     ap.add_argument("--conv-tol", type=float, default=1e-7)
+    ap.add_argument("--final-tol", type=float, default=1e-10,
+                    help="both solves then continue from where they stopped to this step "
+                         "tolerance; their energies there are the final energies compared")
     ap.add_argument("--shape", default="16,160,528")
     ap.add_argument("--out", default="")
     ap.add_argument("--load", default="", help="model file written by --out: skips the "
@@ -220,11 +223,15 @@ def main() -> int:
             torch.cuda.synchronize()
             out[name] = (r, time.perf_counter() - t1)
         (a, ta), (b, tb) = out["mp2"], out["mlp"]
+        fin = [L.solve(*d, conv_tol=args.final_tol, do_triples=False, t1=x.t1, t2=x.t2,
+                       guess=L.LNOCC_GUESS_USER) for x in (a, b)]
         rows.append({"seed": 200000 + k, "iters_mp2": a.n_iter, "iters_mlp": b.n_iter,
                      "s_mp2": ta, "s_mlp": tb, "guess_used": b.guess_used,
-                     "d_e_ccsd": b.e_ccsd - a.e_ccsd, "status": [a.status, b.status]})
+                     "d_e_ccsd": b.e_ccsd - a.e_ccsd,
+                     "d_e_ccsd_final": fin[1].e_ccsd - fin[0].e_ccsd,
+                     "status": [a.status, b.status, fin[0].status, fin[1].status]})
         log(f"held-out {k}: iterations {a.n_iter} (MP2 start) vs {b.n_iter} (learned), "
-            f"dE {b.e_ccsd - a.e_ccsd:.1e}")
+            f"dE {b.e_ccsd - a.e_ccsd:.1e}, final dE {fin[1].e_ccsd - fin[0].e_ccsd:.1e}")
     pool.shutdown()
     mean = lambda key: float(np.mean([r[key] for r in rows])) if rows else None   # noqa: E731
     summary = {
@@ -238,6 +245,9 @@ def main() -> int:
         "mean_iters_mp2": mean("iters_mp2"), "mean_iters_mlp": mean("iters_mlp"),
         "mean_seconds_mp2": mean("s_mp2"), "mean_seconds_mlp": mean("s_mlp"),
         "max_abs_d_e_ccsd": float(max(abs(r["d_e_ccsd"]) for r in rows)) if rows else None,
+        "final_tol": args.final_tol,
+        "max_abs_d_e_ccsd_final": (float(max(abs(r["d_e_ccsd_final"]) for r in rows))
+                                   if rows else None),
         "fallbacks": int(sum(r["guess_used"] != L.LNOCC_GUESS_MLP for r in rows)),
         "rows": rows,
     }

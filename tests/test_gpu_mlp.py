@@ -249,3 +249,36 @@ def test_learned_start_on_held_out_fragments():
         it_mp2.append(a.n_iter)
         it_mlp.append(b.n_iter)
     assert np.mean(it_mlp) <= np.mean(it_mp2) + 1
+
+
+def test_learned_start_final_energies_at_config_size():
+    """Learned-guess workload shape (nocc 16, nvir 160, naux 528): solves from the
+    MP2 start and from the learned start stop at the step tolerance 1e-7 (where
+    iterations are counted), then both continue from where they stopped to
+    1e-10.  The final energies of the two starts agree within 1e-8 Eh: the CCSD
+    equations, not the start, decide the result."""
+    say("learned start at 16/160/528: final energies")
+    o, v, X = 16, 160, 528
+    train = [fragment_tensors(make_fragment(o, v, X, 100000 + k), DEV) for k in range(3)]
+    Xs, Ys, _ = collect_samples(train, per_fragment=1 << 16, seed=1, precision="fp32",
+                                conv_tol=1e-8)
+    del train
+    model = LearnedGuess(DEV)
+    model.init(Xs, Ys, seed=0)
+    model.train(Xs, Ys, steps=300, batch=16384, lr=1e-3, lr_final=2e-5, seed=2)
+    for k in range(2):
+        d = fragment_tensors(make_fragment(o, v, X, 200000 + k), DEV)
+        runs = {}
+        for name, kw in (("mp2", {}), ("mlp", {"guess": L.LNOCC_GUESS_MLP, "mlp": model.blob})):
+            r = L.solve(*d, conv_tol=1e-7, do_triples=False, precision="fp32", **kw)
+            assert r.status == L.LNOCC_OK, L.lnocc_last_error()
+            t = L.solve(*d, conv_tol=1e-10, do_triples=False, t1=r.t1, t2=r.t2,
+                        guess=L.LNOCC_GUESS_USER)
+            assert t.status == L.LNOCC_OK
+            runs[name] = (r, t)
+        (a, at), (b, bt) = runs["mp2"], runs["mlp"]
+        say(f"  fragment {k}: iterations {a.n_iter} vs {b.n_iter} (guess {b.guess_used}); "
+            f"dE at 1e-7 {b.e_ccsd - a.e_ccsd:.1e}, final dE {bt.e_ccsd - at.e_ccsd:.1e}")
+        assert abs(bt.e_ccsd - at.e_ccsd) < 1e-8
+        assert abs(b.e_ccsd - a.e_ccsd) < 1e-6
+
