@@ -10,9 +10,11 @@ from .fragments import (
     batch_shapes,
     CONFIG_SHAPES,
     random_amplitudes,
+    System,
+    make_system,
     BATCH_ORACLE_SUBSET,
     LARGE_TRIPLES_SHAPE,
 )
 
-__all__ = ["Fragment", "make_fragment", "batch_shapes", "CONFIG_SHAPES", "random_amplitudes",
+__all__ = ["Fragment", "make_fragment", "batch_shapes", "CONFIG_SHAPES", "random_amplitudes", "System", "make_system",
            "BATCH_ORACLE_SUBSET", "LARGE_TRIPLES_SHAPE"]

@@ -104,3 +104,64 @@ BATCH_ORACLE_SUBSET = (20, 48, 31, 51, 53, 4, 49, 26)
 # amplitude seed).
 LARGE_TRIPLES_SHAPE = (6, 400, 1300, 4, 44)
 
+
+
+@dataclasses.dataclass
+class System:
+    """A whole (Gamma-point supercell) system upstream of the fragment problems:
+    canonical orbital energies, AO-basis DF factors, canonical MO coefficients
+    and the LO coefficients of its fragments."""
+    nocc: int
+    nvir: int
+    naux: int
+    Lao: np.ndarray      # [naux, n, n] AO-basis DF factors, symmetric in (mu, nu)
+    C: np.ndarray        # [n, n] canonical MO coefficients (orthogonal), occupied first
+    eps_occ: np.ndarray  # [nocc] ascending
+    eps_vir: np.ndarray  # [nvir] ascending
+    U_occ: np.ndarray    # [nocc, nlo] LO coefficients on the occupied orbitals
+    U_vir: np.ndarray    # [nvir, nlo] LO coefficients on the virtual orbitals (zero for
+                         # LOs inside the occupied space)
+    fragments: list      # list of lists of LO indices
+
+    @property
+    def n(self) -> int:
+        return self.nocc + self.nvir
+
+    @property
+    def B(self) -> np.ndarray:
+        """DF factors in the canonical MO basis."""
+        return np.einsum("Pmn,mp,nq->Ppq", self.Lao, self.C, self.C, optimize=True)
+
+
+def make_system(nocc: int, nvir: int, naux: int, seed: int, nlo_vir: int = 0,
+                nfrag: int = 2) -> System:
+    """Seeded synthetic system.  rng = default_rng(seed); draws in this order:
+    Z ~ N(0,1) (naux, n, n) for L = 0.1 e^{-|mu-nu|/8} e^{-3P/naux} Z symmetrized in
+    (mu, nu); M ~ N(0,1) (n, n), C = Q of its QR factorization (columns occupied
+    first); eps_occ ~ U[-1.2,-0.4], eps_vir ~ U[0.3,4.0] sorted; R ~ N(0,1)
+    (nlo, nlo), O = Q of its QR (nlo = nocc + nlo_vir); S ~ N(0,1) (nvir, nlo_vir),
+    Vs = Q of its QR.  LOs: U_occ = O[:nocc], U_vir = Vs O[nocc:] (rows of U_occ are
+    orthonormal, so the LOs span the occupied space, Eq. 5; nlo_vir > 0 gives LOs
+    that also reach into nlo_vir virtual directions).  Fragments: the LOs dealt
+    round-robin into nfrag groups."""
+    n = nocc + nvir
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal((naux, n, n))
+    p = np.arange(n)
+    L = Z * (0.1 * np.exp(-np.abs(p[:, None] - p[None, :]) / 8.0))[None]
+    L *= np.exp(-3.0 * np.arange(naux) / naux)[:, None, None]
+    L = 0.5 * (L + L.transpose(0, 2, 1))
+    C, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    eps_occ = np.sort(rng.uniform(-1.2, -0.4, nocc))
+    eps_vir = np.sort(rng.uniform(0.3, 4.0, nvir))
+    nlo = nocc + nlo_vir
+    O, _ = np.linalg.qr(rng.standard_normal((nlo, nlo)))
+    U_occ = np.ascontiguousarray(O[:nocc])
+    if nlo_vir > 0:
+        Vs, _ = np.linalg.qr(rng.standard_normal((nvir, nlo_vir)))
+        U_vir = Vs @ O[nocc:]
+    else:
+        U_vir = np.zeros((nvir, nlo))
+    frags = [list(range(f, nlo, nfrag)) for f in range(nfrag)]
+    return System(nocc, nvir, naux, np.ascontiguousarray(L), C, eps_occ, eps_vir, U_occ,
+                  np.ascontiguousarray(U_vir), frags)
