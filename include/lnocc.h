@@ -243,6 +243,86 @@ int lnocc_ccsd_residuals(lnocc_fragment_t *f, const lnocc_options_t *opt,
  * fragments are done. */
 int lnocc_batch_solve(lnocc_fragment_t *f, int32_t nfrag, const lnocc_options_t *opt);
 
+/* ---- local active space of a fragment (Sec. II.C-E) ------------------------
+ * The whole system the fragments come from, device FP64:
+ *   Lao     [naux][n][n] DF factors in the AO basis, (mu nu|la si) =
+ *           sum_P Lao[P][mu][nu] Lao[P][la][si], symmetric in (mu, nu);
+ *   C       [n][n] canonical MO coefficients (row = AO, column = MO,
+ *           occupied first, orthonormal in the metric Lao is given in);
+ *   eps_occ [nocc], eps_vir [nvir] canonical orbital energies (Eq. 11 is
+ *           diagonal in this basis).  n = nocc + nvir. */
+typedef struct lnocc_system_t {
+  int32_t nocc, nvir, naux, reserved0;
+  const double *Lao, *C, *eps_occ, *eps_vir;
+} lnocc_system_t;
+
+/* One fragment's active space.  In: U_occ [nocc][nlo] (row i = canonical
+ * occupied orbital i, column = one of the fragment's nlo LOs), U_vir
+ * [nvir][nlo] or NULL (LOs with components in the virtual space), the
+ * thresholds eta_occ, eta_vir >= 0 of Eq. 26 and cbno (0: the densities of
+ * Eq. 20 with one internal occupied index; 1: the cluster-specific densities
+ * of Eq. 28).  Steps: internal orbitals = left singular vectors of U with
+ * non-zero singular values (Eqs. 18-19; eigenvalues of U U^T above 1e-10
+ * max(1, largest)), made semi-canonical; MP1 amplitudes with the internal
+ * orbital energies as f_{i_F i_F} (Eqs. 21-23); the densities, diagonalized
+ * inside the external spaces (Eqs. 24-25); LNOs with |lambda| >= eta kept
+ * (Eq. 26); internal orbitals plus kept LNOs made semi-canonical.
+ * Out (device, caller-allocated): C_occ [nocc][nocc] and C_vir [nvir][nvir]
+ * (column c < n_occ / n_vir = active orbital c on the canonical orbitals, in
+ * ascending order of its orbital energy), eps_occ [nocc] / eps_vir [nvir]
+ * (first n_occ / n_vir entries), lambda_occ [nocc] / lambda_vir [nvir] (may be
+ * NULL; the first nocc - n_int_occ / nvir - n_int_vir entries hold every
+ * external eigenvalue by descending |lambda|), U_act [nocc][nlo] (may be
+ * NULL; rows c < n_occ: the LOs on the active occupied orbitals,
+ * U_act[c][alpha] = sum_i C_occ[i][c] U_occ[i][alpha], the U that
+ * lnocc_fragment_pair_energies projects with).  Out (host): n_occ, n_vir (the
+ * active sizes) and n_int_occ, n_int_vir (the internal ranks).  Orbitals are
+ * defined up to sign (and up to rotations inside degenerate eigenspaces).
+ * The workspace must hold lnocc_local_space_workspace_bytes(sys, nlo, cbno)
+ * bytes, 256-byte aligned.  Errors: EINVAL for NULL arrays, sizes <= 0,
+ * nocc or nvir above 2048 (the eigensolver's limit), negative or non-finite
+ * eta; ENOMEM for a short workspace. */
+typedef struct lnocc_local_space_t {
+  const double *U_occ, *U_vir;
+  int32_t nlo, cbno;
+  double eta_occ, eta_vir;
+  double *C_occ, *eps_occ, *C_vir, *eps_vir, *lambda_occ, *lambda_vir, *U_act;
+  int32_t n_occ, n_vir, n_int_occ, n_int_vir;
+} lnocc_local_space_t;
+
+int lnocc_local_space_workspace_bytes(const lnocc_system_t *sys, int32_t nlo, int32_t cbno,
+                                      size_t *bytes);
+int lnocc_local_space(const lnocc_system_t *sys, lnocc_local_space_t *sp, void *workspace,
+                      size_t workspace_bytes, void *stream);
+
+/* DF factors of the local Hamiltonian (Eq. 27b) over the active orbitals
+ * C_occ (first n_occ columns of a [nocc][nocc] array) and C_vir (first n_vir
+ * columns of a [nvir][nvir] array), as lnocc_local_space returns them:
+ *   B[P][p][q] = sum_{mu nu} Lao[P][mu][nu] Ca[mu][p] Ca[nu][q],
+ *   Ca = [C[:, :nocc] C_occ | C[:, nocc:] C_vir],
+ * written to B [naux][na][na], na = n_occ + n_vir, occupied first: the B of
+ * lnocc_fragment_t, with the eps_occ / eps_vir of the active space. */
+int lnocc_local_hamiltonian_workspace_bytes(const lnocc_system_t *sys, int32_t n_occ,
+                                            int32_t n_vir, size_t *bytes);
+int lnocc_local_hamiltonian(const lnocc_system_t *sys, const double *C_occ, int32_t n_occ,
+                            const double *C_vir, int32_t n_vir, double *B, void *workspace,
+                            size_t workspace_bytes, void *stream);
+
+/* MP2 of a fragment Hamiltonian (or of the whole system, as a fragment with
+ * every orbital active): t1 = 0 (when f->t1 != NULL), t2[i][j][a][b] =
+ * (ia|jb) / D_ij^ab (when f->t2 != NULL) and
+ * f->e_mp2 = sum_ijab (ia|jb) (2 (ia|jb) - (ib|ja)) / D_ij^ab.  Uses
+ * opt->workspace and opt->stream only; without t2 the integrals pass through
+ * the workspace a block of occupied rows at a time (at least one row,
+ * nocc nvir^2 doubles: lnocc_mp2_workspace_bytes).  Passing the amplitudes to
+ * lnocc_fragment_pair_energies (pair_t = NULL) gives the fragment's projected
+ * MP2 energy, the fragment term of Eq. 17. */
+int lnocc_mp2_workspace_bytes(const lnocc_fragment_t *f, size_t *bytes);
+int lnocc_fragment_mp2(lnocc_fragment_t *f, const lnocc_options_t *opt);
+
+/* Eq. 17's composite correction: e_mp2_full - sum_k e_mp2_fragments[k] (host). */
+double lnocc_mp2_composite(double e_mp2_full, const double *e_mp2_fragments, int32_t nfrag);
+
 /* ---- building block -------------------------------------------------------
  * Batched two-index-mode tensor contraction used for every DF product
  * (Eq. 27a: sums over the auxiliary index) and amplitude contraction:

@@ -16,7 +16,8 @@ PKG = pathlib.Path(__file__).resolve().parent
 SRC = PKG / "csrc"
 OUT = PKG / "_build"
 LIB = PKG / "liblnocc.so"
-SOURCES = ["gett.hip", "kernels.hip", "triples.hip", "pairs.hip", "mlp.hip", "solver.hip", "abi.hip"]
+SOURCES = ["gett.hip", "kernels.hip", "triples.hip", "pairs.hip", "mlp.hip", "lno.hip", "solver.hip",
+           "abi.hip", "abi_lno.hip"]
 
 # -packed-fp32-ops: no v_pk_*_f32 generation (see the numerics notes of the design).
 FLAGS = [

@@ -74,6 +74,21 @@ class lnocc_contract_t(C.Structure):
     ]
 
 
+class lnocc_system_t(C.Structure):
+    _fields_ = [("nocc", C.c_int32), ("nvir", C.c_int32), ("naux", C.c_int32),
+                ("reserved0", C.c_int32), ("Lao", C.c_void_p), ("C", C.c_void_p),
+                ("eps_occ", C.c_void_p), ("eps_vir", C.c_void_p)]
+
+
+class lnocc_local_space_t(C.Structure):
+    _fields_ = [("U_occ", C.c_void_p), ("U_vir", C.c_void_p), ("nlo", C.c_int32),
+                ("cbno", C.c_int32), ("eta_occ", C.c_double), ("eta_vir", C.c_double),
+                ("C_occ", C.c_void_p), ("eps_occ", C.c_void_p), ("C_vir", C.c_void_p),
+                ("eps_vir", C.c_void_p), ("lambda_occ", C.c_void_p), ("lambda_vir", C.c_void_p),
+                ("U_act", C.c_void_p), ("n_occ", C.c_int32), ("n_vir", C.c_int32), ("n_int_occ", C.c_int32),
+                ("n_int_vir", C.c_int32)]
+
+
 class lnocc_kernel_stats_t(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("flops", C.c_double)]
 
@@ -89,7 +104,9 @@ EXPORTS = ("lnocc_default_options", "lnocc_status_string", "lnocc_last_error",
            "lnocc_profile_collect", "lnocc_set_validation_mode", "lnocc_mlp_workspace_bytes",
            "lnocc_mlp_samples", "lnocc_mlp_init", "lnocc_mlp_predict", "lnocc_mlp_loss_grad",
            "lnocc_mlp_train", "lnocc_autotune_save", "lnocc_autotune_load",
-           "lnocc_autotune_clear")
+           "lnocc_autotune_clear", "lnocc_local_space_workspace_bytes", "lnocc_local_space",
+           "lnocc_local_hamiltonian_workspace_bytes", "lnocc_local_hamiltonian",
+           "lnocc_mp2_workspace_bytes", "lnocc_fragment_mp2", "lnocc_mp2_composite")
 
 
 def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
@@ -145,6 +162,20 @@ def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
     lib.lnocc_autotune_load.restype = C.c_int
     lib.lnocc_autotune_clear.argtypes = []
     lib.lnocc_autotune_clear.restype = None
+    SP, LP = C.POINTER(lnocc_system_t), C.POINTER(lnocc_local_space_t)
+    SZ = C.POINTER(C.c_size_t)
+    lib.lnocc_local_space_workspace_bytes.argtypes = [SP, C.c_int32, C.c_int32, SZ]
+    lib.lnocc_local_space.argtypes = [SP, LP, P, C.c_size_t, P]
+    lib.lnocc_local_hamiltonian_workspace_bytes.argtypes = [SP, C.c_int32, C.c_int32, SZ]
+    lib.lnocc_local_hamiltonian.argtypes = [SP, P, C.c_int32, P, C.c_int32, P, P, C.c_size_t, P]
+    lib.lnocc_mp2_workspace_bytes.argtypes = [FP, SZ]
+    lib.lnocc_fragment_mp2.argtypes = [FP, OP]
+    lib.lnocc_mp2_composite.argtypes = [C.c_double, C.POINTER(C.c_double), C.c_int32]
+    lib.lnocc_mp2_composite.restype = C.c_double
+    for name in ("lnocc_local_space_workspace_bytes", "lnocc_local_space",
+                 "lnocc_local_hamiltonian_workspace_bytes", "lnocc_local_hamiltonian",
+                 "lnocc_mp2_workspace_bytes", "lnocc_fragment_mp2"):
+        getattr(lib, name).restype = C.c_int
     for name in ("lnocc_mlp_workspace_bytes", "lnocc_mlp_samples", "lnocc_mlp_init",
                  "lnocc_mlp_predict", "lnocc_mlp_loss_grad", "lnocc_mlp_train"):
         getattr(lib, name).restype = C.c_int
@@ -281,6 +312,46 @@ def lnocc_mlp_train(blob_ptr: int, adam_ptr: int, step0: int, nsteps: int, x_ptr
     return st, (list(losses)[:nsteps] if want_losses else [])
 
 
+def lnocc_local_space_workspace_bytes(sys: lnocc_system_t, nlo: int, cbno: bool) -> tuple[int, int]:
+    out = C.c_size_t(0)
+    st = _lib.lnocc_local_space_workspace_bytes(C.byref(sys), nlo, int(bool(cbno)), C.byref(out))
+    return st, out.value
+
+
+def lnocc_local_space(sys: lnocc_system_t, sp: lnocc_local_space_t, workspace: int,
+                      workspace_bytes: int, stream: int = 0) -> int:
+    return _lib.lnocc_local_space(C.byref(sys), C.byref(sp), workspace, workspace_bytes, stream)
+
+
+def lnocc_local_hamiltonian_workspace_bytes(sys: lnocc_system_t, n_occ: int,
+                                            n_vir: int) -> tuple[int, int]:
+    out = C.c_size_t(0)
+    st = _lib.lnocc_local_hamiltonian_workspace_bytes(C.byref(sys), n_occ, n_vir, C.byref(out))
+    return st, out.value
+
+
+def lnocc_local_hamiltonian(sys: lnocc_system_t, C_occ: int | None, n_occ: int,
+                            C_vir: int | None, n_vir: int, B: int, workspace: int,
+                            workspace_bytes: int, stream: int = 0) -> int:
+    return _lib.lnocc_local_hamiltonian(C.byref(sys), C_occ, n_occ, C_vir, n_vir, B, workspace,
+                                        workspace_bytes, stream)
+
+
+def lnocc_mp2_workspace_bytes(frag: lnocc_fragment_t) -> tuple[int, int]:
+    out = C.c_size_t(0)
+    st = _lib.lnocc_mp2_workspace_bytes(C.byref(frag), C.byref(out))
+    return st, out.value
+
+
+def lnocc_fragment_mp2(frag: lnocc_fragment_t, opt: lnocc_options_t) -> int:
+    return _lib.lnocc_fragment_mp2(C.byref(frag), C.byref(opt))
+
+
+def lnocc_mp2_composite(e_mp2_full: float, e_mp2_fragments) -> float:
+    arr = (C.c_double * max(1, len(e_mp2_fragments)))(*e_mp2_fragments)
+    return _lib.lnocc_mp2_composite(e_mp2_full, arr, len(e_mp2_fragments))
+
+
 # ------------------------------------------------------------ torch helpers
 @dataclasses.dataclass
 class Result:
@@ -399,3 +470,105 @@ def solve_batch(fragments, *, conv_tol=1e-8, workspace=None, **kw) -> list[Resul
     lnocc_batch_solve(arr, opt)
     return [Result(arr[k].status, arr[k].e_mp2, arr[k].e_ccsd, arr[k].e_t, arr[k].n_iter,
                    arr[k].residual, *amps[k], arr[k].guess_used) for k in range(len(fragments))]
+
+
+# ------------------------------------------------------------ local active spaces
+@dataclasses.dataclass
+class ActiveSpace:
+    status: int
+    C_occ: object        # [nocc, n_occ] active occupied orbitals on the canonical ones
+    eps_occ: object      # [n_occ]
+    C_vir: object        # [nvir, n_vir]
+    eps_vir: object      # [n_vir]
+    lambda_occ: object   # external occupied eigenvalues, descending |lambda|
+    lambda_vir: object
+    U_act: object        # [n_occ, nlo] the fragment's LOs on the active occupied orbitals
+    n_int_occ: int
+    n_int_vir: int
+
+
+def make_system_struct(Lao, Cmo, eps_occ, eps_vir) -> lnocc_system_t:
+    s = lnocc_system_t()
+    s.nocc, s.nvir, s.naux = eps_occ.numel(), eps_vir.numel(), Lao.shape[0]
+    s.Lao, s.C = Lao.data_ptr(), Cmo.data_ptr()
+    s.eps_occ, s.eps_vir = eps_occ.data_ptr(), eps_vir.data_ptr()
+    return s
+
+
+def local_space(Lao, Cmo, eps_occ, eps_vir, U_occ, U_vir=None, *, eta_occ=0.0, eta_vir=0.0,
+                cbno=False, workspace=None) -> ActiveSpace:
+    """lnocc_local_space on device tensors (FP64); returns views of the active
+    columns."""
+    torch = _torch()
+    dev = Lao.device
+    sysd = make_system_struct(Lao, Cmo, eps_occ, eps_vir)
+    no, nv = sysd.nocc, sysd.nvir
+    nlo = U_occ.shape[1]
+    sp = lnocc_local_space_t()
+    sp.U_occ = U_occ.data_ptr()
+    sp.U_vir = U_vir.data_ptr() if U_vir is not None else None
+    sp.nlo, sp.cbno, sp.eta_occ, sp.eta_vir = nlo, int(bool(cbno)), eta_occ, eta_vir
+    f64 = dict(dtype=torch.float64, device=dev)
+    Co, Cv = torch.zeros((no, no), **f64), torch.zeros((nv, nv), **f64)
+    eo, ev = torch.zeros(no, **f64), torch.zeros(nv, **f64)
+    lo, lv = torch.zeros(no, **f64), torch.zeros(nv, **f64)
+    sp.C_occ, sp.eps_occ, sp.C_vir, sp.eps_vir = (Co.data_ptr(), eo.data_ptr(), Cv.data_ptr(),
+                                                  ev.data_ptr())
+    sp.lambda_occ, sp.lambda_vir = lo.data_ptr(), lv.data_ptr()
+    Ua = torch.zeros((no, nlo), **f64)
+    sp.U_act = Ua.data_ptr()
+    st, nbytes = lnocc_local_space_workspace_bytes(sysd, nlo, cbno)
+    if st != LNOCC_OK:
+        raise ValueError(lnocc_status_string(st))
+    ws = (workspace or Workspace(dev)).ensure(nbytes)
+    st = lnocc_local_space(sysd, sp, ws.data_ptr(), ws.numel(), _stream_handle(torch))
+    if st < 0:
+        raise RuntimeError(f"lnocc_local_space: {lnocc_status_string(st)} {lnocc_last_error()}")
+    return ActiveSpace(st, Co[:, :sp.n_occ], eo[:sp.n_occ], Cv[:, :sp.n_vir], ev[:sp.n_vir],
+                       lo[:no - sp.n_int_occ], lv[:nv - sp.n_int_vir], Ua[:sp.n_occ],
+                       sp.n_int_occ, sp.n_int_vir)
+
+
+def local_hamiltonian(Lao, Cmo, eps_occ, eps_vir, C_occ, C_vir, workspace=None):
+    """lnocc_local_hamiltonian: B [naux, na, na] of the active orbitals C_occ
+    [nocc, n_occ] and C_vir [nvir, n_vir] (copied into the [nocc][nocc] /
+    [nvir][nvir] arrays the C call reads)."""
+    torch = _torch()
+    dev = Lao.device
+    sysd = make_system_struct(Lao, Cmo, eps_occ, eps_vir)
+    no, nv = sysd.nocc, sysd.nvir
+    n_occ, n_vir = C_occ.shape[1], C_vir.shape[1]
+    Co = torch.zeros((no, no), dtype=torch.float64, device=dev)
+    Cv = torch.zeros((nv, nv), dtype=torch.float64, device=dev)
+    Co[:, :n_occ] = C_occ
+    Cv[:, :n_vir] = C_vir
+    na = n_occ + n_vir
+    B = torch.empty((sysd.naux, na, na), dtype=torch.float64, device=dev)
+    st, nbytes = lnocc_local_hamiltonian_workspace_bytes(sysd, n_occ, n_vir)
+    if st != LNOCC_OK:
+        raise ValueError(lnocc_status_string(st))
+    ws = (workspace or Workspace(dev)).ensure(nbytes)
+    st = lnocc_local_hamiltonian(sysd, Co.data_ptr(), n_occ, Cv.data_ptr(), n_vir, B.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), _stream_handle(torch))
+    if st != LNOCC_OK:
+        raise RuntimeError(f"lnocc_local_hamiltonian: {lnocc_status_string(st)} {lnocc_last_error()}")
+    return B
+
+
+def fragment_mp2(B, eps_occ, eps_vir, *, want_t2=True, workspace=None):
+    """lnocc_fragment_mp2: (E_MP2, t2 or None)."""
+    torch = _torch()
+    o, v = eps_occ.numel(), eps_vir.numel()
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=B.device) if want_t2 else None
+    f = make_fragment_struct(B, eps_occ, eps_vir, None, t2, 1e-8)
+    st, nbytes = lnocc_mp2_workspace_bytes(f)
+    if st != LNOCC_OK:
+        raise ValueError(lnocc_status_string(st))
+    opt = make_options()
+    ws = (workspace or Workspace(B.device)).ensure(nbytes)
+    opt.workspace, opt.workspace_bytes = ws.data_ptr(), ws.numel()
+    opt.stream = _stream_handle(torch)
+    st = lnocc_fragment_mp2(f, opt)
+    if st != LNOCC_OK:
+        raise RuntimeError(f"lnocc_fragment_mp2: {lnocc_status_string(st)} {lnocc_last_error()}")
+    return f.e_mp2, t2

@@ -14,7 +14,9 @@ from .fragments import (
     make_system,
     BATCH_ORACLE_SUBSET,
     LARGE_TRIPLES_SHAPE,
+    random_orthonormal,
 )
 
 __all__ = ["Fragment", "make_fragment", "batch_shapes", "CONFIG_SHAPES", "random_amplitudes", "System", "make_system",
-           "BATCH_ORACLE_SUBSET", "LARGE_TRIPLES_SHAPE"]
+           "BATCH_ORACLE_SUBSET", "LARGE_TRIPLES_SHAPE",
+           "random_orthonormal"]

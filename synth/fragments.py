@@ -165,3 +165,10 @@ def make_system(nocc: int, nvir: int, naux: int, seed: int, nlo_vir: int = 0,
     frags = [list(range(f, nlo, nfrag)) for f in range(nfrag)]
     return System(nocc, nvir, naux, np.ascontiguousarray(L), C, eps_occ, eps_vir, U_occ,
                   np.ascontiguousarray(U_vir), frags)
+
+
+def random_orthonormal(n: int, k: int, seed: int) -> np.ndarray:
+    """[n, k] matrix with orthonormal columns: Q of the QR factorization of an
+    N(0,1) draw (default_rng(seed))."""
+    Q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, k)))
+    return np.ascontiguousarray(Q)

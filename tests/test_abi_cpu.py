@@ -41,7 +41,8 @@ def test_every_declared_function_is_exported():
 def test_struct_layouts_match_the_header():
     structs = {"lnocc_fragment_t": L.lnocc_fragment_t, "lnocc_options_t": L.lnocc_options_t,
                "lnocc_operand_t": L.lnocc_operand_t, "lnocc_contract_t": L.lnocc_contract_t,
-               "lnocc_kernel_stats_t": L.lnocc_kernel_stats_t}
+               "lnocc_kernel_stats_t": L.lnocc_kernel_stats_t,
+               "lnocc_system_t": L.lnocc_system_t, "lnocc_local_space_t": L.lnocc_local_space_t}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -183,6 +184,100 @@ def test_pair_energy_launches_stay_in_bounds(validation_mode, o, v, X):
     assert L.lnocc_fragment_pair_energies(f, opt, *args) == L.LNOCC_ENOMEM
     opt.workspace_bytes = nbytes
     assert L.lnocc_fragment_pair_energies(f, opt, out, None, out + (2 << 30), 0, out, None) == L.LNOCC_EINVAL
+
+
+def _fake_system(o, v, X):
+    s = L.lnocc_system_t()
+    s.nocc, s.nvir, s.naux = o, v, X
+    n = o + v
+    base = 1 << 44
+    s.Lao = base
+    s.C = base + X * n * n * 8 + 4096
+    s.eps_occ = s.C + n * n * 8 + 4096
+    s.eps_vir = s.eps_occ + o * 8 + 4096
+    return s
+
+
+def _fake_space(o, v, nlo, cbno, with_vir):
+    sp = L.lnocc_local_space_t()
+    out = 1 << 46
+    sp.U_occ = out
+    sp.U_vir = out + (1 << 36) if with_vir else None
+    sp.nlo, sp.cbno, sp.eta_occ, sp.eta_vir = nlo, int(cbno), 1e-5, 1e-6
+    for k, name in enumerate(("C_occ", "eps_occ", "C_vir", "eps_vir", "lambda_occ",
+                              "lambda_vir", "U_act")):
+        setattr(sp, name, out + ((k + 2) << 36))
+    return sp
+
+
+LNO_SHAPES = [(4, 10, 30, 2), (3, 5, 18, 8), (1, 1, 1, 1), (16, 160, 528, 3), (7, 53, 90, 40),
+              (32, 400, 1300, 2)]
+
+
+@pytest.mark.parametrize("with_vir", [False, True])
+@pytest.mark.parametrize("cbno", [False, True])
+@pytest.mark.parametrize("o,v,X,nlo", LNO_SHAPES)
+def test_local_space_launches_stay_in_bounds(validation_mode, o, v, X, nlo, cbno, with_vir):
+    """Every launch of the active-space construction (Sec. II.C-E) and of the
+    local Hamiltonian's DF transform (Eq. 27b) stays inside the workspace and the
+    caller's arrays (validation mode keeps every internal orbital and every LNO,
+    the largest sizes); a workspace one byte short is refused."""
+    sysd = _fake_system(o, v, X)
+    st, nbytes = L.lnocc_local_space_workspace_bytes(sysd, nlo, cbno)
+    assert st == L.LNOCC_OK and nbytes > 0
+    sp = _fake_space(o, v, nlo, cbno, with_vir)
+    ws = 1 << 45
+    assert L.lnocc_local_space(sysd, sp, ws, nbytes) == L.LNOCC_OK, L.lnocc_last_error()
+    assert (sp.n_int_occ, sp.n_occ) == (min(nlo, o), o)
+    assert (sp.n_int_vir, sp.n_vir) == ((min(nlo, v) if with_vir else 0), v)
+    assert L.lnocc_local_space(sysd, sp, ws, nbytes - 1) == L.LNOCC_ENOMEM
+    st, hb = L.lnocc_local_hamiltonian_workspace_bytes(sysd, sp.n_occ, sp.n_vir)
+    assert st == L.LNOCC_OK
+    B = 1 << 47
+    assert L.lnocc_local_hamiltonian(sysd, sp.C_occ, sp.n_occ, sp.C_vir, sp.n_vir, B, ws,
+                                     hb) == L.LNOCC_OK, L.lnocc_last_error()
+    assert L.lnocc_local_hamiltonian(sysd, sp.C_occ, sp.n_occ, sp.C_vir, sp.n_vir, B, ws,
+                                     hb - 1) == L.LNOCC_ENOMEM
+    if o > 1 and v > 1:   # a truncated space
+        st, hb = L.lnocc_local_hamiltonian_workspace_bytes(sysd, o - 1, v // 2)
+        assert L.lnocc_local_hamiltonian(sysd, sp.C_occ, o - 1, sp.C_vir, v // 2, B, ws,
+                                         hb) == L.LNOCC_OK
+
+
+def test_local_space_argument_errors():
+    sysd = _fake_system(4, 10, 30)
+    assert L.lnocc_local_space_workspace_bytes(sysd, 0, False)[0] == L.LNOCC_EINVAL
+    big = _fake_system(4, 2049, 30)
+    assert L.lnocc_local_space_workspace_bytes(big, 2, False)[0] == L.LNOCC_EINVAL
+    st, nbytes = L.lnocc_local_space_workspace_bytes(sysd, 2, False)
+    for field, value in (("eta_occ", -1.0), ("eta_vir", float("nan")), ("nlo", 0),
+                         ("U_occ", None), ("C_vir", None)):
+        sp = _fake_space(4, 10, 2, False, False)
+        setattr(sp, field, value)
+        assert L.lnocc_local_space(sysd, sp, 1 << 45, nbytes) == L.LNOCC_EINVAL, field
+    assert L.lnocc_local_hamiltonian_workspace_bytes(sysd, 5, 3)[0] == L.LNOCC_EINVAL
+    assert L.lnocc_local_hamiltonian_workspace_bytes(sysd, 0, 0)[0] == L.LNOCC_EINVAL
+    assert L.lnocc_mp2_composite(-1.0, [-0.25, -0.5]) == pytest.approx(-0.25, abs=0)
+
+
+@pytest.mark.parametrize("o,v,X", [(4, 20, 72), (1, 1, 1), (6, 45, 100), (16, 160, 528)])
+def test_mp2_launches_stay_in_bounds(validation_mode, o, v, X):
+    """The MP2 entry point (whole amplitudes, or energy only through a workspace
+    of one or a few occupied rows) stays in bounds; a short workspace is refused."""
+    opt = L.make_options()
+    f = _fake_fragment(o, v, X)
+    st, nbytes = L.lnocc_mp2_workspace_bytes(f)
+    assert st == L.LNOCC_OK
+    opt.workspace, opt.workspace_bytes = 1 << 45, nbytes
+    assert L.lnocc_fragment_mp2(f, opt) == L.LNOCC_OK, L.lnocc_last_error()
+    opt.workspace_bytes = nbytes - 1
+    assert L.lnocc_fragment_mp2(f, opt) == L.LNOCC_ENOMEM
+    f.t2 = None
+    st, n1 = L.lnocc_mp2_workspace_bytes(f)
+    assert n1 > nbytes
+    for extra in (0, 3 * o * v * v * 8 // 2):
+        opt.workspace_bytes = n1 + extra
+        assert L.lnocc_fragment_mp2(f, opt) == L.LNOCC_OK, L.lnocc_last_error()
 
 
 def test_static_scratch_entry_point(validation_mode):
