@@ -50,20 +50,28 @@ typedef enum {
   LNOCC_ENUMERIC = -4      /* a non-finite residual or energy appeared */
 } lnocc_status_t;
 
-/* Arithmetic of the two dominant contractions (the particle-particle ladder
- * of the CCSD residual and the W contraction of (T)).  Energies, denominators,
+/* Arithmetic of the dominant contractions (the particle-particle ladder of
+ * the CCSD residual, the W contraction of (T) and, in the reduced modes, the
+ * o^3 v^3 ring contractions of the residual).  Energies, denominators,
  * residual norms and DIIS stay FP64 in every mode. */
 typedef enum {
   LNOCC_FP64 = 0,
-  LNOCC_FP32 = 1, /* FP32 storage; FP32-accurate products: on the FP32 matrix cores, or
-                     split as in LNOCC_FP32_SPLIT where that is faster (the ladder
-                     contraction; the autotuner may pick either per shape); FP32
-                     accumulation per tile */
-  LNOCC_BF16 = 2, /* BF16 matrix-core products (round to nearest even), FP32 accumulation */
-  LNOCC_FP32_SPLIT = 3 /* lnocc_contract only (not a solve precision): FP32 operands, each
-                          split into three bf16 parts (round to nearest even); a product is
-                          the sum of the six largest part products on the BF16 matrix
-                          cores, FP32 accumulation: FP32-level accuracy at BF16 rates */
+  LNOCC_FP32 = 1, /* FP32 storage of the ladder and (T) operands; FP32-accurate products:
+                     on the FP32 matrix cores, or split as in LNOCC_FP32_SPLIT where that
+                     is faster (the ladder contraction; the autotuner may pick either per
+                     shape); FP32 accumulation per tile.  The ring contractions keep FP64
+                     operands and use the products of LNOCC_FP64_SPLIT while the last
+                     step norm is above 100 conv_tol, FP64 products after that */
+  LNOCC_BF16 = 2, /* experimental: BF16 matrix-core products of the ladder (round to nearest
+                     even), FP32 accumulation; errors of order 1e-4 Eh and a residual
+                     floor near 1e-5 (the triples W contraction runs in FP32 and the
+                     ring contractions as in LNOCC_FP32) */
+  LNOCC_FP32_SPLIT = 3, /* lnocc_contract only (not a solve precision): FP32 operands, each
+                           split into three bf16 parts (round to nearest even); a product is
+                           the sum of the six largest part products on the BF16 matrix
+                           cores, FP32 accumulation: FP32-level accuracy at BF16 rates */
+  LNOCC_FP64_SPLIT = 4  /* lnocc_contract only: FP64 operands rounded to FP32 (nearest even)
+                           as they are staged, then multiplied as in LNOCC_FP32_SPLIT */
 } lnocc_precision_t;
 
 typedef enum {
@@ -333,7 +341,8 @@ double lnocc_mp2_composite(double e_mp2_full, const double *e_mp2_fragments, int
  * are in elements.  precision selects the operand element type and product
  * arithmetic (LNOCC_FP64: double; LNOCC_FP32: float, FP32 accumulation;
  * LNOCC_BF16: bf16 bit patterns, FP32 accumulation; LNOCC_FP32_SPLIT: float,
- * split bf16 products, FP32 accumulation); C is always FP64. */
+ * split bf16 products, FP32 accumulation; LNOCC_FP64_SPLIT: double, rounded to
+ * float, split bf16 products, FP32 accumulation); C is always FP64. */
 typedef struct lnocc_operand_t {
   const double *p;
   int64_t s_ro, s_ri, s_ko, s_ki;

@@ -837,7 +837,7 @@ int lnocc_contract(const lnocc_contract_t *c, void *stream) {
   d.c_b0 = c->c_b0; d.c_b1 = c->c_b1; d.c_b2 = 0; d.c_bid = c->c_bid;
   d.beta = c->beta;
   d.batch = c->batch; d.nb1 = c->nb1; d.table = nullptr;
-  if (c->precision < 0 || c->precision > 3) return LNOCC_EINVAL;
+  if (c->precision < 0 || c->precision > 4) return LNOCC_EINVAL;
   d.prec = (Prec)c->precision;
   d.c_type = 0;
   if (c->tile < 0 || c->tile > 9) return LNOCC_EINVAL;

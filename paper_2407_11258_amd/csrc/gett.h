@@ -16,8 +16,9 @@
 namespace lnocc {
 
 // F32S: FP32 operands whose products run on the bf16 matrix cores as sums of
-// split products (FP32-level accuracy; see the kernel source).
-enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2, F32S = 3 };
+// split products (FP32-level accuracy; see the kernel source).  F64S: FP64
+// operands in memory, rounded to FP32 when staged and multiplied as F32S.
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2, F32S = 3, F64S = 4 };
 
 // What a contraction computes; each class is its own kernel symbol (so
 // profiler statistics separate them) and its own timing bucket.

@@ -88,6 +88,18 @@ struct ModeF32S {
   static constexpr bool kRowMajor = true;
   __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
 };
+// FP64 operands in memory, rounded to FP32 as they are staged, then split as in
+// ModeF32S: FP32-class products at bf16 matrix-core rates for FP64 tensors that
+// need no FP32 copy.
+struct ModeF64S {
+  using T = double;
+  using L = uint16_t;
+  static constexpr int kPlanes = 3;
+  using Acc = float4_t;
+  static constexpr int KS = 32, BK = 32;
+  static constexpr bool kRowMajor = true;
+  __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
 
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 // round to nearest even (finite inputs)
@@ -171,6 +183,7 @@ template <class M> __device__ inline typename M::T scaled(typename M::T x, doubl
 template <> __device__ inline double scaled<ModeF64>(double x, double s) { return s * x; }
 template <> __device__ inline float scaled<ModeF32>(float x, double s) { return (float)s * x; }
 template <> __device__ inline float scaled<ModeF32S>(float x, double s) { return (float)s * x; }
+template <> __device__ inline double scaled<ModeF64S>(double x, double s) { return s * x; }
 
 __device__ inline uint16_t bf16_rn_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 // x -> (h, m, l) of the split-product mode
@@ -284,7 +297,7 @@ struct Slice {
       const E x = scaled<M>(__builtin_bit_cast(E, (U)(__builtin_bit_cast(U, reg[s]) & m)), scale);
       if constexpr (M::kPlanes == 3) {
         uint16_t h, mid, l;
-        split3(x, h, mid, l);
+        split3((float)x, h, mid, l);
         const int o = row_of(kfast, s) * LD + k_of(kfast, s);
         lds[o] = h;
         lds[PS + o] = mid;
@@ -579,7 +592,7 @@ void gett_kernel(GemmDesc d, int tiles_m, int slices_per_split) {
       const int64_t moff = mok ? two_index_off(d.mdiv, (uint32_t)m, d.c_mo, d.c_mi) : 0;
 #pragma unroll
       for (int j = 0; j < C::NI; ++j) {
-        if constexpr (std::is_same<E, double>::value) {
+        if constexpr (std::is_same<typename M::Acc, double4_t>::value) {
           const double4_t w = regroup_rows_f64(acc[i][j], lane);   // whole wave
           if (mok && cok[j]) store_out4(d, pc, ps, moff + coff[j], w);
         } else {
@@ -752,7 +765,7 @@ bool operand_ok(const GemmDesc &d, const GOperand &op, int64_t rows, int64_t Ri,
   add_term(s, bmax[1], op.b1);
   add_term(s, bmax[2], op.b2);
   add_term(s, d.batch - 1, op.bid);
-  const size_t esz = d.prec == Prec::F64 ? 8 : (d.prec == Prec::BF16 ? 2 : 4);
+  const size_t esz = (d.prec == Prec::F64 || d.prec == Prec::F64S) ? 8 : (d.prec == Prec::BF16 ? 2 : 4);
   return inside(op.p, s, esz);
 }
 
@@ -878,8 +891,8 @@ void launch_kind(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t
       hipLaunchKernelGGL((gett_kernel<M, C, 2>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
     case Kind::TriplesW:
       hipLaunchKernelGGL((gett_kernel<M, C, 3>), grid, dim3(C::T), 0, stream, d, tiles_m, sps); break;
-    case Kind::Ring:   // FP64 only
-      if constexpr (std::is_same<M, ModeF64>::value)
+    case Kind::Ring:   // FP64 operands (FP64 or split products)
+      if constexpr (std::is_same<M, ModeF64>::value || std::is_same<M, ModeF64S>::value)
         hipLaunchKernelGGL((gett_kernel<M, C, 5>), grid, dim3(C::T), 0, stream, d, tiles_m, sps);
       else
         hipLaunchKernelGGL((gett_kernel<M, C, 0>), grid, dim3(C::T), 0, stream, d, tiles_m, sps);
@@ -908,6 +921,7 @@ void launch(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stre
     case Prec::F32: launch_kind<ModeF32, C>(d, grid, tiles_m, sps, stream); break;
     case Prec::BF16: launch_kind<ModeBF16, C>(d, grid, tiles_m, sps, stream); break;
     case Prec::F32S: launch_kind<ModeF32S, C>(d, grid, tiles_m, sps, stream); break;
+    case Prec::F64S: launch_kind<ModeF64S, C>(d, grid, tiles_m, sps, stream); break;
     default: launch_kind<ModeF64, C>(d, grid, tiles_m, sps, stream); break;
   }
 }
@@ -1059,7 +1073,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   if (d.Mi <= 0 || d.Ni <= 0 || d.nseg <= 0 || d.nseg > kMaxSeg) return hipErrorInvalidValue;
   // k per LDS slice: 32 for the bf16 matrix-core arithmetics, else 16
   auto tile_bk = [&](int t) {
-    return (d.prec == Prec::BF16 || d.prec == Prec::F32S || t == kTileSplit ||
+    return (d.prec == Prec::BF16 || d.prec == Prec::F32S || d.prec == Prec::F64S || t == kTileSplit ||
             t == kTileSplit160) ? 32 : 16;
   };
   int slices16 = 0, slices32 = 0;

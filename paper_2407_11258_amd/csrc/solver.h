@@ -54,6 +54,7 @@ struct Layout {
   double *t2_lp;                    // t2 for (T): [o][o][v][vp] in the (T) element type
   bool t_f32 = false;               // (T) products and W in FP32
   Prec lp;                          // precision of the ladder and (T) products
+  Prec rp;                          // o^3 v^3 ring products: F64, or F64S in the FP32 / BF16 modes
   int lpt;                          // its element type: 0 double, 1 float, 2 bf16
   double *dx, *de;                  // DIIS vectors and errors [m][namp]
   int64_t chunk_a, namp;
@@ -108,7 +109,10 @@ int64_t unique_triples(int64_t o);
 void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout &L);
 int setup_fragment(const Layout &L, const double *B, const double *eo, const double *ev,
                    bool ccsd_phase, hipStream_t s);
-int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s);
+// split_ring: the o^3 v^3 ring products in L.rp (split bf16 in the reduced
+// modes) instead of FP64.
+int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s,
+                   bool split_ring = false);
 int tune_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s);
 int energy(const Layout &L, const double *t1, const double *t2, double *dev_out, hipStream_t s);
 struct Readback;
@@ -146,6 +150,10 @@ struct Readback {
 // has landed, and after_* consumes it.  The batch driver interleaves several
 // of these on one stream, so the host round trip of one fragment overlaps the
 // device work of the others.
+// Reduced modes: ring products in split bf16 while the last step norm exceeds
+// this multiple of the convergence threshold.
+constexpr double kSplitRingFactor = 100.0;
+
 struct CcsdRun {
   enum class Phase { Idle, Started, Iterating, Converged, Exhausted };
   const Layout *L;
@@ -163,7 +171,7 @@ struct CcsdRun {
   mutable int polls = 0;
   bool mlp_check = false;      // the first step from the learned start is still to be judged
   double r_mp2 = 0.0;          // first step norm from the MP2 start
-  hipGraphExec_t graph = nullptr;   // captured residual evaluation (replayed per iteration)
+  hipGraphExec_t graph[2] = {nullptr, nullptr};   // captured residual evaluation, FP64 / split ring
 
   CcsdRun(const Layout &L, const Inputs &in, const lnocc_options_t &opt, hipStream_t s,
           Readback &rb);
@@ -185,6 +193,7 @@ struct CcsdRun {
   hipError_t mark();
   int learned_start();
   int residuals();             // eager, or through the captured graph
+  bool split_ring() const;     // ring products of this iteration in split bf16
 };
 
 }  // namespace lnocc

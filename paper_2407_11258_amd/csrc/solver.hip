@@ -104,6 +104,7 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   L = Layout{};
   L.dm = dm;
   L.lp = opt.precision == LNOCC_FP32 ? Prec::F32 : (opt.precision == LNOCC_BF16 ? Prec::BF16 : Prec::F64);
+  L.rp = L.lp == Prec::F64 ? Prec::F64 : Prec::F64S;
   L.lpt = (int)L.lp;
   // common
   L.Boo = A.d(X * oo); L.Bov = A.d(X * ov); L.Bvv = A.d(X * vv);
@@ -312,14 +313,17 @@ int setup_fragment(const Layout &L, const double *B, const double *eo, const dou
 
 // Autotuning on the residual evaluation, which recomputes every intermediate
 // from (t1, t2): one evaluation per candidate, each timed launch by launch.
+// Both ring arithmetics of the reduced modes are tuned (each has its own shapes).
 int tune_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s) {
+  const int variants = L.rp != Prec::F64 ? 2 : 1;
   tune_probe_begin();
-  int st = ccsd_residuals(L, t1, t2, s);
+  int st = LNOCC_OK;
+  for (int w = 0; w < variants && !st; ++w) st = ccsd_residuals(L, t1, t2, s, w == 1);
   const int unplanned = tune_probe_end();
   if (st || unplanned == 0) return st;
   for (int c = 0; c < tune_candidates() && !st; ++c) {
     tune_candidate(c);
-    st = ccsd_residuals(L, t1, t2, s);
+    for (int w = 0; w < variants && !st; ++w) st = ccsd_residuals(L, t1, t2, s, w == 1);
   }
   tune_candidate(-1);
   tune_commit();
@@ -331,8 +335,10 @@ int tune_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
   return st;
 }
 
-int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s) {
+int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStream_t s,
+                   bool split_ring) {
   const int64_t o = L.dm.o, v = L.dm.v, X = L.dm.X;
+  const Prec ring = split_ring ? L.rp : Prec::F64;
   const int64_t ov = o * v, oo = o * o, vv = v * v, ovv = o * vv, vvv = vv * v, ooo = oo * o;
   const size_t B8 = sizeof(double);
   // --- T1 dressing of the DF factors
@@ -444,6 +450,7 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
       GemmDesc d = DESC(oo, 1, ov, v, L.Zl, ov, 0, v, 1, 0.0);
       SEG(d, vv, v, 1.0, OP(t2, vv, 0, v, 1), OP(L.Gkc, vvv, v, vv, 1));
       d.kind = Kind::Ring;
+      d.prec = ring;
       LN_TRY(gett(d, s));
     }
     {  // W[ij][k][l] = sum_cd t_ij^cd (kc|ld) ; Y[ij][k][b] = sum_l W[ij][k][l] t_l^b
@@ -511,10 +518,12 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     d.c_src = L.Goovv;
     SEG(d, ov, v, -0.5, OP(t2, vv, v, ovv, 1), OP(L.Q2, ovv, v, vv, 1));
     d.kind = Kind::Ring;
+    d.prec = ring;
     LN_TRY(gett(d, s));
     d = DESC(ov, v, ov, v, L.Xc, ovv, v, vv, 1, 0.0);
     SEG(d, ov, v, 1.0, OP(L.Cint, vv, v, ovv, 1), OP(t2, vv, v, ovv, 1));
     d.kind = Kind::Ring;
+    d.prec = ring;
     LN_TRY(gett(d, s));
   }
   // Coulomb-type ring: Dint_iakc = 2 (ai|kc)~ - (ki|ac)~ + 1/2 sum_ld u_il^ad L_ldkc ;
@@ -527,10 +536,12 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     d = DESC(ov, v, ov, 1, L.Dint, ovv, ov, 1, 0, 1.0);
     SEG(d, ov, v, 0.5, OP(L.u, ovv, v, vv, 1), OP(L.Lov, 1, 0, ovv, ov));
     d.kind = Kind::Ring;
+    d.prec = ring;
     LN_TRY(gett(d, s));
     d = DESC(ov, v, ov, v, L.S, ovv, v, vv, 1, 0.0);
     SEG(d, ov, v, 0.5, OP(L.Dint, ovv, ov, v, 1), OP(L.u, ovv, v, vv, 1));
     d.kind = Kind::Ring;
+    d.prec = ring;
     LN_TRY(gett(d, s));
   }
   // Fock-type terms: F'_bc = F~_bc - sum_kld u_kl^bd (ld|kc), F'_kj = F~_kj + sum_lcd u_lj^cd (kd|lc)
@@ -645,15 +656,26 @@ CcsdRun::CcsdRun(const Layout &L_, const Inputs &in_, const lnocc_options_t &opt
       G((size_t)L_.diis_m * L_.diis_m, 0.0) {}
 
 CcsdRun::~CcsdRun() {
-  if (graph) (void)hipGraphExecDestroy(graph);
+  for (hipGraphExec_t g : graph)
+    if (g) (void)hipGraphExecDestroy(g);
+}
+
+// Ring products of the reduced modes: split bf16 (FP32-class) while the step
+// norm is far above the convergence threshold, FP64 for the last iterations,
+// so the rounding of the split products never sets the final residual.
+bool CcsdRun::split_ring() const {
+  return L->rp != Prec::F64 && prev > kSplitRingFactor * in.conv_tol;
 }
 
 // The residual evaluation enqueues the same ~100 launches with the same
 // arguments in every iteration of a solve (only the amplitude values change),
-// so it is captured once and replayed.  It records no memset (copies only).
+// so it is captured once per ring arithmetic and replayed.  It records no
+// memset (copies only).
 int CcsdRun::residuals() {
+  const bool split = split_ring();
   if (!opt.graphs || dry_run() || profile_enabled())
-    return ccsd_residuals(*L, in.t1, in.t2, s);
+    return ccsd_residuals(*L, in.t1, in.t2, s, split);
+  hipGraphExec_t &graph = this->graph[split ? 1 : 0];
   if (!graph) {   // captured on a stream of its own (the caller's may be the null stream)
     hipStream_t cs = nullptr;
     LN_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -662,7 +684,7 @@ int CcsdRun::residuals() {
       (void)hipStreamDestroy(cs);
       LN_TRY(e);
     }
-    const int st = ccsd_residuals(*L, in.t1, in.t2, cs);
+    const int st = ccsd_residuals(*L, in.t1, in.t2, cs, split);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
@@ -706,7 +728,7 @@ hipError_t CcsdRun::wait() const {
 // correction over the unique amplitudes, chunk by chunk.
 int CcsdRun::learned_start() {
   const int64_t o = L->dm.o, v = L->dm.v, N = L->namp;
-  int st = ccsd_residuals(*L, in.t1, in.t2, s);
+  int st = ccsd_residuals(*L, in.t1, in.t2, s, split_ring());
   if (st) return st;
   install_splitk_scratch(L->splitk, (size_t)L->splitk_elems);
   LN_TRY(jacobi_step(in.t1, in.t2, L->R1, L->R2, in.eo, in.ev, o, v, opt.level_shift, L->dx,

@@ -21,7 +21,7 @@ LNOCC_ENOMEM = -2
 LNOCC_EDEVICE = -3
 LNOCC_ENUMERIC = -4
 
-LNOCC_FP64, LNOCC_FP32, LNOCC_BF16, LNOCC_FP32_SPLIT = 0, 1, 2, 3
+LNOCC_FP64, LNOCC_FP32, LNOCC_BF16, LNOCC_FP32_SPLIT, LNOCC_FP64_SPLIT = 0, 1, 2, 3, 4
 LNOCC_GUESS_MP2, LNOCC_GUESS_USER, LNOCC_GUESS_MLP = 0, 1, 2
 LNOCC_MLP_FEATURES, LNOCC_MLP_HIDDEN, LNOCC_MLP_HEADER, LNOCC_MLP_PARAMS = 16, 256, 64, 136256
 LNOCC_MLP_BLOB = LNOCC_MLP_HEADER + LNOCC_MLP_PARAMS

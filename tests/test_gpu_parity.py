@@ -254,15 +254,18 @@ def test_contract_matrix_vector(M, Mi, K, kfast):
     np.testing.assert_allclose(host(c), ref, rtol=0, atol=1e-12 * np.sqrt(K) * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
-def test_contract_split_products_exact(tile):
-    """Split bf16 products (LNOCC_FP32_SPLIT) on operands x = s (1 + c 2^-9),
-    s = +-1, c in {-1, 0, 1}: x needs 10 significant bits, so it splits into a
-    bf16 high part s and a nonzero middle part s c 2^-9.  Every part product the
-    kernel forms is exact, and with K = 16 every partial sum fits FP32's 24 bits,
-    so C must equal the exact product bit for bit; dropping the middle-part
-    products (h m', m h', m m') would change it by multiples of 2^-18."""
-    say(f"contract split products exact tile {tile}")
+@pytest.mark.parametrize("tile,precision", [(0, 3), (1, 3), (2, 3), (3, 3), (4, 3), (0, 4),
+                                            (1, 4), (3, 4)])
+def test_contract_split_products_exact(tile, precision):
+    """Split bf16 products (LNOCC_FP32_SPLIT on FP32 operands, LNOCC_FP64_SPLIT
+    on FP64 ones) on operands x = s (1 + c 2^-9), s = +-1, c in {-1, 0, 1}: x
+    needs 10 significant bits (exact in FP32, so the FP64 -> FP32 rounding is
+    exact too), so it splits into a bf16 high part s and a nonzero middle part
+    s c 2^-9.  Every part product the kernel forms is exact, and with K = 16
+    every partial sum fits FP32's 24 bits, so C must equal the exact product
+    bit for bit; dropping the middle-part products (h m', m h', m m') would
+    change it by multiples of 2^-18."""
+    say(f"contract split products exact tile {tile} precision {precision}")
     rng = np.random.default_rng(40 + tile)
     M, N, K = 133, 70, 16
 
@@ -273,12 +276,38 @@ def test_contract_split_products_exact(tile):
     A, Bm = draw(M, K), draw(N, K)
     ref = A @ Bm.T                                   # exact in FP64 (<= 30 bits)
     c = torch.zeros((M, N), dtype=torch.float64, device=DEV)
-    a_t = torch.tensor(A.astype(np.float32), device=DEV)
-    b_t = torch.tensor(Bm.astype(np.float32), device=DEV)
+    dt = np.float32 if precision == L.LNOCC_FP32_SPLIT else np.float64
+    a_t = torch.tensor(A.astype(dt), device=DEV)
+    b_t = torch.tensor(Bm.astype(dt), device=DEV)
     _contract(M, 1, N, 1, c, (N, 0, 1, 0),
               [(K, 1, 1.0, _operand(a_t, K, 0, 1, 0), _operand(b_t, K, 0, 1, 0))],
-              precision=L.LNOCC_FP32_SPLIT, tile=tile)
+              precision=precision, tile=tile)
     np.testing.assert_array_equal(host(c), ref)
+
+
+@pytest.mark.parametrize("tile", [0, 1, 3])
+def test_contract_fp64_split_accuracy(tile):
+    """LNOCC_FP64_SPLIT on full-mantissa FP64 operands (the arithmetic of the
+    ring contractions in the reduced modes): each operand is rounded to FP32
+    (relative error 2^-24) and split, so the result has FP32-level accuracy
+    against the FP64 product; a row-contiguous second segment and beta."""
+    say(f"contract FP64 split accuracy tile {tile}")
+    rng = np.random.default_rng(80 + tile)
+    M, N, K1, K2 = 299, 257, 640, 33
+    A1, B1 = rng.standard_normal((M, K1)), rng.standard_normal((N, K1))
+    A2, B2 = rng.standard_normal((K2, M)), rng.standard_normal((N, K2))
+    C0 = rng.standard_normal((M, N))
+    ref = A1 @ B1.T - 0.5 * A2.T @ B2.T + 0.25 * C0
+    t = [dev(x) for x in (A1, B1, A2, B2)]
+    segs = [(K1, 1, 1.0, _operand(t[0], K1, 0, 1, 0), _operand(t[1], K1, 0, 1, 0)),
+            (K2, 1, -0.5, _operand(t[2], 1, 0, M, 0), _operand(t[3], K2, 0, 1, 0))]
+    c = dev(C0)
+    _contract(M, 1, N, 1, c, (N, 0, 1, 0), segs, precision=L.LNOCC_FP64_SPLIT, tile=tile,
+              beta=0.25)
+    err = np.abs(host(c) - ref).max() / np.abs(ref).max()
+    say(f"  relative error {err:.2e}")
+    assert err < 2e-6 * np.sqrt(K1 + K2)
+    assert err > 1e-12          # not FP64 products
 
 
 @pytest.mark.parametrize("tile", [0, 1, 3])
@@ -398,6 +427,30 @@ def test_mixed_precision_solve(precision, tol):
     t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=DEV)
     st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=1e-9,
                    precision=precision)
+    say(f"  {precision}: dE_ccsd={fs.e_ccsd - ref.e_ccsd:.3e} dE_t={fs.e_t - ref_t:.3e} "
+        f"iters={fs.n_iter} status={st}")
+    assert st in (L.LNOCC_OK, L.LNOCC_NOT_CONVERGED)
+    assert abs(fs.e_ccsd - ref.e_ccsd) < tol * max(1.0, abs(ref.e_ccsd) * 10)
+    assert abs(fs.e_t - ref_t) < tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-6), ("bf16", 5e-3)])
+def test_mixed_precision_on_the_fly_ladder(precision, tol):
+    """The ladder built in every iteration from the T1-dressed B_vv (converted
+    to the low precision), written one block of a at a time (a chunk of a few
+    a values, so several blocks and a short last one run) and contracted with
+    split-bf16 (FP32) or bf16 products: energies against the FP64 oracle at
+    the same bounds as the stored ladder."""
+    say(f"mixed precision on-the-fly ladder {precision}")
+    o, v, X, seed = 6, 45, 100, 5
+    f = make_fragment(o, v, X, seed)
+    ref = occ.ccsd(f.B, f.eps_occ, f.eps_vir, conv_tol=1e-10)
+    ref_t = otr.e_triples_restricted(f.B, f.eps_occ, f.eps_vir, ref.t1, ref.t2)
+    B, eo, ev = _fragment_on_device(f)
+    t1 = torch.empty((o, v), dtype=torch.float64, device=DEV)
+    t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=DEV)
+    st, fs = _call(L.lnocc_fragment_ccsd, f, B, eo, ev, t1, t2, conv_tol=1e-9,
+                   precision=precision, ladder="on_the_fly", ladder_chunk_bytes=v ** 3 * 4 * 7)
     say(f"  {precision}: dE_ccsd={fs.e_ccsd - ref.e_ccsd:.3e} dE_t={fs.e_t - ref_t:.3e} "
         f"iters={fs.n_iter} status={st}")
     assert st in (L.LNOCC_OK, L.LNOCC_NOT_CONVERGED)
