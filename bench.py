@@ -129,11 +129,15 @@ def roofline(prof: dict, precision: str, workload: str) -> dict:
     dominant = max(prof, key=lambda k: prof[k]["ms"])
     d = prof[dominant]
     achieved = d["flops"] / d["ms"] / 1e9 if d["ms"] > 0 else 0.0
-    # ladder and (T) products run in the chosen precision; every other contraction in FP64
+    # ladder and (T) products run in the chosen precision; every other contraction in FP64;
+    # split-bf16 products (their own class) against the bf16 matrix-core peak over the
+    # six bf16 products that make one FP32-class product
     kprec = precision if dominant in ("ladder_build", "ladder_contract", "triples_w") else "fp64"
     if dominant == "mlp":
         kprec = "fp32"
-    peak = PEAKS_TFLOPS[kprec]
+    if dominant == "split":
+        kprec = "split_bf16x6"
+    peak = PEAKS_TFLOPS["bf16"] / 6.0 if kprec == "split_bf16x6" else PEAKS_TFLOPS[kprec]
     traffic = None
     tpath = ROOT / "profiles" / "traffic.json"
     if tpath.exists():

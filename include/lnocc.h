@@ -59,9 +59,12 @@ typedef enum {
   LNOCC_FP32 = 1, /* FP32 storage of the ladder and (T) operands; FP32-accurate products:
                      on the FP32 matrix cores, or split as in LNOCC_FP32_SPLIT where that
                      is faster (the ladder contraction; the autotuner may pick either per
-                     shape); FP32 accumulation per tile.  The ring contractions keep FP64
-                     operands and use the products of LNOCC_FP64_SPLIT while the last
-                     step norm is above 100 conv_tol, FP64 products after that */
+                     shape); FP32 accumulation per tile.  The other sizeable products of
+                     the residual (the ring contractions, the DF products over Q, the T1
+                     dressing) keep FP64 operands and use the products of
+                     LNOCC_FP64_SPLIT in the early iterations, FP64 products from the
+                     first step norm within 100 conv_tol (or the second in a row
+                     without a new minimum) on */
   LNOCC_BF16 = 2, /* experimental: BF16 matrix-core products of the ladder (round to nearest
                      even), FP32 accumulation; errors of order 1e-4 Eh and a residual
                      floor near 1e-5 (the triples W contraction runs in FP32 and the
@@ -381,6 +384,9 @@ int lnocc_contract(const lnocc_contract_t *desc, void *stream);
  *   4 products of the learned-guess network (forward and backward)
  *   5 o^3 v^3 ring products of the CCSD residual (exchange and Coulomb rings,
  *     the T1 terms of the stored ladder)
+ *   6 every launch of the classes above whose products run as split bf16
+ *     products (LNOCC_FP32_SPLIT / LNOCC_FP64_SPLIT arithmetic: six bf16
+ *     matrix-core products per product), whatever it computes
  * flops counts 2 M N K per product term (the algorithmic count). */
 typedef struct lnocc_kernel_stats_t {
   int64_t launches;
@@ -388,7 +394,7 @@ typedef struct lnocc_kernel_stats_t {
   double flops;
 } lnocc_kernel_stats_t;
 
-#define LNOCC_KERNEL_CLASSES 6
+#define LNOCC_KERNEL_CLASSES 7
 void lnocc_profile_enable(int on);
 void lnocc_profile_collect(lnocc_kernel_stats_t out[LNOCC_KERNEL_CLASSES]);
 

@@ -29,7 +29,8 @@ enum class Kind : int {
   TriplesW = 3,       // W_ijk^abc for a batch of unique triples
   Mlp = 4,            // learned-guess network layers and their gradients (FP32 only)
   Ring = 5,           // o^3 v^3 ring terms of the CCSD residual (and the ladder's T1 terms)
-  Count = 6
+  Split = 6,          // timing bucket only: every launch with split-bf16 products, any kind
+  Count = 7
 };
 
 // Division by a runtime-invariant divisor via multiply-high (Granlund and

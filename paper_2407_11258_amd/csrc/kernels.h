@@ -38,6 +38,8 @@ hipError_t sub_oovv_into_dint(const double *Goovv, int64_t o, int64_t v, double 
                               hipStream_t s);
 hipError_t combine_r2(double *R2, const double *S, const double *Xc, int64_t o, int64_t v,
                       hipStream_t s);
+// R2 <- its pair-symmetric part, (R2[i][j][a][b] + R2[j][i][b][a]) / 2
+hipError_t pair_symmetrize(double *R2, int64_t o, int64_t v, hipStream_t s);
 // partials[kRedBlocks] <- pieces of sum (2 (ia|jb) - (ib|ja)) (t2 + t1 t1)
 hipError_t energy_partials(const double *Kov, const double *t1, const double *t2, int64_t o,
                            int64_t v, double *partials, hipStream_t s);

@@ -136,6 +136,42 @@ __global__ void k_sub_oovv(const double *__restrict__ G, int64_t o, int64_t v, d
 // X[i][j] at (b, a)) are staged through LDS so that every global access runs
 // along the contiguous index.
 constexpr int kCT = 32;
+// R2[i][j][a][b] and R2[j][i][b][a] <- their mean.  A block takes one pair i <= j
+// and one (a0, b0) tile with its mirror tile (b0, a0) of the partner pair, so every
+// element and its mirror are read and written by the same block (for i = j only
+// the tiles with a0 <= b0, a diagonal tile being its own mirror).
+__global__ void k_pair_symmetrize(double *R2, int64_t o, int64_t v) {
+  __shared__ double P[kCT][kCT + 1], Q[kCT][kCT + 1];   // [r][c]: (a0 + r, b0 + c) / (b0 + r, a0 + c)
+  const int64_t vv = v * v;
+  const int tiles = (int)((v + kCT - 1) / kCT);
+  const int ta = blockIdx.x / tiles, tb = blockIdx.x % tiles;
+  const int64_t a0 = (int64_t)ta * kCT, b0 = (int64_t)tb * kCT;
+  const int64_t npairs = o * (o + 1) / 2;
+  for (int64_t p = blockIdx.y; p < npairs; p += gridDim.y) {
+    // p -> (i, j), i <= j, rows of the upper triangle in order
+    int64_t i = 0, rem = p;
+    while (rem >= o - i) { rem -= o - i; ++i; }
+    const int64_t j = i + rem;
+    if (i == j && ta > tb) continue;          // uniform over the block
+    double *X = R2 + (i * o + j) * vv, *Y = R2 + (j * o + i) * vv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kCT * kCT; e += blockDim.x) {
+      const int r = e / kCT, c = e % kCT;
+      const int64_t a = a0 + r, b = b0 + c, b2 = b0 + r, a2 = a0 + c;
+      P[r][c] = (a < v && b < v) ? X[a * v + b] : 0.0;
+      Q[r][c] = (b2 < v && a2 < v) ? Y[b2 * v + a2] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kCT * kCT; e += blockDim.x) {
+      const int r = e / kCT, c = e % kCT;
+      const int64_t a = a0 + r, b = b0 + c, b2 = b0 + r, a2 = a0 + c;
+      // X(a, b) pairs with Y(b, a) = Q[c][r]; Y(b2, a2) pairs with X(a2, b2) = P[c][r]
+      if (a < v && b < v) X[a * v + b] = 0.5 * (P[r][c] + Q[c][r]);
+      if (b2 < v && a2 < v) Y[b2 * v + a2] = 0.5 * (Q[r][c] + P[c][r]);
+    }
+  }
+}
+
 __global__ void k_combine_r2(double *R2, const double *__restrict__ S, const double *__restrict__ Xc,
                              int64_t o, int64_t v) {
   __shared__ double T[3][kCT][kCT + 1];   // [b - b0][a - a0] of S[j][i], X[j][i], X[i][j]
@@ -556,6 +592,16 @@ hipError_t combine_r2(double *R2, const double *S, const double *Xc, int64_t o, 
   const unsigned pairs = (unsigned)std::min<int64_t>(o * o, 65535);   // grid rows over (i, j)
   hipLaunchKernelGGL(k_combine_r2, dim3(tiles * tiles, pairs), dim3(kEwThreads), 0, s, R2, S, Xc,
                      o, v);
+  return hipGetLastError();
+}
+hipError_t pair_symmetrize(double *R2, int64_t o, int64_t v, hipStream_t s) {
+  if (dry_run()) return hipSuccess;
+  if (o == 0 || v == 0) return hipSuccess;
+  const int tiles = (int)((v + kCT - 1) / kCT);
+  const int64_t npairs = o * (o + 1) / 2;
+  const unsigned rows = (unsigned)std::min<int64_t>(npairs, 65535);
+  hipLaunchKernelGGL(k_pair_symmetrize, dim3(tiles * tiles, rows), dim3(kEwThreads), 0, s, R2, o,
+                     v);
   return hipGetLastError();
 }
 hipError_t energy_partials(const double *Kov, const double *t1, const double *t2, int64_t o,

@@ -150,8 +150,8 @@ struct Readback {
 // has landed, and after_* consumes it.  The batch driver interleaves several
 // of these on one stream, so the host round trip of one fragment overlaps the
 // device work of the others.
-// Reduced modes: ring products in split bf16 while the last step norm exceeds
-// this multiple of the convergence threshold.
+// Reduced modes: residual products in split bf16 until the step norm is within
+// this multiple of the convergence threshold (or stops improving).
 constexpr double kSplitRingFactor = 100.0;
 
 struct CcsdRun {
@@ -171,7 +171,9 @@ struct CcsdRun {
   mutable int polls = 0;
   bool mlp_check = false;      // the first step from the learned start is still to be judged
   double r_mp2 = 0.0;          // first step norm from the MP2 start
-  hipGraphExec_t graph[2] = {nullptr, nullptr};   // captured residual evaluation, FP64 / split ring
+  hipGraphExec_t graph[2] = {nullptr, nullptr};   // captured residual evaluation, FP64 / split
+  bool split = false;          // residual products of the next iteration in split bf16
+  int split_stall = 0;         // iterations in a row without a new minimum step norm
 
   CcsdRun(const Layout &L, const Inputs &in, const lnocc_options_t &opt, hipStream_t s,
           Readback &rb);

@@ -339,6 +339,17 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
                    bool split_ring) {
   const int64_t o = L.dm.o, v = L.dm.v, X = L.dm.X;
   const Prec ring = split_ring ? L.rp : Prec::F64;
+  // The early iterations of the reduced modes also take every sizeable FP64
+  // contraction (the DF products over Q, the T1 dressing, the hole ladder) in
+  // split-bf16 products; tiny products keep FP64 tiles and the matrix-vector path.
+  auto run = [&](GemmDesc &d) {
+    if (split_ring && d.prec == Prec::F64 && d.kind != Kind::LadderBuild) {
+      int64_t K = 0;
+      for (int q = 0; q < d.nseg; ++q) K += d.seg[q].K;
+      if ((int64_t)d.M * d.N >= 65536 && K >= 256) d.prec = L.rp;
+    }
+    return gett(d, s);
+  };
   const int64_t ov = o * v, oo = o * o, vv = v * v, ovv = o * vv, vvv = vv * v, ooo = oo * o;
   const size_t B8 = sizeof(double);
   // --- T1 dressing of the DF factors
@@ -347,14 +358,14 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     d.c_src = L.Boo;
     BATCH_Q(d, X, oo);
     SEG(d, v, 1, 1.0, OPB(OP(L.Bov, v, 0, 1, 0), ov, 0, 0), OP(t1, v, 0, 1, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   {  // B~_ab = B_ab - sum_k t_k^a B_kb
     GemmDesc d = DESC(v, 1, v, 1, L.Btvv, v, 0, 1, 0, 1.0);
     d.c_src = L.Bvv;
     BATCH_Q(d, X, vv);
     SEG(d, o, 1, -1.0, OP(t1, 1, 0, v, 0), OPB(OP(L.Bov, 1, 0, v, 0), ov, 0, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   {  // B~_ai = B_ai + sum_b B_ab t_i^b - sum_k t_k^a B~_ki, stored [Q][i][a]
     GemmDesc d = DESC(o, 1, v, 1, L.Btai, v, 0, 1, 0, 1.0);
@@ -362,7 +373,7 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     BATCH_Q(d, X, ov);
     SEG(d, v, 1, 1.0, OP(t1, v, 0, 1, 0), OPB(OP(L.Bvv, v, 0, 1, 0), vv, 0, 0));
     SEG(d, o, 1, -1.0, OPB(OP(L.Btoo, 1, 0, o, 0), oo, 0, 0), OP(t1, 1, 0, v, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   LN_TRY(diag_sum(L.Btoo, X, o, L.J, s));
   // --- dressed Fock: F~ = Lm h Rm^T + G(B~)
@@ -370,21 +381,21 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
   {
     GemmDesc d = DESC(o, 1, o, 1, L.Foo, o, 0, 1, 0, 1.0);
     SEG(d, v, 1, 1.0, OP(L.hov, v, 0, 1, 0), OP(t1, v, 0, 1, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   LN_TRY(dcopy(L.Fov, L.hov, ov * B8, s));
   LN_TRY(dcopy(L.Fvv, L.hvv, vv * B8, s));
   {
     GemmDesc d = DESC(v, 1, v, 1, L.Fvv, v, 0, 1, 0, 1.0);
     SEG(d, o, 1, -1.0, OP(t1, 1, 0, v, 0), OP(L.hov, 1, 0, v, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   LN_TRY(dcopy(L.Fvo, L.hvo, ov * B8, s));
   {
     GemmDesc d = DESC(v, 1, o, 1, L.Fvo, o, 0, 1, 0, 1.0);
     SEG(d, v, 1, 1.0, OP(L.hvv, v, 0, 1, 0), OP(t1, v, 0, 1, 0));
     SEG(d, o, 1, -1.0, OP(t1, 1, 0, v, 0), OP(L.Foo, 1, 0, o, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   int st = fock_two_electron(L, L.Btoo, L.Bov, L.Btai, L.Btvv, L.J, L.Foo, L.Fov, L.Fvo, L.Fvv,
                              2.0, -1.0, s);
@@ -395,29 +406,29 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
   {  // Y[Q][i][d] = sum_kc u_ki^cd B_Q,kc ; R1 += sum_Qd Y[Q][i][d] B~_Q,ad
     GemmDesc d = DESC(X, 1, ov, v, L.Y1, ov, 0, v, 1, 0.0);
     SEG(d, ov, v, 1.0, OP(L.Bov, ov, 0, v, 1), OP(L.u, vv, 1, ovv, v));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
     d = DESC(o, 1, v, 1, L.R1, v, 0, 1, 0, 1.0);
     SEG(d, X * v, v, 1.0, OP(L.Y1, v, 0, ov, 1), OP(L.Btvv, v, 0, vv, 1));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   {  // Z[Q][k][a] = sum_lc u_kl^ac B_Q,lc ; R1 -= sum_Qk B~_Q,ki Z[Q][k][a]
     GemmDesc d = DESC(X, 1, ov, v, L.Z1, ov, 0, v, 1, 0.0);
     SEG(d, ov, v, 1.0, OP(L.Bov, ov, 0, v, 1), OP(L.u, ovv, v, vv, 1));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
     d = DESC(o, 1, v, 1, L.R1, v, 0, 1, 0, 1.0);
     SEG(d, X * o, o, -1.0, OP(L.Btoo, 1, 0, oo, o), OP(L.Z1, 1, 0, ov, v));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   {  // R1 += sum_kc u_ik^ac F~_kc
     GemmDesc d = DESC(ov, v, 1, 1, L.R1, v, 1, 0, 0, 1.0);
     SEG(d, ov, v, 1.0, OP(L.u, ovv, v, vv, 1), OP(L.Fov, 0, 0, v, 1));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   // --- doubles residual: R2 <- (ai|bj)~
   {
     GemmDesc d = DESC(ov, v, ov, v, L.R2, ovv, v, vv, 1, 0.0);
     SEG(d, X, 1, 1.0, OP(L.Btai, v, 1, ov, 0), OP(L.Btai, v, 1, ov, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   // Particle-particle ladder R_ij^ab = sum_cd t_ij^cd (ac|bd)~ through
   // S = R^ab + R^ba = sum_cd (t^cd + t^dc) (ac|bd) (symmetric in ij and ab) and
@@ -442,7 +453,7 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
       SEG(d, vv, 1, 1.0, OP((const double *)L.Lst, vv, 0, 1, 0), OP(L.Tsa, vv, 0, 1, 0));
       d.kind = Kind::LadderContract;
       d.prec = L.lp;
-      LN_TRY(gett(d, s));
+      LN_TRY(run(d));
     }
     LN_TRY(unpack_ladder(L.SA, o, v, L.chunk_a, L.lrows, L.R2, s));
     (void)esz;
@@ -451,15 +462,15 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
       SEG(d, vv, v, 1.0, OP(t2, vv, 0, v, 1), OP(L.Gkc, vvv, v, vv, 1));
       d.kind = Kind::Ring;
       d.prec = ring;
-      LN_TRY(gett(d, s));
+      LN_TRY(run(d));
     }
     {  // W[ij][k][l] = sum_cd t_ij^cd (kc|ld) ; Y[ij][k][b] = sum_l W[ij][k][l] t_l^b
       GemmDesc d = DESC(oo, 1, oo, o, L.Wl, oo, 0, o, 1, 0.0);
       SEG(d, vv, v, 1.0, OP(t2, vv, 0, v, 1), OP(L.Kov, ovv, v, ov, 1));
-      LN_TRY(gett(d, s));
+      LN_TRY(run(d));
       d = DESC(ooo, 1, v, 1, L.Yl, v, 0, 1, 0, 0.0);
       SEG(d, o, 1, 1.0, OP(L.Wl, o, 0, 1, 0), OP(t1, 1, 0, v, 0));
-      LN_TRY(gett(d, s));
+      LN_TRY(run(d));
     }
     {  // R2[ij][a][b] += -t1^T (Z - Y)_ij - Z_ji^T t1, batched over (i, j)
       GemmDesc d = DESC(v, 1, v, 1, L.R2, v, 0, 1, 0, 1.0);
@@ -470,7 +481,7 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
       SEG(d, o, 1, -1.0, OP(t1, 1, 0, v, 0), OPB(OP(L.Zl, 1, 0, v, 0), oo * v, ov, 0));
       SEG(d, o, 1, 1.0, OP(t1, 1, 0, v, 0), OPB(OP(L.Yl, 1, 0, v, 0), oo * v, ov, 0));
       SEG(d, o, 1, -1.0, OPB(OP(L.Zl, 1, 0, v, 0), ov, oo * v, 0), OP(t1, 1, 0, v, 0));
-      LN_TRY(gett(d, s));
+      LN_TRY(run(d));
     }
   } else {
     const char *bvv = (const char *)L.Btvv;
@@ -486,31 +497,31 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
       d.kind = Kind::LadderBuild;
       d.prec = L.lp;
       d.c_type = L.lpt;
-      LN_TRY(gett(d, s));
+      LN_TRY(run(d));
       // SA[r][a][b] = sum_cd Tsa[r][cd] g[a][b][cd], rows (a, b < a1) of the block
       d = DESC(na * a1, a1, oo, 1, L.SA + a0 * v, v, 1, vv, 0, 0.0);
       SEG(d, vv, 1, 1.0, OP(L.chunk, vvv, vv, 1, 0), OP(L.Tsa, vv, 0, 1, 0));
       d.kind = Kind::LadderContract;
       d.prec = L.lp;
-      LN_TRY(gett(d, s));
+      LN_TRY(run(d));
     }
     LN_TRY(unpack_ladder(L.SA, o, v, 0, vv, L.R2, s));
   }
   {  // hole-hole ladder: W_klij = (ki|lj)~ + sum_cd (kc|ld) t_ij^cd ; R2 += sum_kl t_kl^ab W_klij
     GemmDesc d = DESC(oo, o, oo, o, L.Wkl, ooo, o, oo, 1, 0.0);
     SEG(d, X, 1, 1.0, OP(L.Btoo, o, 1, oo, 0), OP(L.Btoo, o, 1, oo, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
     d = DESC(oo, o, oo, 1, L.Wkl, ooo, oo, 1, 0, 1.0);
     SEG(d, vv, v, 1.0, OP(L.Kov, ovv, v, ov, 1), OP(t2, vv, 0, v, 1));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
     d = DESC(oo, 1, vv, 1, L.R2, vv, 0, 1, 0, 1.0);
     SEG(d, oo, 1, 1.0, OP(L.Wkl, 1, 0, oo, 0), OP(t2, 1, 0, vv, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   {  // (ki|ac)~
     GemmDesc d = DESC(oo, 1, vv, 1, L.Goovv, vv, 0, 1, 0, 0.0);
     SEG(d, X, 1, 1.0, OP(L.Btoo, 1, 0, oo, 0), OP(L.Btvv, 1, 0, vv, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   // exchange-type ring: Cint_kiac = (ki|ac)~ - 1/2 sum_ld t_li^ad (kd|lc); X_ijab = sum_kc t_kj^bc Cint_kiac
   {
@@ -519,53 +530,57 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     SEG(d, ov, v, -0.5, OP(t2, vv, v, ovv, 1), OP(L.Q2, ovv, v, vv, 1));
     d.kind = Kind::Ring;
     d.prec = ring;
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
     d = DESC(ov, v, ov, v, L.Xc, ovv, v, vv, 1, 0.0);
     SEG(d, ov, v, 1.0, OP(L.Cint, vv, v, ovv, 1), OP(t2, vv, v, ovv, 1));
     d.kind = Kind::Ring;
     d.prec = ring;
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   // Coulomb-type ring: Dint_iakc = 2 (ai|kc)~ - (ki|ac)~ + 1/2 sum_ld u_il^ad L_ldkc ;
   // S = 1/2 sum_kc u_jk^bc Dint_iakc
   {
     GemmDesc d = DESC(ov, 1, ov, 1, L.Dint, ov, 0, 1, 0, 0.0);
     SEG(d, X, 1, 2.0, OP(L.Btai, 1, 0, ov, 0), OP(L.Bov, 1, 0, ov, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
     LN_TRY(sub_oovv_into_dint(L.Goovv, o, v, L.Dint, s));
     d = DESC(ov, v, ov, 1, L.Dint, ovv, ov, 1, 0, 1.0);
     SEG(d, ov, v, 0.5, OP(L.u, ovv, v, vv, 1), OP(L.Lov, 1, 0, ovv, ov));
     d.kind = Kind::Ring;
     d.prec = ring;
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
     d = DESC(ov, v, ov, v, L.S, ovv, v, vv, 1, 0.0);
     SEG(d, ov, v, 0.5, OP(L.Dint, ovv, ov, v, 1), OP(L.u, ovv, v, vv, 1));
     d.kind = Kind::Ring;
     d.prec = ring;
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   // Fock-type terms: F'_bc = F~_bc - sum_kld u_kl^bd (ld|kc), F'_kj = F~_kj + sum_lcd u_lj^cd (kd|lc)
   LN_TRY(dcopy(L.Fvvp, L.Fvv, vv * B8, s));
   {
     GemmDesc d = DESC(v, 1, v, 1, L.Fvvp, v, 0, 1, 0, 1.0);
     SEG(d, oo * v, v, -1.0, OP(L.u, v, 0, vv, 1), OP(L.Pvv, 1, 0, vv, v));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   LN_TRY(dcopy(L.Foop, L.Foo, oo * B8, s));
   {
     GemmDesc d = DESC(o, 1, o, 1, L.Foop, o, 0, 1, 0, 1.0);
     SEG(d, o * vv, vv, 1.0, OP(L.Q2, ovv, 0, vv, 1), OP(L.u, vv, 0, ovv, 1));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   {  // S += sum_c t_ij^ac F'_bc - sum_k t_ik^ab F'_kj
     GemmDesc d = DESC(oo * v, 1, v, 1, L.S, v, 0, 1, 0, 1.0);
     SEG(d, v, 1, 1.0, OP(t2, v, 0, 1, 0), OP(L.Fvvp, v, 0, 1, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
     d = DESC(o * vv, vv, o, 1, L.S, ovv, 1, vv, 0, 1.0);
     SEG(d, o, 1, -1.0, OP(t2, ovv, 1, vv, 0), OP(L.Foop, 1, 0, o, 0));
-    LN_TRY(gett(d, s));
+    LN_TRY(run(d));
   }
   LN_TRY(combine_r2(L.R2, L.S, L.Xc, o, v, s));
+  // The residual of pair-symmetric amplitudes is pair-symmetric; rounding (of
+  // split products above all) breaks that slightly, and an antisymmetric part
+  // left in R2 would pass into t2, where no later iteration removes it.
+  LN_TRY(pair_symmetrize(L.R2, o, v, s));
   return LNOCC_OK;
 }
 
@@ -653,19 +668,19 @@ bool Readback::ok() const {
 CcsdRun::CcsdRun(const Layout &L_, const Inputs &in_, const lnocc_options_t &opt_, hipStream_t s_,
                  Readback &rb_)
     : L(&L_), in(in_), opt(opt_), s(s_), rb(&rb_), host(rb_.host),
-      G((size_t)L_.diis_m * L_.diis_m, 0.0) {}
+      G((size_t)L_.diis_m * L_.diis_m, 0.0), split(L_.rp != Prec::F64) {}
 
 CcsdRun::~CcsdRun() {
   for (hipGraphExec_t g : graph)
     if (g) (void)hipGraphExecDestroy(g);
 }
 
-// Ring products of the reduced modes: split bf16 (FP32-class) while the step
-// norm is far above the convergence threshold, FP64 for the last iterations,
-// so the rounding of the split products never sets the final residual.
-bool CcsdRun::split_ring() const {
-  return L->rp != Prec::F64 && prev > kSplitRingFactor * in.conv_tol;
-}
+// Reduced modes: the residual products run as split bf16 (FP32-class) in the
+// early iterations and in FP64 from the first iteration whose step norm is
+// within kSplitRingFactor of the threshold, or that fails twice in a row to
+// reach a new minimum (the rounding of the split products then limits the
+// step); the last iterations are FP64, so that rounding never sets the result.
+bool CcsdRun::split_ring() const { return split; }
 
 // The residual evaluation enqueues the same ~100 launches with the same
 // arguments in every iteration of a solve (only the amplitude values change),
@@ -841,6 +856,18 @@ int CcsdRun::after_iteration() {
   if (!std::isfinite(r2) || !std::isfinite(host[1 + (use_diis ? slot : 0)])) {
     note_error("non-finite residual norm or DIIS overlap at iteration %d", it);
     return LNOCC_ENUMERIC;
+  }
+  // end of the split phase (the DIIS subspace keeps its vectors: restarting it
+  // here measured two more iterations)
+  if (split) {
+    split_stall = (out.residual < 0.9 * best) ? 0 : split_stall + 1;
+    if (out.residual <= kSplitRingFactor * in.conv_tol || split_stall >= 2) {
+      split = false;
+      if (log_enabled()) {
+        std::fprintf(stderr, "lnocc: FP64 residual products from iteration %d on\n", it + 1);
+        std::fflush(stderr);
+      }
+    }
   }
   if (out.residual <= in.conv_tol) {
     LN_TRY(scatter_vec(xs, o, v, in.t1, in.t2, s));

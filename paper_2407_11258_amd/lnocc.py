@@ -93,8 +93,9 @@ class lnocc_kernel_stats_t(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("flops", C.c_double)]
 
 
-LNOCC_KERNEL_CLASSES = 6
-KERNEL_CLASS_NAMES = ("other", "ladder_build", "ladder_contract", "triples_w", "mlp", "ring")
+LNOCC_KERNEL_CLASSES = 7
+KERNEL_CLASS_NAMES = ("other", "ladder_build", "ladder_contract", "triples_w", "mlp", "ring",
+                      "split")
 
 EXPORTS = ("lnocc_default_options", "lnocc_status_string", "lnocc_last_error",
            "lnocc_workspace_bytes",
