@@ -368,7 +368,12 @@ typedef struct lnocc_contract_t {
                                     rows x columns, 7: 128x128 with the products of
                                     LNOCC_FP32_SPLIT, 8: 160x160, 9: 128x160 with split
                                     products (5..7 and 9 for LNOCC_FP32 operands only, 8 for
-                                    LNOCC_FP64 only; ignored otherwise) */
+                                    LNOCC_FP64 only; ignored otherwise), 10: 128x128 with
+                                    split products staged in 4x4 blocks (LNOCC_FP32 and the
+                                    split precisions, when every 4-element group along k, or
+                                    along the rows of an operand contiguous in its rows, is
+                                    contiguous and aligned and M, N, K are multiples of 4;
+                                    ignored otherwise) */
 } lnocc_contract_t;
 
 int lnocc_contract(const lnocc_contract_t *desc, void *stream);

@@ -840,7 +840,7 @@ int lnocc_contract(const lnocc_contract_t *c, void *stream) {
   if (c->precision < 0 || c->precision > 4) return LNOCC_EINVAL;
   d.prec = (Prec)c->precision;
   d.c_type = 0;
-  if (c->tile < 0 || c->tile > 9) return LNOCC_EINVAL;
+  if (c->tile < 0 || c->tile > 10) return LNOCC_EINVAL;
   d.tile_hint = c->tile;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = gett(d, s);

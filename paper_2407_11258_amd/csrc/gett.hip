@@ -135,13 +135,15 @@ using Wide160S = Cfg<128, 160, 4, 2>;
 // Tile ids of the launcher and the autotuner (rows x columns per workgroup).
 // Id 6 is the 128 x 128 tile with FP32 products evaluated as split bf16
 // products (an arithmetic choice for FP32 contractions, same accuracy class).
-constexpr int kTileBM[9] = {128, 128, 128, 32, 128, 256, 128, 160, 128};
-constexpr int kTileBN[9] = {128, 80, 64, 32, 160, 128, 128, 160, 160};
-constexpr int kTileSplit = 6, kTileSq160 = 7, kTileSplit160 = 8;
-// tiles 4..6 and 8 serve FP32 operands only, tile 7 FP64 only
+constexpr int kTileBM[10] = {128, 128, 128, 32, 128, 256, 128, 160, 128, 128};
+constexpr int kTileBN[10] = {128, 80, 64, 32, 160, 128, 128, 160, 160, 128};
+constexpr int kTileSplit = 6, kTileSq160 = 7, kTileSplit160 = 8, kTileSplitV = 9;
+// tiles 4..6 and 8 serve FP32 operands only, tile 7 FP64 only, tile 9 (split
+// products with 4 x 4 staging) FP32 and the split modes when split_v4_ok
 inline bool tile_valid(int t, Prec p) {
-  if (t < 0 || t > 8) return false;
+  if (t < 0 || t > 9) return false;
   if (t < 4) return true;
+  if (t == kTileSplitV) return p == Prec::F32 || p == Prec::F32S || p == Prec::F64S;
   return t == kTileSq160 ? p == Prec::F64 : p == Prec::F32;
 }
 
@@ -469,6 +471,76 @@ __device__ inline double4_t regroup_rows_f64(const double4_t &a, int lane) {
   return out;
 }
 
+// Epilogue of the tile kernels: raw split-K partials, or the final store of
+// C (vector stores of four adjacent rows when c_vec4 allows).
+template <class M, class C>
+__device__ inline void store_tile(const GemmDesc &d, typename M::Acc (&acc)[C::MI][C::NI], int m0,
+                                  int n0, int wm, int wn, int lane, const BatchIdx &bi, int64_t id,
+                                  int split) {
+  if (d.splitk) {   // raw partial sums, row-major [split][M][N]
+    double *pw = d.splitk + (int64_t)split * d.M * d.N;
+#pragma unroll
+    for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * (C::BM / C::WM) + i * 16 + M::row(lane, r);
+        if (m >= d.M) continue;
+#pragma unroll
+        for (int j = 0; j < C::NI; ++j) {
+          const int n = n0 + wn * (C::BN / C::WN) + j * 16 + lane % 16;
+          if (n < d.N) pw[(int64_t)m * d.N + n] = (double)acc[i][j][r];
+        }
+      }
+    return;
+  }
+  const int esz = d.c_type == 0 ? 8 : (d.c_type == 1 ? 4 : 2);
+  const int64_t cbat = (bi.i0 * d.c_b0 + bi.i1 * d.c_b1 + bi.i2 * d.c_b2 + id * d.c_bid) * esz;
+  char *pc = (char *)d.c + cbat;
+  const char *ps = d.c_src ? (const char *)d.c_src + cbat : pc;
+  int64_t coff[C::NI];
+  bool cok[C::NI];
+#pragma unroll
+  for (int j = 0; j < C::NI; ++j) {
+    const int n = n0 + wn * (C::BN / C::WN) + j * 16 + lane % 16;
+    cok[j] = n < d.N;
+    coff[j] = cok[j] ? two_index_off(d.ndiv, (uint32_t)n, d.c_no, d.c_ni) : 0;
+  }
+  if (d.c_vec4) {
+    // rows 4 (lane / 16) + s, s = 0..3, of one column are adjacent in C: one
+    // 16- or 32-byte access per column instead of four scattered ones
+#pragma unroll
+    for (int i = 0; i < C::MI; ++i) {
+      const int m = m0 + wm * (C::BM / C::WM) + i * 16 + 4 * (lane / 16);
+      const bool mok = m < d.M;
+      const int64_t moff = mok ? two_index_off(d.mdiv, (uint32_t)m, d.c_mo, d.c_mi) : 0;
+#pragma unroll
+      for (int j = 0; j < C::NI; ++j) {
+        if constexpr (std::is_same<typename M::Acc, double4_t>::value) {
+          const double4_t w = regroup_rows_f64(acc[i][j], lane);   // whole wave
+          if (mok && cok[j]) store_out4(d, pc, ps, moff + coff[j], w);
+        } else {
+          if (mok && cok[j]) store_out4(d, pc, ps, moff + coff[j], acc[i][j]);
+        }
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < C::MI; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm * (C::BM / C::WM) + i * 16 + M::row(lane, r);
+      if (m >= d.M) continue;
+      const int64_t moff = two_index_off(d.mdiv, (uint32_t)m, d.c_mo, d.c_mi);
+#pragma unroll
+      for (int j = 0; j < C::NI; ++j) {
+        if (!cok[j]) continue;
+        store_out(d, pc, ps, moff + coff[j], (double)acc[i][j][r]);
+      }
+    }
+  }
+}
+
 // Workgroups per CU the register allocation must allow: two for the 8-wave FP64
 // tiles (at most 128 VGPRs: a few row offsets spill), so that one workgroup's
 // barrier and LDS stage overlap the other's matrix ops.  Measured: the FP64 matrix
@@ -554,68 +626,154 @@ void gett_kernel(GemmDesc d, int tiles_m, int slices_per_split) {
     }
   }
 
-  if (d.splitk) {   // raw partial sums, row-major [split][M][N]
-    double *pw = d.splitk + (int64_t)split * d.M * d.N;
+  store_tile<M, C>(d, acc, m0, n0, wm, wn, lane, bi, id, split);
+}
+
+// Split-bf16 products with 4 x 4 staging blocks: 128 x 128 outputs per
+// workgroup of 4 waves (64 x 64 each: 4 x 4 blocks of 16 x 16, so every LDS
+// fragment feeds four matrix ops of each of the six part products), one LDS
+// buffer of three bf16 planes per operand (60 KB, two workgroups per CU: one
+// stages while the other multiplies).  Each thread stages one 4-row x 4-k block
+// of each operand per 32-k slice: four 4-element vector loads (along k when the
+// operand is contiguous along k, else along its rows, then transposed in
+// registers), split, and one 8-byte LDS store per row and plane.  The host
+// launches it only when every 4-element group is contiguous and aligned
+// (split_v4_ok).
+using SplitV = Cfg<128, 128, 2, 2>;
+
+template <class E> struct Vec4Of;
+template <> struct Vec4Of<float> { using V = float4_t; };
+template <> struct Vec4Of<double> { using V = double4_t; };
+
+template <class E>
+struct Block4 {
+  static constexpr int R = 128, BK = 32;
+  using V = typename Vec4Of<E>::V;
+  int64_t roff[4];
+  bool rok;
+  // k-contiguous operands: 8 consecutive threads cover the 32 k of a row group
+  // (coalesced loads, conflict-free 8-byte LDS stores); row-contiguous ones:
+  // 32 consecutive threads cover the 128 rows at one k group
+  __device__ static int rg(bool kfast) { return kfast ? threadIdx.x / 8 : threadIdx.x % 32; }
+  __device__ static int kg(bool kfast) { return kfast ? threadIdx.x % 8 : threadIdx.x / 32; }
+  __device__ void init(const GOperand &op, const FastDiv &rdiv, bool kfast, int nrows, int row0) {
+    const int r0 = row0 + 4 * rg(kfast);
+    rok = r0 < nrows;   // nrows is a multiple of 4
 #pragma unroll
-    for (int i = 0; i < C::MI; ++i)
+    for (int j = 0; j < 4; ++j)
+      roff[j] = rok ? two_index_off(rdiv, (uint32_t)(r0 + j), op.s_ro, op.s_ri) : 0;
+  }
+  // reg[4 j + c] = element (row j, k c) of the block
+  __device__ void load(const E *__restrict__ base, const GOperand &op, const FastDiv &kdiv,
+                       bool kfast, int K, int k0, E (&reg)[16], bool &ok) const {
+    const int k = k0 + 4 * kg(kfast);
+    ok = rok && k < K;   // K is a multiple of 4
+    if (kfast) {
+      const int64_t ko = ok ? two_index_off(kdiv, (uint32_t)k, op.s_ko, op.s_ki) : 0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * (C::BM / C::WM) + i * 16 + M::row(lane, r);
-        if (m >= d.M) continue;
+      for (int j = 0; j < 4; ++j) {
+        const V v = *(const V *)(base + (ok ? roff[j] + ko : 0));
 #pragma unroll
-        for (int j = 0; j < C::NI; ++j) {
-          const int n = n0 + wn * (C::BN / C::WN) + j * 16 + lane % 16;
-          if (n < d.N) pw[(int64_t)m * d.N + n] = (double)acc[i][j][r];
-        }
+        for (int c = 0; c < 4; ++c) reg[4 * j + c] = v[c];
       }
-    return;
-  }
-  const int esz = d.c_type == 0 ? 8 : (d.c_type == 1 ? 4 : 2);
-  const int64_t cbat = (bi.i0 * d.c_b0 + bi.i1 * d.c_b1 + bi.i2 * d.c_b2 + id * d.c_bid) * esz;
-  char *pc = (char *)d.c + cbat;
-  const char *ps = d.c_src ? (const char *)d.c_src + cbat : pc;
-  int64_t coff[C::NI];
-  bool cok[C::NI];
+    } else {
 #pragma unroll
-  for (int j = 0; j < C::NI; ++j) {
-    const int n = n0 + wn * (C::BN / C::WN) + j * 16 + lane % 16;
-    cok[j] = n < d.N;
-    coff[j] = cok[j] ? two_index_off(d.ndiv, (uint32_t)n, d.c_no, d.c_ni) : 0;
-  }
-  if (d.c_vec4) {
-    // rows 4 (lane / 16) + s, s = 0..3, of one column are adjacent in C: one
-    // 16- or 32-byte access per column instead of four scattered ones
+      for (int c = 0; c < 4; ++c) {
+        const int64_t ko = ok ? two_index_off(kdiv, (uint32_t)(k + c), op.s_ko, op.s_ki) : 0;
+        const V v = *(const V *)(base + (ok ? roff[0] + ko : 0));
 #pragma unroll
-    for (int i = 0; i < C::MI; ++i) {
-      const int m = m0 + wm * (C::BM / C::WM) + i * 16 + 4 * (lane / 16);
-      const bool mok = m < d.M;
-      const int64_t moff = mok ? two_index_off(d.mdiv, (uint32_t)m, d.c_mo, d.c_mi) : 0;
-#pragma unroll
-      for (int j = 0; j < C::NI; ++j) {
-        if constexpr (std::is_same<typename M::Acc, double4_t>::value) {
-          const double4_t w = regroup_rows_f64(acc[i][j], lane);   // whole wave
-          if (mok && cok[j]) store_out4(d, pc, ps, moff + coff[j], w);
-        } else {
-          if (mok && cok[j]) store_out4(d, pc, ps, moff + coff[j], acc[i][j]);
-        }
-      }
-    }
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i < C::MI; ++i) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = m0 + wm * (C::BM / C::WM) + i * 16 + M::row(lane, r);
-      if (m >= d.M) continue;
-      const int64_t moff = two_index_off(d.mdiv, (uint32_t)m, d.c_mo, d.c_mi);
-#pragma unroll
-      for (int j = 0; j < C::NI; ++j) {
-        if (!cok[j]) continue;
-        store_out(d, pc, ps, moff + coff[j], (double)acc[i][j][r]);
+        for (int j = 0; j < 4; ++j) reg[4 * j + c] = v[j];
       }
     }
   }
+  template <int LD, int PS>
+  __device__ static void store(uint16_t *lds, bool kfast, const E (&reg)[16], bool ok,
+                               double scale) {
+    const int row = 4 * rg(kfast), kk = 4 * kg(kfast);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint16_t h[4], m[4], l[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float x = ok ? (float)(scale * (double)reg[4 * j + c]) : 0.0f;
+        split3(x, h[c], m[c], l[c]);
+      }
+      const int o = (row + j) * LD + kk;
+      *(uint2 *)(lds + o) = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                       (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+      *(uint2 *)(lds + PS + o) = make_uint2((uint32_t)m[0] | ((uint32_t)m[1] << 16),
+                                            (uint32_t)m[2] | ((uint32_t)m[3] << 16));
+      *(uint2 *)(lds + 2 * PS + o) = make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16),
+                                                (uint32_t)l[2] | ((uint32_t)l[3] << 16));
+    }
+  }
+};
+
+template <class M, int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void gett_split_v4(GemmDesc d, int tiles_m, int slices_per_split) {
+  using C = SplitV;
+  using E = typename M::T;
+  constexpr int BK = 32, LD = BK + 8, SZ = C::BM * LD;   // both operands 128 rows
+  __shared__ __attribute__((aligned(16))) uint16_t As[3 * SZ];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[3 * SZ];
+
+  const int tile = blockIdx.x;
+  const int tm = tile % tiles_m, tn = tile / tiles_m;
+  const int m0 = tm * C::BM, n0 = tn * C::BN;
+  const BatchIdx bi = decode_batch(d, blockIdx.y);
+  const int64_t id = blockIdx.y;
+  const int split = blockIdx.z;
+  const int q0 = split * slices_per_split, q1 = q0 + slices_per_split;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave / C::WN, wn = wave % C::WN;
+
+  typename M::Acc acc[C::MI][C::NI];
+#pragma unroll
+  for (int i = 0; i < C::MI; ++i)
+#pragma unroll
+    for (int j = 0; j < C::NI; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+  int qbase = 0;
+  for (int sg = 0; sg < d.nseg; ++sg) {
+    const GSegment &S = d.seg[sg];
+    const int ns = (S.K + BK - 1) / BK;
+    const int lo = max(q0, qbase) - qbase, hi = min(q1, qbase + ns) - qbase;
+    qbase += ns;
+    if (lo >= hi) continue;
+    const E *pa = (const E *)S.a.p + bi.i0 * S.a.b0 + bi.i1 * S.a.b1 + bi.i2 * S.a.b2 + id * S.a.bid;
+    const E *pb = (const E *)S.b.p + bi.i0 * S.b.b0 + bi.i1 * S.b.b1 + bi.i2 * S.b.b2 + id * S.b.bid;
+    const bool akf = S.a_kfast != 0, bkf = S.b_kfast != 0;
+    Block4<E> sa, sb;
+    sa.init(S.a, d.mdiv, akf, d.M, m0);
+    sb.init(S.b, d.ndiv, bkf, d.N, n0);
+    E ra[16], rb[16];
+    bool oka, okb;
+    sa.load(pa, S.a, S.kdiv, akf, S.K, lo * BK, ra, oka);
+    sb.load(pb, S.b, S.kdiv, bkf, S.K, lo * BK, rb, okb);
+    __syncthreads();   // the previous segment's last slice has been read
+    Block4<E>::template store<LD, SZ>(As, akf, ra, oka, S.scale);
+    Block4<E>::template store<LD, SZ>(Bs, bkf, rb, okb, 1.0);
+    __syncthreads();
+    for (int q = lo; q < hi; ++q) {
+      const bool more = q + 1 < hi;
+      if (more) {
+        sa.load(pa, S.a, S.kdiv, akf, S.K, (q + 1) * BK, ra, oka);
+        sb.load(pb, S.b, S.kdiv, bkf, S.K, (q + 1) * BK, rb, okb);
+      }
+      mma_slice_impl<M, C, LD, LD, SZ, SZ>(As, Bs, lane, wm, wn, acc);
+      if (more) {
+        __syncthreads();   // every wave has read the slice
+        Block4<E>::template store<LD, SZ>(As, akf, ra, oka, S.scale);
+        Block4<E>::template store<LD, SZ>(Bs, bkf, rb, okb, 1.0);
+        __syncthreads();
+      }
+    }
+  }
+  store_tile<M, C>(d, acc, m0, n0, wm, wn, lane, bi, id, split);
 }
 
 // Matrix-vector products (N = 1, one segment, FP64, no batch):
@@ -915,6 +1073,51 @@ template <class C>
 void launch_f64(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
   launch_kind<ModeF64, C>(d, grid, tiles_m, sps, stream);
 }
+template <class M>
+void launch_split_v4_kind(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
+  switch (d.kind) {
+    case Kind::LadderContract:
+      hipLaunchKernelGGL((gett_split_v4<M, 2>), grid, dim3(256), 0, stream, d, tiles_m, sps); break;
+    case Kind::TriplesW:
+      hipLaunchKernelGGL((gett_split_v4<M, 3>), grid, dim3(256), 0, stream, d, tiles_m, sps); break;
+    case Kind::Ring:
+      hipLaunchKernelGGL((gett_split_v4<M, 5>), grid, dim3(256), 0, stream, d, tiles_m, sps); break;
+    default:
+      hipLaunchKernelGGL((gett_split_v4<M, 0>), grid, dim3(256), 0, stream, d, tiles_m, sps); break;
+  }
+}
+void launch_split_v4(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
+  if (d.prec == Prec::F64S) launch_split_v4_kind<ModeF64S>(d, grid, tiles_m, sps, stream);
+  else launch_split_v4_kind<ModeF32S>(d, grid, tiles_m, sps, stream);
+}
+
+// gett_split_v4 stages 4 x 4 operand blocks with 4-element vector loads: every
+// 4-element group (along k for a k-contiguous operand, along its rows
+// otherwise) must be contiguous and aligned, and M, N and every K multiples of 4.
+bool split_v4_ok(const GemmDesc &d) {
+  if (d.prec != Prec::F32 && d.prec != Prec::F32S && d.prec != Prec::F64S) return false;
+  if (d.M % 4 || d.N % 4) return false;
+  const int64_t esz = d.prec == Prec::F64S ? 8 : 4;
+  auto al = [](int64_t x) { return x % 4 == 0; };
+  auto op_ok = [&](const GOperand &o, int rows_i, int Ki, bool kfast) {
+    if (((uintptr_t)o.p) % (4 * esz)) return false;
+    if (!al(o.b0) || !al(o.b1) || !al(o.b2) || !al(o.bid)) return false;
+    if (kfast) {
+      const bool kg = Ki == 1 ? o.s_ko == 1 : (o.s_ki == 1 && Ki % 4 == 0 && al(o.s_ko));
+      return kg && al(o.s_ro) && (rows_i == 1 || al(o.s_ri));
+    }
+    const bool rg = rows_i == 1 ? o.s_ro == 1 : (o.s_ri == 1 && rows_i % 4 == 0 && al(o.s_ro));
+    return rg && al(o.s_ko) && (Ki == 1 || al(o.s_ki));
+  };
+  for (int q = 0; q < d.nseg; ++q) {
+    const GSegment &S = d.seg[q];
+    if (S.K % 4) return false;
+    if (!op_ok(S.a, d.Mi, S.Ki, contiguous_along_k(S.a, S.Ki))) return false;
+    if (!op_ok(S.b, d.Ni, S.Ki, contiguous_along_k(S.b, S.Ki))) return false;
+  }
+  return true;
+}
+
 template <class C>
 void launch(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
   switch (d.prec) {
@@ -956,13 +1159,14 @@ void install_splitk_scratch(double *p, size_t elems) {
 // ---------------------------------------------------------------- autotuning
 // Candidate c = (tile, split rule): tiles 128x128, 128x80, 128x64, 32x32 (and,
 // for FP32 products, 128x160, 256x128, and 128x128 and 128x160 with split bf16 products;
-// for FP64 products, 160x160);
+// for FP64 products, 160x160; for FP32 and split products whose operands allow it,
+// the 4 x 4-staged split tile);
 // split rules: the cost-model split, no split, twice the cost-model split.  While a
 // candidate is active every launch is timed with events under its shape key;
 // tune_commit() keeps, per key, the fastest candidate's (tile, split count),
 // which later launches of that shape use instead of the heuristic.
 namespace {
-constexpr int kTileCands = 9, kSplitRules = 3;
+constexpr int kTileCands = 10, kSplitRules = 3;
 struct TilePlan { int tile; int nsplit; };
 std::mutex g_plan_mu;
 std::map<std::string, TilePlan> g_plans;
@@ -1074,6 +1278,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   // k per LDS slice: 32 for the bf16 matrix-core arithmetics, else 16
   auto tile_bk = [&](int t) {
     return (d.prec == Prec::BF16 || d.prec == Prec::F32S || d.prec == Prec::F64S || t == kTileSplit ||
+            t == kTileSplitV ||
             t == kTileSplit160) ? 32 : 16;
   };
   int slices16 = 0, slices32 = 0;
@@ -1187,6 +1392,18 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   };
   // the ladder contraction (long K, large output) of the FP32 modes: split products
   if (d.prec == Prec::F32 && d.kind == Kind::LadderContract && tile != 3) tile = kTileSplit;
+  // FP32 split products with k-contiguous operands take the 4 x 4-staged kernel
+  // (measured: 4096^3 145 against 111 TFLOP/s, the ladder contraction 101 against
+  // 92); FP64-operand split products stay on the 8-wave tile, where the staged
+  // kernel's single LDS buffer exposes the longer FP64 loads (94 against 96), and
+  // so do row-contiguous operands (92 against 111); the autotuner tries both
+  const bool v4 = split_v4_ok(d);
+  bool all_kfast = true;
+  for (int q = 0; q < d.nseg; ++q)
+    all_kfast = all_kfast && contiguous_along_k(d.seg[q].a, d.seg[q].Ki) &&
+                contiguous_along_k(d.seg[q].b, d.seg[q].Ki);
+  if (v4 && all_kfast && tile != 3 && (d.prec == Prec::F32S || tile == kTileSplit))
+    tile = kTileSplitV;
   // FP64 with 160 x 160 tiles when the cost model (rounds of one workgroup per
   // CU x slices, plus partial sums) prefers them
   auto model = [&](int t, int ns) {
@@ -1200,7 +1417,9 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
       d.kind != Kind::LadderBuild &&
       model(kTileSq160, heuristic_split(kTileSq160)) < 0.95 * model(tile, heuristic_split(tile)))
     tile = kTileSq160;
-  if (d.tile_hint > 0 && tile_valid(d.tile_hint - 1, d.prec)) tile = d.tile_hint - 1;
+  if (d.tile_hint > 0 && tile_valid(d.tile_hint - 1, d.prec) &&
+      (d.tile_hint - 1 != kTileSplitV || v4))
+    tile = d.tile_hint - 1;
   int nsplit = heuristic_split(tile);
   // autotuning: a probe pass only collects keys; a candidate overrides the
   // choice (and is timed); otherwise a stored plan for this shape is used
@@ -1216,7 +1435,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
     }
     // the FP32-only tiles stand in for the heuristic choice in other precisions
     auto set_tile = [&](int t) {
-      if (tile_valid(t, d.prec)) tile = t;
+      if (tile_valid(t, d.prec) && (t != kTileSplitV || v4)) tile = t;
     };
     if (g_cand >= 0) {
       cand = g_cand;
@@ -1280,6 +1499,12 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
       launch_kind<ModeF32S, Wide160S>(e, grid, tiles_m, sps, stream);
       break;
     }
+    case kTileSplitV: {
+      GemmDesc e = d;
+      if (e.prec == Prec::F32) e.prec = Prec::F32S;
+      launch_split_v4(e, grid, tiles_m, sps, stream);
+      break;
+    }
     default: launch<Big>(d, grid, tiles_m, sps, stream); break;
   }
   hipError_t err = hipGetLastError();
@@ -1312,13 +1537,15 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
                     (long long)g.a.s_ki, (long long)g.b.s_ro, (long long)g.b.s_ri,
                     (long long)g.b.s_ko, (long long)g.b.s_ki, (long long)d.c_mo,
                     (long long)d.c_mi, (long long)d.c_no, (long long)d.c_ni, BMx, BNx,
-                    (tile == kTileSplit || tile == kTileSplit160) ? " bf16-split" : "", nsplit);
+                    (tile == kTileSplit || tile == kTileSplit160) ? " bf16-split"
+                    : (tile == kTileSplitV ? " split-v4" : ""), nsplit);
       shape = buf;
     }
     std::lock_guard<std::mutex> lock(g_records_mu);
     // split-bf16 products are timed in a bucket of their own (one arithmetic, one peak)
     const bool split_products = d.prec == Prec::F32S || d.prec == Prec::F64S ||
-                                tile == kTileSplit || tile == kTileSplit160;
+                                tile == kTileSplit || tile == kTileSplit160 ||
+                                tile == kTileSplitV;
     g_records.push_back(Record{split_products ? Kind::Split : d.kind, ev[0], ev[1],
                                flops * d.batch, shape});
   }

@@ -255,7 +255,7 @@ def test_contract_matrix_vector(M, Mi, K, kfast):
 
 
 @pytest.mark.parametrize("tile,precision", [(0, 3), (1, 3), (2, 3), (3, 3), (4, 3), (0, 4),
-                                            (1, 4), (3, 4)])
+                                            (1, 4), (3, 4), (10, 3), (10, 4)])
 def test_contract_split_products_exact(tile, precision):
     """Split bf16 products (LNOCC_FP32_SPLIT on FP32 operands, LNOCC_FP64_SPLIT
     on FP64 ones) on operands x = s (1 + c 2^-9), s = +-1, c in {-1, 0, 1}: x
@@ -267,7 +267,7 @@ def test_contract_split_products_exact(tile, precision):
     change it by multiples of 2^-18."""
     say(f"contract split products exact tile {tile} precision {precision}")
     rng = np.random.default_rng(40 + tile)
-    M, N, K = 133, 70, 16
+    M, N, K = (132, 72, 16) if tile == 10 else (133, 70, 16)   # 4 x 4 staging: multiples of 4
 
     def draw(*shape):
         sgn = rng.choice([-1.0, 1.0], size=shape)
@@ -283,6 +283,43 @@ def test_contract_split_products_exact(tile, precision):
               [(K, 1, 1.0, _operand(a_t, K, 0, 1, 0), _operand(b_t, K, 0, 1, 0))],
               precision=precision, tile=tile)
     np.testing.assert_array_equal(host(c), ref)
+
+
+@pytest.mark.parametrize("precision", [1, 3, 4])
+def test_contract_split_v4_layouts(precision):
+    """Tile 10 (split products staged as 4 x 4 blocks) on the layouts it takes:
+    a k-contiguous operand with a two-index k (inner extent 36, padded row
+    pitch) and two-index rows, a row-contiguous operand pair (4-row groups
+    along memory), a batch of two, beta != 0, ragged M and N (multiples of 4,
+    not of 128) and K not a multiple of the 32-k slice; FP32 operands (precision
+    1 and 3) and FP64 operands (4).  FP32-level agreement with the FP64 product."""
+    say(f"contract split v4 layouts precision {precision}")
+    rng = np.random.default_rng(500 + precision)
+    nb, o, v, Ko, Ki, N, K2 = 2, 4, 36, 5, 36, 132, 68
+    M, K1 = o * v, Ko * Ki
+    A1p = rng.standard_normal((nb, o, v, Ko, Ki + 4))    # rows (i, a), k = (x, c), padded pitch
+    B1 = rng.standard_normal((nb, N, K1))
+    A2 = rng.standard_normal((nb, K2, M))                # row-contiguous
+    B2 = rng.standard_normal((nb, K2, N))
+    C0 = rng.standard_normal((nb, M, N))
+    dt = np.float64 if precision == 4 else np.float32
+    A1p, B1, A2, B2 = (x.astype(dt) for x in (A1p, B1, A2, B2))
+    A1 = A1p[..., :Ki].reshape(nb, M, K1).astype(np.float64)
+    ref = (np.einsum("emk,enk->emn", A1, B1.astype(np.float64))
+           - 0.25 * np.einsum("ekm,ekn->emn", A2.astype(np.float64), B2.astype(np.float64))
+           + 0.5 * C0)
+    tA1, tB1, tA2, tB2 = (torch.tensor(np.ascontiguousarray(x), device=DEV) for x in (A1p, B1, A2, B2))
+    c = dev(C0)
+    sri, sko = Ko * (Ki + 4), Ki + 4
+    seg1 = (K1, Ki, 1.0, _operand(tA1, v * sri, sri, sko, 1, bid=o * v * sri),
+            _operand(tB1, K1, 0, Ki, 1, bid=N * K1))
+    seg2 = (K2, 1, -0.25, _operand(tA2, v, 1, M, 0, bid=K2 * M),
+            _operand(tB2, 1, 0, N, 0, bid=K2 * N))
+    _contract(M, v, N, 1, c, (N * v, N, 1, 0), [seg1, seg2], beta=0.5, batch=nb, nb1=1,
+              cb=(0, 0, M * N), precision=precision, tile=10)
+    err = np.abs(host(c) - ref).max() / np.abs(ref).max()
+    say(f"  relative error {err:.2e}")
+    assert err < 2e-6 * np.sqrt(K1 + K2)
 
 
 @pytest.mark.parametrize("tile", [0, 1, 3])
