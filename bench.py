@@ -118,6 +118,10 @@ def parse_args():
                     help="add the large-fragment (T) leg (mixed and FP64, about 90 s)")
     ap.add_argument("--batch-leg", type=int, default=1,
                     help="add the batched-workload leg (mixed batch vs sequential FP64)")
+    ap.add_argument("--plans", default="",
+                    help="load contraction plans from this file before timing (if it exists)")
+    ap.add_argument("--save-plans", default="",
+                    help="save the contraction plans in use after the timed run to this file")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device (a plain copy of known size "
                          "that scales hardware byte counters)")
@@ -204,6 +208,8 @@ def run_single(args, L, torch) -> dict:
         log(f"{precision} profiled solve done")
         return fs, opt, elapsed, prof
 
+    if args.plans and pathlib.Path(args.plans).exists():
+        log(f"loaded {L.lnocc_autotune_load(args.plans)} contraction plans")
     fs, opt, elapsed, prof = timed(args.precision, args.steps, args.warmup)
     res = {"value": args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
            "config": {"workload": args.workload, "nocc": o, "nvir": v, "naux": X, "seed": seed,
@@ -234,6 +240,9 @@ def run_single(args, L, torch) -> dict:
                                    "d_e_t": ft.e_t - golden["e_t"]}
     if args.compare_fp64 and args.precision != "fp64":
         f64, opt64, el64, prof64 = timed("fp64", args.steps, args.warmup)
+    if args.save_plans:
+        log(f"saved {L.lnocc_autotune_save(args.save_plans)} contraction plans")
+    if args.compare_fp64 and args.precision != "fp64":
         ft64 = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
         st = L.lnocc_fragment_triples(ft64, opt64)
         torch.cuda.synchronize()
