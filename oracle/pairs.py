@@ -16,6 +16,11 @@ with W, V and Delta those of the (T) module (SI Sec. S1).  The sum over all
 alpha of the projected energies is the trace of E when the LOs span the
 occupied space (Eq. 5), which is the canonical correlation energy (Eq. 7 for
 CCSD, Eq. 16 at i = i' summed for (T)).
+
+Parity unpinned: the off-diagonal elements (i != i') of E_T.  Their sum with
+the diagonal is pinned (trace, projection identity, block structure of
+non-interacting fragments), but no closed form or brute-force route checks
+the Delta_i'jk scaling of v for i != i' on its own.
 """
 from __future__ import annotations
 
