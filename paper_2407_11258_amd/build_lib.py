@@ -34,26 +34,54 @@ def hipcc() -> str:
     return exe
 
 
-def _compile(src: pathlib.Path, obj: pathlib.Path) -> None:
-    cmd = [hipcc(), *FLAGS, "-c", str(src), "-o", str(obj)]
+# Host-sanitized variant for the CPU checks of the ABI (validation mode runs
+# every host code path without a device): AddressSanitizer and UBSan on the
+# host code only; the device code is built as usual.
+SAN_OUT = PKG / "_build_asan"
+SAN_LIB = PKG / "liblnocc_asan.so"
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _compile(src: pathlib.Path, obj: pathlib.Path, flags) -> None:
+    cmd = [hipcc(), *flags, "-c", str(src), "-o", str(obj)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src.name}:\n{r.stderr}")
 
 
-def build(jobs: int = 4) -> pathlib.Path:
-    OUT.mkdir(exist_ok=True)
-    objs = [OUT / (s.replace(".hip", ".o")) for s in SOURCES]
+def _build(out: pathlib.Path, lib: pathlib.Path, flags, link_flags, jobs: int) -> pathlib.Path:
+    out.mkdir(exist_ok=True)
+    objs = [out / (s.replace(".hip", ".o")) for s in SOURCES]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        list(ex.map(lambda so: _compile(SRC / so[0], so[1]), zip(SOURCES, objs)))
-    tmp = LIB.with_suffix(".so.tmp")
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *map(str, objs), "-o", str(tmp)]
+        list(ex.map(lambda so: _compile(SRC / so[0], so[1], flags), zip(SOURCES, objs)))
+    tmp = lib.with_suffix(".so.tmp")
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *link_flags, *map(str, objs),
+           "-o", str(tmp)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(jobs: int = 4) -> pathlib.Path:
+    return _build(OUT, LIB, FLAGS, [], jobs)
+
+
+def build_sanitized(jobs: int = 4) -> pathlib.Path:
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"] + SAN_HOST
+    return _build(SAN_OUT, SAN_LIB, flags, SAN_HOST[:4] + ["-shared-libsan"], jobs)
+
+
+def sanitizer_runtime() -> pathlib.Path | None:
+    """The compiler's AddressSanitizer runtime (preloaded by the sanitized checks)."""
+    for c in sorted(pathlib.Path("/opt/rocm").glob("lib/llvm/lib/clang/*/lib/linux/"
+                                                  "libclang_rt.asan-x86_64.so")):
+        return c
+    return None
 
 
 if __name__ == "__main__":
     print(build())
+    print(build_sanitized())

@@ -111,6 +111,9 @@ EXPORTS = ("lnocc_default_options", "lnocc_status_string", "lnocc_last_error",
 
 
 def load_library(path: str | os.PathLike | None = None) -> C.CDLL:
+    # LNOCC_LIBRARY names another build of the same library (the host-sanitized
+    # one of the CPU checks); the default is the in-tree build
+    path = path or os.environ.get("LNOCC_LIBRARY") or None
     p = pathlib.Path(path) if path else _LIB_PATH
     if not p.exists():
         raise RuntimeError(f"liblnocc not built ({p}); run paper_2407_11258_amd.build_lib.build()")
