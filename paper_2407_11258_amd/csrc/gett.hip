@@ -649,7 +649,10 @@ template <class E>
 struct Block4 {
   static constexpr int R = 128, BK = 32;
   using V = typename Vec4Of<E>::V;
-  int64_t roff[4];
+  // one thread's 4 x 4 block: q0..q3 = rows 0..3, four consecutive k each (every
+  // index below is a literal, so the block stays in registers)
+  struct Regs { V q0, q1, q2, q3; };
+  int64_t roff0, roff1, roff2, roff3;
   bool rok;
   // k-contiguous operands: 8 consecutive threads cover the 32 k of a row group
   // (coalesced loads, conflict-free 8-byte LDS stores); row-contiguous ones:
@@ -659,53 +662,52 @@ struct Block4 {
   __device__ void init(const GOperand &op, const FastDiv &rdiv, bool kfast, int nrows, int row0) {
     const int r0 = row0 + 4 * rg(kfast);
     rok = r0 < nrows;   // nrows is a multiple of 4
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      roff[j] = rok ? two_index_off(rdiv, (uint32_t)(r0 + j), op.s_ro, op.s_ri) : 0;
+    roff0 = rok ? two_index_off(rdiv, (uint32_t)(r0 + 0), op.s_ro, op.s_ri) : 0;
+    roff1 = rok ? two_index_off(rdiv, (uint32_t)(r0 + 1), op.s_ro, op.s_ri) : 0;
+    roff2 = rok ? two_index_off(rdiv, (uint32_t)(r0 + 2), op.s_ro, op.s_ri) : 0;
+    roff3 = rok ? two_index_off(rdiv, (uint32_t)(r0 + 3), op.s_ro, op.s_ri) : 0;
   }
-  // reg[4 j + c] = element (row j, k c) of the block
   __device__ void load(const E *__restrict__ base, const GOperand &op, const FastDiv &kdiv,
-                       bool kfast, int K, int k0, E (&reg)[16], bool &ok) const {
+                       bool kfast, int K, int k0, Regs &r, bool &ok) const {
     const int k = k0 + 4 * kg(kfast);
     ok = rok && k < K;   // K is a multiple of 4
     if (kfast) {
       const int64_t ko = ok ? two_index_off(kdiv, (uint32_t)k, op.s_ko, op.s_ki) : 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const V v = *(const V *)(base + (ok ? roff[j] + ko : 0));
-#pragma unroll
-        for (int c = 0; c < 4; ++c) reg[4 * j + c] = v[c];
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int64_t ko = ok ? two_index_off(kdiv, (uint32_t)(k + c), op.s_ko, op.s_ki) : 0;
-        const V v = *(const V *)(base + (ok ? roff[0] + ko : 0));
-#pragma unroll
-        for (int j = 0; j < 4; ++j) reg[4 * j + c] = v[j];
-      }
+      r.q0 = *(const V *)(base + (ok ? roff0 + ko : 0));
+      r.q1 = *(const V *)(base + (ok ? roff1 + ko : 0));
+      r.q2 = *(const V *)(base + (ok ? roff2 + ko : 0));
+      r.q3 = *(const V *)(base + (ok ? roff3 + ko : 0));
+    } else {   // four rows at each of the four k, transposed into rows
+      const V c0 = *(const V *)(base + (ok ? roff0 + two_index_off(kdiv, (uint32_t)(k + 0), op.s_ko, op.s_ki) : 0));
+      const V c1 = *(const V *)(base + (ok ? roff0 + two_index_off(kdiv, (uint32_t)(k + 1), op.s_ko, op.s_ki) : 0));
+      const V c2 = *(const V *)(base + (ok ? roff0 + two_index_off(kdiv, (uint32_t)(k + 2), op.s_ko, op.s_ki) : 0));
+      const V c3 = *(const V *)(base + (ok ? roff0 + two_index_off(kdiv, (uint32_t)(k + 3), op.s_ko, op.s_ki) : 0));
+      r.q0 = V{c0[0], c1[0], c2[0], c3[0]};
+      r.q1 = V{c0[1], c1[1], c2[1], c3[1]};
+      r.q2 = V{c0[2], c1[2], c2[2], c3[2]};
+      r.q3 = V{c0[3], c1[3], c2[3], c3[3]};
     }
   }
+  // one row: four values split into the three planes, one 8-byte store per plane
   template <int LD, int PS>
-  __device__ static void store(uint16_t *lds, bool kfast, const E (&reg)[16], bool ok,
-                               double scale) {
-    const int row = 4 * rg(kfast), kk = 4 * kg(kfast);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      uint16_t h[4], m[4], l[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const float x = ok ? (float)(scale * (double)reg[4 * j + c]) : 0.0f;
-        split3(x, h[c], m[c], l[c]);
-      }
-      const int o = (row + j) * LD + kk;
-      *(uint2 *)(lds + o) = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
-                                       (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-      *(uint2 *)(lds + PS + o) = make_uint2((uint32_t)m[0] | ((uint32_t)m[1] << 16),
-                                            (uint32_t)m[2] | ((uint32_t)m[3] << 16));
-      *(uint2 *)(lds + 2 * PS + o) = make_uint2((uint32_t)l[0] | ((uint32_t)l[1] << 16),
-                                                (uint32_t)l[2] | ((uint32_t)l[3] << 16));
-    }
+  __device__ static void put_row(uint16_t *lds, int o, const V &x, bool ok, double scale) {
+    uint16_t h0, m0, l0, h1, m1, l1, h2, m2, l2, h3, m3, l3;
+    const float sc = (float)scale;
+    split3(ok ? sc * (float)x[0] : 0.0f, h0, m0, l0);
+    split3(ok ? sc * (float)x[1] : 0.0f, h1, m1, l1);
+    split3(ok ? sc * (float)x[2] : 0.0f, h2, m2, l2);
+    split3(ok ? sc * (float)x[3] : 0.0f, h3, m3, l3);
+    *(uint2 *)(lds + o) = make_uint2((uint32_t)h0 | ((uint32_t)h1 << 16), (uint32_t)h2 | ((uint32_t)h3 << 16));
+    *(uint2 *)(lds + PS + o) = make_uint2((uint32_t)m0 | ((uint32_t)m1 << 16), (uint32_t)m2 | ((uint32_t)m3 << 16));
+    *(uint2 *)(lds + 2 * PS + o) = make_uint2((uint32_t)l0 | ((uint32_t)l1 << 16), (uint32_t)l2 | ((uint32_t)l3 << 16));
+  }
+  template <int LD, int PS>
+  __device__ static void store(uint16_t *lds, bool kfast, const Regs &r, bool ok, double scale) {
+    const int o = 4 * rg(kfast) * LD + 4 * kg(kfast);
+    put_row<LD, PS>(lds, o, r.q0, ok, scale);
+    put_row<LD, PS>(lds, o + LD, r.q1, ok, scale);
+    put_row<LD, PS>(lds, o + 2 * LD, r.q2, ok, scale);
+    put_row<LD, PS>(lds, o + 3 * LD, r.q3, ok, scale);
   }
 };
 
@@ -750,7 +752,7 @@ void gett_split_v4(GemmDesc d, int tiles_m, int slices_per_split) {
     Block4<E> sa, sb;
     sa.init(S.a, d.mdiv, akf, d.M, m0);
     sb.init(S.b, d.ndiv, bkf, d.N, n0);
-    E ra[16], rb[16];
+    typename Block4<E>::Regs ra, rb;
     bool oka, okb;
     sa.load(pa, S.a, S.kdiv, akf, S.K, lo * BK, ra, oka);
     sb.load(pb, S.b, S.kdiv, bkf, S.K, lo * BK, rb, okb);
@@ -1090,7 +1092,6 @@ void launch_split_v4(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStre
   if (d.prec == Prec::F64S) launch_split_v4_kind<ModeF64S>(d, grid, tiles_m, sps, stream);
   else launch_split_v4_kind<ModeF32S>(d, grid, tiles_m, sps, stream);
 }
-
 // gett_split_v4 stages 4 x 4 operand blocks with 4-element vector loads: every
 // 4-element group (along k for a k-contiguous operand, along its rows
 // otherwise) must be contiguous and aligned, and M, N and every K multiples of 4.
@@ -1392,17 +1393,13 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   };
   // the ladder contraction (long K, large output) of the FP32 modes: split products
   if (d.prec == Prec::F32 && d.kind == Kind::LadderContract && tile != 3) tile = kTileSplit;
-  // FP32 split products with k-contiguous operands take the 4 x 4-staged kernel
-  // (measured: 4096^3 145 against 111 TFLOP/s, the ladder contraction 101 against
-  // 92); FP64-operand split products stay on the 8-wave tile, where the staged
-  // kernel's single LDS buffer exposes the longer FP64 loads (94 against 96), and
-  // so do row-contiguous operands (92 against 111); the autotuner tries both
+  // split products take the 4 x 4-staged kernel where the operands allow it
+  // (measured: 4096^3 FP32 operands 149 against 100-111 TFLOP/s for the 8-wave
+  // tile, FP64 operands 152 against 96, the ladder contraction shape 133 / 125
+  // (k- / row-contiguous) against 91 / 108)
   const bool v4 = split_v4_ok(d);
-  bool all_kfast = true;
-  for (int q = 0; q < d.nseg; ++q)
-    all_kfast = all_kfast && contiguous_along_k(d.seg[q].a, d.seg[q].Ki) &&
-                contiguous_along_k(d.seg[q].b, d.seg[q].Ki);
-  if (v4 && all_kfast && tile != 3 && (d.prec == Prec::F32S || tile == kTileSplit))
+  if (v4 && tile != 3 &&
+      (d.prec == Prec::F32S || d.prec == Prec::F64S || tile == kTileSplit))
     tile = kTileSplitV;
   // FP64 with 160 x 160 tiles when the cost model (rounds of one workgroup per
   // CU x slices, plus partial sums) prefers them
