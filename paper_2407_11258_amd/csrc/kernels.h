@@ -10,20 +10,12 @@ namespace lnocc {
 // FP64 energy and norm) is independent of timing and bitwise reproducible.
 constexpr int kRedBlocks = 512;
 constexpr int kRedThreads = 256;
-constexpr int kTriplesBlocks = 128;   // (T) energy blocks per triple (grid-stride over cube tiles),
-constexpr int kTriplesGrid = 4096;    // raised so that one launch has at least this many blocks
-// Blocks per triple of a (T) energy launch over nb triples (before the cap at the
-// number of cube-tile orbits; the partial-sum buffer holds nb times this many).
-inline int64_t triples_blocks_per_entry(int64_t nb) {
-  const int64_t fill = (kTriplesGrid + nb - 1) / nb;
-  return fill > kTriplesBlocks ? fill : kTriplesBlocks;
-}
-// Partial sums any launch over b <= nb triples can write: b * max(128, ceil(4096 / b))
-// is at most max(128 nb, 4096 + b - 1).
-inline int64_t triples_partials_capacity(int64_t nb) {
-  const int64_t a = nb * kTriplesBlocks, b = kTriplesGrid + nb;
-  return a > b ? a : b;
-}
+// Blocks of a (T) energy launch: every block resident at once (256 CUs, five
+// blocks of the FP32-W kernel or four of the FP64 one per CU), a multiple of 8
+// (the launch is cut into one range of work per XCD); one partial sum per block.
+constexpr int kTriplesEnergyGrid = 1280;
+constexpr int kTriplesEnergyGrid64 = 1024;
+inline int64_t triples_partials_capacity(int64_t) { return kTriplesEnergyGrid; }
 
 hipError_t split_B(const double *B, int64_t X, int64_t o, int64_t v,
                    double *Boo, double *Bov, double *Bvv, hipStream_t s);
@@ -77,7 +69,8 @@ hipError_t unpack_ladder(const double *SA, int64_t o, int64_t v, int64_t ca, int
 hipError_t triples_table(int *table, int64_t o, hipStream_t s);
 
 // (T) energy of a batch of unique triples whose W tensors sit in W[nb][v][v][v].
-// table holds (i, j, k) per entry, i <= j <= k; partials[nb * tiles] per tile.
+// table holds (i, j, k) per entry, i <= j <= k; W holds nb triples in the blocked
+// layout of triples_w (triples.h); one partial per block, kTriplesEnergyGrid of them.
 // W element type: 0 double, 1 float
 // sym = 0: W holds W itself; sym = 1 (2): W holds Z with W(a,b,c) = Z(a,b,c) +
 // Z(b,a,c) (Z(a,b,c) + Z(a,c,b)).  capacity: length of partials; a launch that

@@ -413,77 +413,164 @@ __global__ void k_unpack_ladder(const double *__restrict__ SA, int64_t o, int64_
   }
 }
 
-// (T) energy epilogue on cube tiles of the W tensors.
+// (T) energy epilogue on cube tiles of the W tensors (blocked layout: the 8 x 8
+// (b, c) face of a tile is 64 contiguous elements, so a tile is eight 64-element
+// runs).
 constexpr int TT = 8;          // tile edge
 constexpr int TP = TT + 1;     // padded innermost extent in LDS
 
-template <typename TW>
-__device__ inline void load_cube(const TW *__restrict__ W, int64_t v, int64_t o0, int64_t o1,
-                                 int64_t o2, double *L) {
-  for (int e = threadIdx.x; e < TT * TT * TT; e += blockDim.x) {
-    const int p = e / (TT * TT), q = (e / TT) % TT, r = e % TT;
-    const int64_t x = o0 + p, y = o1 + q, z = o2 + r;
-    L[(p * TT + q) * TP + r] = (x < v && y < v && z < v) ? from_lp<TW>(W[(x * v + y) * v + z]) : 0.0;
+// Loads the distinct tiles of one orbit: tile p (slot[p] == p) has block
+// coordinates (c[P[p][0]], c[P[p][1]], c[P[p][2]]).  Rows with a >= v are not
+// read (they are not in memory and never used).
+template <typename TW> struct TileLoad;
+template <> struct TileLoad<float> {
+  // two tiles per pass: 8 rows x 16 four-element vectors each
+  __device__ static void run(const float *__restrict__ W, int v, int vt, int mask, const int *c,
+                             float (*L)[TT * TT * TP]) {
+    constexpr int P[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    const int t = threadIdx.x, half = t >> 7, x = (t >> 4) & 7, q = t & 15;
+    const int y = q >> 1, z = (q & 1) * 4;
+    int rank = 0;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      if (!((mask >> p) & 1)) continue;
+      const int mine = (rank & 1) == half;
+      ++rank;
+      const int a = 8 * c[P[p][0]] + x;
+      if (!mine || a >= v) continue;
+      const float4 f = *(const float4 *)(W + ((int64_t)a * vt * vt + (int64_t)c[P[p][1]] * vt +
+                                              c[P[p][2]]) * 64 + 4 * q);
+      float *d = L[p] + (x * TT + y) * TP + z;
+      d[0] = f.x; d[1] = f.y; d[2] = f.z; d[3] = f.w;
+    }
   }
+};
+template <> struct TileLoad<double> {
+  // one tile per pass: 8 rows x 32 two-element vectors
+  __device__ static void run(const double *__restrict__ W, int v, int vt, int mask, const int *c,
+                             double (*L)[TT * TT * TP]) {
+    constexpr int P[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    const int t = threadIdx.x, x = t >> 5, q = t & 31;
+    const int y = q >> 2, z = (q & 3) * 2;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const int a = 8 * c[P[p][0]] + x;
+      if (!((mask >> p) & 1) || a >= v) continue;
+      const double2 f = *(const double2 *)(W + ((int64_t)a * vt * vt + (int64_t)c[P[p][1]] * vt +
+                                                c[P[p][2]]) * 64 + 2 * q);
+      double *d = L[p] + (x * TT + y) * TP + z;
+      d[0] = f.x; d[1] = f.y;
+    }
+  }
+};
+
+// 1 / x from the hardware reciprocal estimate and two Newton-Raphson steps
+// (r <- r + r (1 - x r); each step squares the relative error), for the (T)
+// denominators, which are negative and far from zero and from overflow.
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
 }
+
+// Index of the ordered pair (u1, u2), u1 != u2, of block-coordinate positions.
+__device__ inline int pair_index(int u1, int u2) { return 2 * u1 + (u2 > u1 ? u2 - 1 : u2); }
 
 // The W tensor of one triple is read in six index orders.  Cube tiles are
 // grouped into orbits under permutations of their (a, b, c) block coordinates;
 // a block loads the (up to six) distinct tiles of one orbit once and evaluates
 // the integrand on all of them, so each W element is read from memory once.
-template <typename TW>
-__global__ void k_triples_energy(const TW *__restrict__ Wall, const int *__restrict__ table,
-                                 const double *__restrict__ Kov, const double *__restrict__ t1,
-                                 const double *__restrict__ eo, const double *__restrict__ ev,
-                                 int64_t o, int64_t v, int tpd, int sym, double *partials) {
-  __shared__ double L[6][TT * TT * TP];
+// The disconnected part of V needs (ia|jb), (ia|kc), (jb|kc) on pairs of the
+// orbit's coordinate blocks, t1 and the orbital energies on its blocks: these go
+// to LDS with the tiles.
+//
+// Work items are (triple, orbit) pairs, triple-major.  Workgroups are dispatched
+// round-robin over the eight XCDs (block b to XCD b % 8), each with its own L2:
+// the items are cut into eight contiguous ranges and the blocks of XCD x share
+// range x, so the integrals of one triple and the neighbouring rows of its W are
+// fetched by one L2.  Each block adds the weighted sums of its items and writes
+// one partial.
+template <typename TW, int SYM>
+__global__ __launch_bounds__(kRedThreads) void k_triples_energy(
+    const TW *__restrict__ Wall, const int *__restrict__ table, int nb,
+    const double *__restrict__ Kov, const double *__restrict__ t1, const double *__restrict__ eo,
+    const double *__restrict__ ev, int o, int v, double *partials) {
+  __shared__ TW L[6][TT * TT * TP];
+  __shared__ double K[3][6][TT * TT];   // (ia|jb), (ia|kc), (jb|kc) on ordered block pairs
+  __shared__ double T1[3][3][TT];       // t1 of i, j, k on each coordinate block
+  __shared__ double EV[3][TT];
   __shared__ double sm[kRedThreads / 64];
   constexpr int P[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-  const int entry = blockIdx.y;
-  const int i = table[3 * entry], j = table[3 * entry + 1], k = table[3 * entry + 2];
-  const TW *W = Wall + (int64_t)entry * v * v * v;
-  const double eijk = eo[i] + eo[j] + eo[k];
-  const int64_t norbits = (int64_t)tpd * (tpd + 1) * (tpd + 2) / 6;
-  double acc = 0.0;
-  for (int64_t orb = blockIdx.x; orb < norbits; orb += gridDim.x) {
+  const int t = threadIdx.x;
+  const int vt = (v + TT - 1) / TT;
+  const int64_t norbits = (int64_t)vt * (vt + 1) * (vt + 2) / 6;
+  const int64_t went = (int64_t)v * vt * vt * 64;   // elements of one triple's W
+  const int xcd = blockIdx.x & 7, S = gridDim.x >> 3, s = blockIdx.x >> 3;
+  const int64_t N = (int64_t)nb * norbits;
+  const int64_t lo = N * xcd / 8, hi = N * (xcd + 1) / 8;
+  // compute mapping: thread -> (x, y) of a tile face and z = zq, zq + 4
+  const int cx = t >> 5, cy = (t >> 2) & 7, zq = t & 3;
+  double total = 0.0;
+  for (int64_t item = lo + s; item < hi; item += S) {
+    const int entry = (int)(item / norbits);
+    const int64_t orb = item % norbits;
+    const int i = table[3 * entry], j = table[3 * entry + 1], k = table[3 * entry + 2];
+    const TW *W = Wall + (int64_t)entry * went;
+    const double eijk = eo[i] + eo[j] + eo[k];
     // canonical block coordinates c0 <= c1 <= c2 of orbit number orb
     int c[3];
     {
       int64_t r = orb;
       int A = 0;
       for (;; ++A) {
-        const int64_t n = (int64_t)(tpd - A) * (tpd - A + 1) / 2;
+        const int64_t n = (int64_t)(vt - A) * (vt - A + 1) / 2;
         if (r < n) break;
         r -= n;
       }
       int Bc = A;
       for (;; ++Bc) {
-        const int64_t n = tpd - Bc;
+        const int64_t n = vt - Bc;
         if (r < n) break;
         r -= n;
       }
       c[0] = A; c[1] = Bc; c[2] = Bc + (int)r;
     }
-    // slot[p]: the first permutation with the same tile coordinates as p
-    int slot[6];
+    // slot[p]: the first permutation with the same tile coordinates as p; bit p
+    // of mask: p is the first of its tile
+    int slot[6], mask = 0;
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
       slot[p] = p;
+#pragma unroll
       for (int q = 0; q < p; ++q)
         if (slot[p] == p && c[P[q][0]] == c[P[p][0]] && c[P[q][1]] == c[P[p][1]] &&
             c[P[q][2]] == c[P[p][2]])
           slot[p] = q;
+      if (slot[p] == p) mask |= 1 << p;
     }
-    __syncthreads();   // the previous orbit's reads of L are done
-#pragma unroll
-    for (int p = 0; p < 6; ++p)
-      if (slot[p] == p)
-        load_cube(W, v, (int64_t)c[P[p][0]] * TT, (int64_t)c[P[p][1]] * TT,
-                  (int64_t)c[P[p][2]] * TT, L[p]);
+    __syncthreads();   // the previous item's reads of LDS are done
+    TileLoad<TW>::run(W, v, vt, mask, c, L);
+    // integral blocks: kind 0 (ia|jb) = Kov[i][a][j][b], 1 (ia|kc), 2 (jb|kc)
+    for (int e = t; e < 3 * 6 * TT * TT; e += kRedThreads) {
+      const int kind = e / (6 * TT * TT), pr = (e / (TT * TT)) % 6, r = (e / TT) % TT, q = e % TT;
+      const int u1 = pr / 2, u2r = pr % 2, u2 = u2r < u1 ? u2r : u2r + 1;
+      const int m1 = kind == 2 ? j : i, m2 = kind == 0 ? j : k;
+      const int x1 = min(8 * c[u1] + r, v - 1), x2 = min(8 * c[u2] + q, v - 1);
+      K[kind][pr][r * TT + q] = Kov[(((int64_t)m1 * v + x1) * o + m2) * v + x2];
+    }
+    if (t < 3 * 3 * TT) {
+      const int m = t / (3 * TT), u = (t / TT) % 3, r = t % TT;
+      const int occ = m == 0 ? i : m == 1 ? j : k;
+      T1[m][u][r] = t1[(int64_t)occ * v + min(8 * c[u] + r, v - 1)];
+    } else if (t < 3 * 3 * TT + 3 * TT) {
+      const int e = t - 3 * 3 * TT, u = e / TT, r = e % TT;
+      EV[u][r] = ev[min(8 * c[u] + r, v - 1)];
+    }
     __syncthreads();
+    double acc = 0.0;
 #pragma unroll
     for (int p = 0; p < 6; ++p) {
-      if (slot[p] != p) continue;   // every distinct tile once
+      if (!((mask >> p) & 1)) continue;   // every distinct tile once
       const int s0 = P[p][0], s1 = P[p][1], s2 = P[p][2];
       // tiles holding W at (b,c,a), (c,a,b), (a,c,b), (b,a,c), (c,b,a) orders
       auto find = [&](int q0, int q1, int q2) {
@@ -493,44 +580,49 @@ __global__ void k_triples_energy(const TW *__restrict__ Wall, const int *__restr
           if (P[q][0] == q0 && P[q][1] == q1 && P[q][2] == q2) r = slot[q];
         return r;
       };
-      const double *Labc = L[p];
-      const double *Lbca = L[find(s1, s2, s0)];
-      const double *Lcab = L[find(s2, s0, s1)];
-      const double *Lacb = L[find(s0, s2, s1)];
-      const double *Lbac = L[find(s1, s0, s2)];
-      const double *Lcba = L[find(s2, s1, s0)];
-      const int64_t a0 = (int64_t)c[s0] * TT, b0 = (int64_t)c[s1] * TT, c0 = (int64_t)c[s2] * TT;
-      for (int e = threadIdx.x; e < TT * TT * TT; e += blockDim.x) {
-        const int x = e / (TT * TT), y = (e / TT) % TT, z = e % TT;
-        const int64_t a = a0 + x, b = b0 + y, cc = c0 + z;
-        if (a >= v || b >= v || cc >= v) continue;
-        const double zabc = Labc[(x * TT + y) * TP + z];
-        const double zbca = Lbca[(y * TT + z) * TP + x];
-        const double zcab = Lcab[(z * TT + x) * TP + y];
-        const double zacb = Lacb[(x * TT + z) * TP + y];
-        const double zbac = Lbac[(y * TT + x) * TP + z];
-        const double zcba = Lcba[(z * TT + y) * TP + x];
+      const TW *Labc = L[p];
+      const TW *Lbca = L[find(s1, s2, s0)];
+      const TW *Lcab = L[find(s2, s0, s1)];
+      const TW *Lacb = L[find(s0, s2, s1)];
+      const TW *Lbac = L[find(s1, s0, s2)];
+      const TW *Lcba = L[find(s2, s1, s0)];
+      const int a = 8 * c[s0] + cx, b = 8 * c[s1] + cy, c0 = 8 * c[s2];
+      if (a >= v || b >= v) continue;
+      const double *Kab = K[0][pair_index(s0, s1)], *Kac = K[1][pair_index(s0, s2)],
+                   *Kbc = K[2][pair_index(s1, s2)];
+      const double kab = Kab[cx * TT + cy], t1a = T1[0][s0][cx], t1b = T1[1][s1][cy];
+      const double eab = eijk - EV[s0][cx] - EV[s1][cy];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int z = zq + 4 * h;
+        if (c0 + z >= v) continue;
+        const double zabc = Labc[(cx * TT + cy) * TP + z];
+        const double zbca = Lbca[(cy * TT + z) * TP + cx];
+        const double zcab = Lcab[(z * TT + cx) * TP + cy];
+        const double zacb = Lacb[(cx * TT + z) * TP + cy];
+        const double zbac = Lbac[(cy * TT + cx) * TP + z];
+        const double zcba = Lcba[(z * TT + cy) * TP + cx];
         // sym 1: W(a,b,c) = Z(a,b,c) + Z(b,a,c); sym 2: W(a,b,c) = Z(a,b,c) + Z(a,c,b);
         // the six permuted values of W are then sums of the six permuted values of Z
-        double w = zabc, wbca = zbca, wcab = zcab, wacb = zacb, wbac = zbac, wcba = zcba;
-        if (sym == 1) {
+        double w, wbca, wcab, wacb, wbac, wcba;
+        if constexpr (SYM == 1) {
           w = zabc + zbac; wbca = zbca + zcba; wcab = zcab + zacb;
           wacb = zacb + zcab; wbac = zbac + zabc; wcba = zcba + zbca;
-        } else if (sym == 2) {
+        } else if constexpr (SYM == 2) {
           w = zabc + zacb; wbca = zbca + zbac; wcab = zcab + zcba;
           wacb = zacb + zabc; wbac = zbac + zbca; wcba = zcba + zcab;
+        } else {
+          w = zabc; wbca = zbca; wcab = zcab; wacb = zacb; wbac = zbac; wcba = zcba;
         }
-        const double V = w + Kov[((i * v + a) * o + j) * v + b] * t1[k * v + cc] +
-                         Kov[((i * v + a) * o + k) * v + cc] * t1[j * v + b] +
-                         Kov[((j * v + b) * o + k) * v + cc] * t1[i * v + a];
+        const double V = w + kab * T1[2][s2][z] + Kac[cx * TT + z] * t1b + Kbc[cy * TT + z] * t1a;
         const double Z = 4.0 * w + wbca + wcab - 2.0 * (wacb + wbac + wcba);
-        acc += V * Z / (eijk - ev[a] - ev[b] - ev[cc]);
+        acc = fma(V * Z, recip(eab - EV[s2][z]), acc);
       }
     }
+    total += ((i < j && j < k) ? 2.0 : 1.0) * acc;   // (6 or 3) / 3
   }
-  const double weight = (i < j && j < k) ? 2.0 : 1.0;   // (6 or 3) / 3
-  const double r = block_sum(acc, sm);
-  if (threadIdx.x == 0) partials[(int64_t)entry * gridDim.x + blockIdx.x] = weight * r;
+  const double r = block_sum(total, sm);
+  if (t == 0) partials[blockIdx.x] = r;
 }
 
 }  // namespace
@@ -705,24 +797,43 @@ hipError_t triples_energy(const void *W, int wtype, int sym, const int *table, i
                           const double *Kov, const double *t1, const double *eo,
                           const double *ev, int64_t o, int64_t v, double *partials,
                           int64_t capacity, int64_t *nparts, hipStream_t s) {
-  const int tpd = (int)((v + TT - 1) / TT);
-  const int64_t orbits = (int64_t)tpd * (tpd + 1) * (tpd + 2) / 6;
-  // small batches (large v) get more blocks per triple, so the launch fills the chip
-  const int64_t want = triples_blocks_per_entry(nb);
-  const int per_entry = (int)(orbits < want ? orbits : want);
-  *nparts = (int64_t)per_entry * nb;
+  if (nb < 1 || o < 1 || v < 1 || o > 65535 || v > 65535 || sym < 0 || sym > 2)
+    return hipErrorInvalidValue;
+  const int grid = wtype == 1 ? kTriplesEnergyGrid : kTriplesEnergyGrid64;
+  *nparts = grid;
   if (*nparts > capacity) {
     note_error("(T) energy partials: %lld needed, %lld allocated", (long long)*nparts,
                (long long)capacity);
     return hipErrorInvalidValue;
   }
+  const int64_t vt = (v + TT - 1) / TT, es = wtype == 1 ? 4 : 8;
+  if (!region_ok(W, (size_t)(nb * v * vt * vt * 64 * es)) ||
+      !region_ok(table, (size_t)nb * 3 * sizeof(int)) ||
+      !region_ok(Kov, (size_t)(o * v * o * v * 8)) || !region_ok(partials, (size_t)*nparts * 8)) {
+    note_error("(T) energy (nocc %lld, nvir %lld, %d triples) leaves its buffers; not launched",
+               (long long)o, (long long)v, nb);
+    return hipErrorInvalidValue;
+  }
   if (dry_run()) return hipSuccess;
-  if (wtype == 1)
-    hipLaunchKernelGGL(k_triples_energy<float>, dim3(per_entry, nb), dim3(kRedThreads), 0, s,
-                       (const float *)W, table, Kov, t1, eo, ev, o, v, tpd, sym, partials);
-  else
-    hipLaunchKernelGGL(k_triples_energy<double>, dim3(per_entry, nb), dim3(kRedThreads), 0, s,
-                       (const double *)W, table, Kov, t1, eo, ev, o, v, tpd, sym, partials);
+  const dim3 g(grid), b(kRedThreads);
+  const int io = (int)o, iv = (int)v;
+  if (wtype == 1) {
+    const float *w = (const float *)W;
+    if (sym == 1)
+      hipLaunchKernelGGL((k_triples_energy<float, 1>), g, b, 0, s, w, table, nb, Kov, t1, eo, ev, io, iv, partials);
+    else if (sym == 2)
+      hipLaunchKernelGGL((k_triples_energy<float, 2>), g, b, 0, s, w, table, nb, Kov, t1, eo, ev, io, iv, partials);
+    else
+      hipLaunchKernelGGL((k_triples_energy<float, 0>), g, b, 0, s, w, table, nb, Kov, t1, eo, ev, io, iv, partials);
+  } else {
+    const double *w = (const double *)W;
+    if (sym == 1)
+      hipLaunchKernelGGL((k_triples_energy<double, 1>), g, b, 0, s, w, table, nb, Kov, t1, eo, ev, io, iv, partials);
+    else if (sym == 2)
+      hipLaunchKernelGGL((k_triples_energy<double, 2>), g, b, 0, s, w, table, nb, Kov, t1, eo, ev, io, iv, partials);
+    else
+      hipLaunchKernelGGL((k_triples_energy<double, 0>), g, b, 0, s, w, table, nb, Kov, t1, eo, ev, io, iv, partials);
+  }
   return hipGetLastError();
 }
 

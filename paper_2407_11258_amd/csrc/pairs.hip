@@ -196,7 +196,7 @@ int pair_energies(const Layout &L, const double *t1, const double *t2, const dou
       for (int k = j; k < o; ++k, ++pidx) {
         const int *table = P.table + 3 * pidx * o;
         for (int ori = 0; ori < 3; ++ori)
-          PR_TRY(triples_w(P.Gt, P.T, P.Jt, P.W, table, (int)o, o, v, ori, 0, ori > 0, 2, s));
+          PR_TRY(triples_w(P.Gt, P.T, P.Jt, P.W, table, (int)o, o, v, ori, 0, ori > 0, 2, 0, s));
         if (!dry) {
           hipLaunchKernelGGL(k_pair_yz, dim3(blocks_for(o * vvv)), dim3(kThreads), 0, s, P.W,
                              L.Kov, t1, eo, ev, o, v, j, k, P.Y, P.Z);

@@ -179,12 +179,13 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
   const int64_t tes = L.t_f32 ? 4 : 8, vp = triples_pad(v);
   auto dwords = [](int64_t bytes) { return (bytes + 7) / 8; };
   int64_t nb = opt.triples_batch;
-  if (nb <= 0) nb = std::max<int64_t>(1, ((int64_t)2 << 30) / (tes * vvv));
+  const int64_t wel = triples_w_elems(v, 1);   // W of one triple, blocked layout
+  if (nb <= 0) nb = std::max<int64_t>(1, ((int64_t)2 << 30) / (tes * wel));
   nb = std::max<int64_t>(1, std::min<int64_t>({nb, std::max<int64_t>(nt, 1), 4096}));
   L.nb = (int)nb;
   L.ntriples = nt;
   L.Gt = A.d(dwords(ov * v * vp * tes)); L.Jt = A.d(dwords(oo * ov * tes));
-  L.W = A.d(dwords(nb * vvv * tes));
+  L.W = A.d(dwords(nb * wel * tes));
   L.t2_lp = A.d(dwords(oo * v * vp * tes));
   L.tpart_elems = triples_partials_capacity(nb);
   L.tpart = A.d(L.tpart_elems);
@@ -1061,7 +1062,7 @@ int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s, bool autot
       const int *table = L.table + 3 * t0;
       auto w = [&](int ori, int accumulate, int nterms) {
         return triples_w(L.Gt, L.t2_lp, L.Jt, L.W, table, nb, o, v, ori, ttype, accumulate,
-                         nterms, s);
+                         nterms, 1, s);
       };
       if (g == 0) {
         LN_TRY(w(0, 0, 2));

@@ -94,8 +94,19 @@ struct TripleArgs {
   int ori;
   int accumulate;       // 0: W = product; 1: W += product
   int nterms;           // 2: both particle and both hole terms; 1: the first of each
+  int blocked;          // W layout: 0 plain [v][v][v], 1 blocked [v][vt][vt][8][8]
   int tiles_m, tiles_n;
 };
+
+// Offset within one triple's W of index x in position role (0: a, 1: b, 2: c).
+__device__ inline int64_t w_offset(const TripleArgs &A, int role, int64_t x) {
+  const int64_t v = A.v;
+  if (!A.blocked) return role == 0 ? x * v * v : role == 1 ? x * v : x;
+  const int64_t vt = (v + 7) / 8;
+  if (role == 0) return x * vt * vt * 64;
+  if (role == 1) return (x >> 3) * vt * 64 + (x & 7) * 8;
+  return (x >> 3) * 64 + (x & 7);
+}
 
 template <typename E, int BM>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2)))
@@ -114,7 +125,7 @@ void k_triples_w(TripleArgs A) {
   constexpr int STAGE = 2 * (SZA + SZB);
   constexpr int CT = CR * LDC;
   __shared__ __attribute__((aligned(16))) E smem[STAGE > CT ? STAGE : CT];
-  __shared__ int64_t rowoff[BM];
+  __shared__ int64_t rowoff[BM], coloff[kBN];
   E *As = smem, *Bs = smem + 2 * SZA;
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -309,17 +320,18 @@ void k_triples_w(TripleArgs A) {
 
   // tile -> LDS (the stage buffers are free after the last barrier) -> W, in
   // passes of CR rows
-  int64_t cs1, cs2, cs3;
-  if (A.ori == 0) { cs1 = vv; cs2 = v; cs3 = 1; }
-  else if (A.ori == 1) { cs1 = vv; cs2 = 1; cs3 = v; }
-  else { cs1 = v; cs2 = 1; cs3 = vv; }
+  // positions of (m1, m2, n) in W[a][b][c]
+  int role1, role2, role3;
+  if (A.ori == 0) { role1 = 0; role2 = 1; role3 = 2; }
+  else if (A.ori == 1) { role1 = 0; role2 = 2; role3 = 1; }
+  else { role1 = 1; role2 = 2; role3 = 0; }
   for (int x = t; x < BM; x += kThreads) {
     const int64_t gr = r0 + x;
-    rowoff[x] = gr < nrows ? (gr / v) * cs1 + (gr % v) * cs2 : -1;
+    rowoff[x] = gr < nrows ? w_offset(A, role1, gr / v) + w_offset(A, role2, gr % v) : -1;
   }
+  for (int x = t; x < kBN; x += kThreads) coloff[x] = n0 + x < v ? w_offset(A, role3, n0 + x) : -1;
   E *Cs = smem;
-  E *W = (E *)A.W + (int64_t)entry * vv * v;
-  const int ncols = min(kBN, A.v - n0);
+  E *W = (E *)A.W + (int64_t)entry * (A.blocked ? v * ((v + 7) / 8) * ((v + 7) / 8) * 64 : vv * v);
 #pragma unroll
   for (int h = 0; h < BM / CR; ++h) {
     if (mw / CR == h) {
@@ -334,11 +346,20 @@ void k_triples_w(TripleArgs A) {
     __syncthreads();
     // element e of this pass: orientation 0 runs along n (the contiguous index
     // of W), 1 and 2 along the rows (m2 contiguous); the old values of a chunk
-    // are all requested before any is used
+    // are all requested before any is used.  In the blocked layout orientations
+    // 0 and 1 take 8 x 8 groups (8 rows x 8 columns), so that the 64 lanes of a
+    // wave cover one 64-element run of W when the rows start on a multiple of 8
+    // in b (orientation 0) or c (orientation 1).
     constexpr int EPT = CR * kBN / kThreads, CH = EPT / 5;
     static_assert(EPT % 5 == 0, "epilogue chunks");
+    static_assert(CR % 8 == 0 && kBN % 8 == 0, "8 x 8 epilogue groups");
     auto place = [&](int e, int &m, int &n) {
-      if (A.ori == 0) { m = e / kBN; n = e % kBN; }
+      if (A.blocked && A.ori < 2) {
+        const int lo = e & 7, hi = (e >> 3) & 7, grp = e >> 6;
+        const int gm = grp / (kBN / 8), gn = grp % (kBN / 8);
+        if (A.ori == 0) { m = 8 * gm + hi; n = 8 * gn + lo; }
+        else { m = 8 * gm + lo; n = 8 * gn + hi; }
+      } else if (A.ori == 0) { m = e / kBN; n = e % kBN; }
       else { n = e / CR; m = e % CR; }
     };
 #pragma unroll
@@ -349,8 +370,8 @@ void k_triples_w(TripleArgs A) {
       for (int u = 0; u < CH; ++u) {
         int m, n;
         place(t + kThreads * (c0 + u), m, n);
-        const int64_t ro = rowoff[h * CR + m];
-        off[u] = (ro < 0 || n >= ncols) ? -1 : ro + (int64_t)(n0 + n) * cs3;
+        const int64_t ro = rowoff[h * CR + m], co = coloff[n];
+        off[u] = (ro < 0 || co < 0) ? -1 : ro + co;
         val[u] = Cs[m * LDC + n];
       }
       if (A.accumulate) {
@@ -384,6 +405,11 @@ __global__ void k_pad_t2(const double *__restrict__ t2, int64_t o, int64_t v, in
 
 int64_t triples_pad(int64_t v) { return (v + 3) / 4 * 4; }
 
+int64_t triples_w_elems(int64_t v, int blocked) {
+  const int64_t vt = (v + 7) / 8;
+  return blocked ? v * vt * vt * 64 : v * v * v;
+}
+
 hipError_t triples_pad_t2(const double *t2, int64_t o, int64_t v, void *out, int f32,
                           hipStream_t s) {
   if (dry_run()) return hipSuccess;
@@ -400,7 +426,7 @@ hipError_t triples_pad_t2(const double *t2, int64_t o, int64_t v, void *out, int
 
 hipError_t triples_w(const void *G, const void *T, const void *J, void *W, const int *table,
                      int nb, int64_t o, int64_t v, int ori, int f32, int accumulate, int nterms,
-                     hipStream_t s) {
+                     int blocked, hipStream_t s) {
   if (nb < 1 || nb > 65535 || ori < 0 || ori > 2 || o < 1 || v < 1 || nterms < 1 || nterms > 2)
     return hipErrorInvalidValue;
   const int64_t vp = triples_pad(v), es = f32 ? 4 : 8;
@@ -409,7 +435,7 @@ hipError_t triples_w(const void *G, const void *T, const void *J, void *W, const
     return hipErrorInvalidValue;
   }
   if (!region_ok(G, (size_t)(o * v * v * vp * es)) || !region_ok(T, (size_t)(o * o * v * vp * es)) ||
-      !region_ok(J, (size_t)(o * o * v * o * es)) || !region_ok(W, (size_t)(nb * v * v * v * es)) ||
+      !region_ok(J, (size_t)(o * o * v * o * es)) || !region_ok(W, (size_t)(nb * triples_w_elems(v, blocked) * es)) ||
       !region_ok(table, (size_t)nb * 3 * sizeof(int))) {
     note_error("(T) W kernel (nocc %lld, nvir %lld, %d triples) leaves its buffers; not launched",
                (long long)o, (long long)v, nb);
@@ -421,6 +447,7 @@ hipError_t triples_w(const void *G, const void *T, const void *J, void *W, const
   a.ori = ori;
   a.accumulate = accumulate;
   a.nterms = nterms;
+  a.blocked = blocked ? 1 : 0;
   constexpr int bm = 128;
   a.tiles_m = (int)((v * v + bm - 1) / bm);
   a.tiles_n = (int)((v + kBN - 1) / kBN);
