@@ -711,24 +711,6 @@ struct Block4 {
   }
 };
 
-// Tile of block number `tile` of a tiles_m x tiles_n grid.  Workgroups are
-// dispatched round-robin over the eight XCDs, each with its own L2 (blocks
-// tile and tile + 8 share one): the column tiles of a row tile go to blocks
-// tile, tile + 8, tile + 16, ..., so one L2 fetches the row tile's operand rows
-// for all of them.  Row tiles past the last multiple of 8 take the plain order.
-__device__ inline void xcd_tile(int tile, int tiles_m, int tiles_n, int &tm, int &tn) {
-  const int G = 8 * tiles_n, full = tiles_m / 8 * G;
-  if (tile < full) {
-    const int g = tile / G, r = tile % G;
-    tm = 8 * g + (r & 7);
-    tn = r >> 3;
-  } else {
-    const int rem = tiles_m % 8, r = tile - full;
-    tm = tiles_m / 8 * 8 + r % rem;
-    tn = r / rem;
-  }
-}
-
 template <class M, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void gett_split_v4(GemmDesc d, int tiles_m, int slices_per_split) {

@@ -129,8 +129,8 @@ void k_triples_w(TripleArgs A) {
   E *As = smem, *Bs = smem + 2 * SZA;
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int tile = blockIdx.x;
-  const int tm = tile % A.tiles_m, tn = tile / A.tiles_m;
+  int tm, tn;
+  xcd_tile(blockIdx.x, A.tiles_m, A.tiles_n, tm, tn);
   const int64_t v = A.v, vp = A.vp, o = A.o, vv = v * v;
   const int64_t nrows = vv;
   const int64_t r0 = (int64_t)tm * BM;
