@@ -118,6 +118,14 @@ typedef struct lnocc_fragment_t {
   int32_t reserved1;
 } lnocc_fragment_t;
 
+/* Progress callback of the CCSD iterations: called on the calling thread after
+ * every iteration of every fragment with the fragment (an element of the array
+ * the call was given), the iteration number (1, 2, ...), the CCSD energy of the
+ * amplitudes that entered the iteration (E_MP2 at the first) and the step norm
+ * ||t_new - t_old||_2 of the iteration.  It must not call the library. */
+typedef void (*lnocc_iter_fn)(const struct lnocc_fragment_t *f, int32_t it, double e,
+                              double residual, void *user);
+
 typedef struct lnocc_options_t {
   int32_t precision;         /* lnocc_precision_t */
   int32_t guess;             /* lnocc_guess_t */
@@ -147,6 +155,15 @@ typedef struct lnocc_options_t {
                                 shapes have no tuned plan yet, time every tile / split
                                 candidate on one residual evaluation (and on the first (T)
                                 batch) and keep the fastest per shape for the process */
+  const char *tune_cache;    /* NULL, or the path of a contraction-plan file (the format of
+                                lnocc_autotune_save): lnocc_fragment_ccsd, lnocc_fragment_triples
+                                and lnocc_batch_solve read it before their first contraction
+                                when it exists, and rewrite it at the end of the call when
+                                autotuning added plans; a file that cannot be read or written
+                                is skipped (not an error).  Ignored by
+                                lnocc_fragment_ccsd_static. */
+  lnocc_iter_fn on_iter;     /* NULL, or the progress callback above */
+  void *user;                /* passed to on_iter */
 } lnocc_options_t;
 
 /* Fills *opt with defaults: FP64, MP2 guess, triples on, max_iter 100,

@@ -201,6 +201,24 @@ double fragment_cost(const lnocc_fragment_t *f) {
   return 20.0 * (X * v * v * v * v + o * o * v * v * v * v) + 2.0 * o * o * o * v * v * v * v;
 }
 
+// The plan file of opt->tune_cache: read when the call starts, rewritten when
+// the call ends if autotuning added plans.
+struct TuneCache {
+  const char *path = nullptr;
+  size_t n0 = 0;
+  bool save = false;
+  explicit TuneCache(const lnocc_options_t *opt) {
+    if (!opt || !opt->tune_cache) return;
+    path = opt->tune_cache;
+    (void)tune_load(path);
+    n0 = tune_plans();
+    save = opt->autotune != 0;
+  }
+  ~TuneCache() {
+    if (path && save && tune_plans() > n0) (void)tune_save(path);
+  }
+};
+
 int worse(int a, int b) {
   if (a < 0 || b < 0) return std::min(a, b);
   return std::max(a, b);
@@ -311,8 +329,9 @@ int lnocc_fragment_ccsd(lnocc_fragment_t *f, const lnocc_options_t *opt) {
   if (st) return finish(f, st);
   hipStream_t s = (hipStream_t)opt->stream;
   Guard guard(f, opt, L);
+  TuneCache cache(opt);
   Inputs in{f->B, f->eps_occ, f->eps_vir, f->t1 ? f->t1 : L.t1w, f->t2 ? f->t2 : L.t2w,
-            f->conv_tol};
+            f->conv_tol, f};
   Outputs out;
   st = run_ccsd(L, in, *opt, out, s);
   if (st >= 0 && opt->do_triples) {
@@ -359,7 +378,7 @@ int lnocc_fragment_ccsd_static(lnocc_fragment_t *f, const lnocc_options_t *opt_i
   hipStream_t s = (hipStream_t)opt.stream;
   Guard guard(f, &opt, L);
   Inputs in{f->B, f->eps_occ, f->eps_vir, f->t1 ? f->t1 : L.t1w, f->t2 ? f->t2 : L.t2w,
-            f->conv_tol};
+            f->conv_tol, f};
   Outputs out;
   Readback rb(sc.host);
   st = run_ccsd(L, in, opt, out, s, &rb);
@@ -461,7 +480,8 @@ int lnocc_fragment_triples(lnocc_fragment_t *f, const lnocc_options_t *opt) {
   if (st) return finish(f, st);
   hipStream_t s = (hipStream_t)opt->stream;
   Guard guard(f, opt, L);
-  Inputs in{f->B, f->eps_occ, f->eps_vir, f->t1, f->t2, f->conv_tol};
+  TuneCache cache(opt);
+  Inputs in{f->B, f->eps_occ, f->eps_vir, f->t1, f->t2, f->conv_tol, f};
   st = setup_fragment(L, f->B, f->eps_occ, f->eps_vir, false, s);
   Outputs out;
   if (!st) st = run_triples(L, in, out, s, opt->autotune != 0);
@@ -518,6 +538,7 @@ int lnocc_batch_solve(lnocc_fragment_t *f, int32_t nfrag, const lnocc_options_t 
   if (order.empty()) return worst;
   if (!opt->workspace) return LNOCC_ENOMEM;
   if (((uintptr_t)opt->workspace) % 256) return LNOCC_EINVAL;
+  TuneCache cache(opt);
   const int nslots = (int)std::min<size_t>(batch_slots((int)order.size(), opt),
                                            opt->workspace_bytes / slot_bytes);
   if (nslots < 1) {
@@ -600,7 +621,7 @@ int lnocc_batch_solve(lnocc_fragment_t *f, int32_t nfrag, const lnocc_options_t 
         lnocc_fragment_t *g = &f[k];
         plan_layout(dims_of(g), *opt, q.base, q.L);
         Inputs in{g->B, g->eps_occ, g->eps_vir, g->t1 ? g->t1 : q.L.t1w,
-                  g->t2 ? g->t2 : q.L.t2w, g->conv_tol};
+                  g->t2 ? g->t2 : q.L.t2w, g->conv_tol, g};
         q.frag = k;
         q.run.reset(new CcsdRun(q.L, in, *opt, q.s, q.rb));
         ++active;

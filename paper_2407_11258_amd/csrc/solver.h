@@ -77,6 +77,7 @@ struct Inputs {
   const double *B, *eo, *ev;
   double *t1, *t2;
   double conv_tol;
+  const lnocc_fragment_t *frag = nullptr;   // passed to the progress callback
 };
 
 struct Outputs {

@@ -858,6 +858,7 @@ int CcsdRun::after_iteration() {
     note_error("non-finite residual norm or DIIS overlap at iteration %d", it);
     return LNOCC_ENUMERIC;
   }
+  if (opt.on_iter) opt.on_iter(in.frag, it, it > 1 ? host[0] : out.e_mp2, out.residual, opt.user);
   // end of the split phase (the DIIS subspace keeps its vectors: restarting it
   // here measured two more iterations)
   if (split) {
@@ -916,7 +917,8 @@ int CcsdRun::after_iteration() {
     }
   }
   if (!extrap) LN_TRY(scatter_vec(xs, o, v, in.t1, in.t2, s));
-  if (log_enabled()) {   // energy of the new iterate, read back with the next Gram row
+  if (log_enabled() || opt.on_iter) {   // energy of the new iterate, read back with the
+                                        // next Gram row (for the log and the callback)
     const int st2 = energy(*L, in.t1, in.t2, L->scal, s);
     if (st2) return st2;
   }

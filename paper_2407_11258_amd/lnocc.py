@@ -44,6 +44,11 @@ class lnocc_fragment_t(C.Structure):
     ]
 
 
+# lnocc_iter_fn: (fragment, iteration, energy, step norm, user)
+lnocc_iter_fn = C.CFUNCTYPE(None, C.POINTER(lnocc_fragment_t), C.c_int32, C.c_double,
+                            C.c_double, C.c_void_p)
+
+
 class lnocc_options_t(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("guess", C.c_int32), ("do_triples", C.c_int32),
@@ -53,6 +58,7 @@ class lnocc_options_t(C.Structure):
         ("batch_slots", C.c_int32), ("level_shift", C.c_double),
         ("batch_streams", C.c_int32), ("ladder_mode", C.c_int32),
         ("mlp", C.c_void_p), ("graphs", C.c_int32), ("autotune", C.c_int32),
+        ("tune_cache", C.c_char_p), ("on_iter", lnocc_iter_fn), ("user", C.c_void_p),
     ]
 
 
@@ -394,7 +400,11 @@ def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int
                  ladder_chunk_bytes: int = 0, triples_batch: int = 0,
                  level_shift: float = 0.0, batch_slots: int = 0,
                  batch_streams: int = 0, mlp=None, ladder: str = "auto",
-                 graphs: bool = True, autotune: bool = False) -> lnocc_options_t:
+                 graphs: bool = True, autotune: bool = False, tune_cache=None,
+                 on_iter=None) -> lnocc_options_t:
+    """Options struct.  on_iter, if given, is called as on_iter(fragment_index, it,
+    energy, residual) after every CCSD iteration, where fragment_index counts the
+    fragments of the call's array; tune_cache is a plan-file path."""
     opt = lnocc_default_options()
     opt.precision = PRECISIONS[precision]
     opt.do_triples = int(do_triples)
@@ -410,6 +420,15 @@ def make_options(precision: str = "fp64", do_triples: bool = True, max_iter: int
     opt.ladder_mode = LADDER_MODES[ladder]
     opt.graphs = int(bool(graphs))
     opt.autotune = int(bool(autotune))
+    if tune_cache is not None:
+        opt.tune_cache = str(tune_cache).encode()
+    if on_iter is not None:
+        def _tramp(frag, it, e, r, user, _cb=on_iter):
+            # the fragment's position in the call's array: its address relative to
+            # the first element, registered in opt.user
+            base = user or 0
+            _cb((C.addressof(frag.contents) - base) // C.sizeof(lnocc_fragment_t), it, e, r)
+        opt.on_iter = lnocc_iter_fn(_tramp)
     if mlp is not None:
         opt.mlp = mlp if isinstance(mlp, int) else mlp.data_ptr()
     return opt
@@ -450,6 +469,8 @@ def solve(B, eps_occ, eps_vir, *, conv_tol=1e-8, t1=None, t2=None, workspace=Non
         t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=B.device)
     opt = make_options(**kw)
     f = make_fragment_struct(B, eps_occ, eps_vir, t1, t2, conv_tol)
+    if opt.on_iter:
+        opt.user = C.addressof(f)
     ws = workspace or Workspace(B.device)
     ws.attach([f], opt)
     st = lnocc_fragment_ccsd(f, opt)
@@ -469,6 +490,8 @@ def solve_batch(fragments, *, conv_tol=1e-8, workspace=None, **kw) -> list[Resul
         amps.append((t1, t2))
         arr[k] = make_fragment_struct(B, eo, ev, t1, t2, conv_tol)
     opt = make_options(**kw)
+    if opt.on_iter:
+        opt.user = C.addressof(arr)
     ws = workspace or Workspace(fragments[0][0].device)
     ws.attach(list(arr), opt)
     lnocc_batch_solve(arr, opt)

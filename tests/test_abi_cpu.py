@@ -146,6 +146,29 @@ def test_small_ladder_blocks_and_triple_batches(validation_mode):
     assert L.lnocc_fragment_ccsd(f, opt) == L.LNOCC_OK
 
 
+def test_tune_cache_is_read_and_a_missing_file_skipped(validation_mode, tmp_path):
+    """opt.tune_cache: the plan file is read before the call's first contraction;
+    a missing file is no error; nothing is rewritten when no plan was added."""
+    plan = tmp_path / "plans.txt"
+    plan.write_text("0.0.0|16.1.16.1|1.1.0.1.1|160.1:160.0.1.0:160.0.1.0|16.0.1.0 3 4\n")
+    opt = L.make_options(tune_cache=plan, autotune=True)
+    f = _fake_fragment(2, 5, 9)
+    st, nbytes = L.lnocc_workspace_bytes([f], opt)
+    assert st == L.LNOCC_OK
+    opt.workspace, opt.workspace_bytes = 1 << 45, nbytes
+    L.lnocc_autotune_clear()
+    try:
+        assert L.lnocc_fragment_ccsd(f, opt) == L.LNOCC_OK
+        out = tmp_path / "out.txt"
+        assert L.lnocc_autotune_save(out) == 1
+        assert out.read_text() == plan.read_text()
+        opt.tune_cache = str(tmp_path / "missing.txt").encode()
+        assert L.lnocc_fragment_ccsd(f, opt) == L.LNOCC_OK
+        assert not (tmp_path / "missing.txt").exists()
+    finally:
+        L.lnocc_autotune_clear()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_triples_partials_fit_every_batch(validation_mode, precision):
     """The (T) energy launch of every batch of triples, the short last one
