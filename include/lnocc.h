@@ -73,15 +73,8 @@ typedef enum {
                            split into three bf16 parts (round to nearest even); a product is
                            the sum of the six largest part products on the BF16 matrix
                            cores, FP32 accumulation: FP32-level accuracy at BF16 rates */
-  LNOCC_FP64_SPLIT = 4, /* lnocc_contract only: FP64 operands rounded to FP32 (nearest even)
+  LNOCC_FP64_SPLIT = 4  /* lnocc_contract only: FP64 operands rounded to FP32 (nearest even)
                            as they are staged, then multiplied as in LNOCC_FP32_SPLIT */
-  LNOCC_FP32_PLANES = 5 /* lnocc_contract only: operands already split as in LNOCC_FP32_SPLIT,
-                           given as three planes of bf16 bit patterns (h = bf16(x),
-                           m = bf16(x - h), l = bf16(x - h - m), uint16 each), plane q of an
-                           operand at p + q * ps elements; same products and results as
-                           LNOCC_FP32_SPLIT on the values x, without the split at staging
-                           time.  Needs k-contiguous operands, 4-element aligned strides
-                           and planes, M, N, K multiples of 4, scale 1 (else EINVAL) */
 } lnocc_precision_t;
 
 typedef enum {
@@ -369,13 +362,11 @@ double lnocc_mp2_composite(double e_mp2_full, const double *e_mp2_fragments, int
  * arithmetic (LNOCC_FP64: double; LNOCC_FP32: float, FP32 accumulation;
  * LNOCC_BF16: bf16 bit patterns, FP32 accumulation; LNOCC_FP32_SPLIT: float,
  * split bf16 products, FP32 accumulation; LNOCC_FP64_SPLIT: double, rounded to
- * float, split bf16 products, FP32 accumulation; LNOCC_FP32_PLANES: three bf16
- * planes per operand, ps elements apart); C is always FP64. */
+ * float, split bf16 products, FP32 accumulation); C is always FP64. */
 typedef struct lnocc_operand_t {
   const double *p;
   int64_t s_ro, s_ri, s_ko, s_ki;
   int64_t b0, b1, bid;
-  int64_t ps;                    /* LNOCC_FP32_PLANES: elements between planes; else unused */
 } lnocc_operand_t;
 
 typedef struct lnocc_contract_t {

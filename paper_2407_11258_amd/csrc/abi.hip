@@ -848,9 +848,9 @@ int lnocc_contract(const lnocc_contract_t *c, void *stream) {
     if (!c->a[s].p || !c->b[s].p || c->K[s] < 0 || c->Ki[s] < 1) return LNOCC_EINVAL;
     GSegment &g = d.seg[s];
     g.a = GOperand{c->a[s].p, c->a[s].s_ro, c->a[s].s_ri, c->a[s].s_ko, c->a[s].s_ki,
-                   c->a[s].b0, c->a[s].b1, 0, c->a[s].bid, c->a[s].ps};
+                   c->a[s].b0, c->a[s].b1, 0, c->a[s].bid};
     g.b = GOperand{c->b[s].p, c->b[s].s_ro, c->b[s].s_ri, c->b[s].s_ko, c->b[s].s_ki,
-                   c->b[s].b0, c->b[s].b1, 0, c->b[s].bid, c->b[s].ps};
+                   c->b[s].b0, c->b[s].b1, 0, c->b[s].bid};
     g.K = c->K[s]; g.Ki = c->Ki[s]; g.scale = c->scale[s];
   }
   d.c = c->c;
@@ -858,14 +858,13 @@ int lnocc_contract(const lnocc_contract_t *c, void *stream) {
   d.c_b0 = c->c_b0; d.c_b1 = c->c_b1; d.c_b2 = 0; d.c_bid = c->c_bid;
   d.beta = c->beta;
   d.batch = c->batch; d.nb1 = c->nb1; d.table = nullptr;
-  if (c->precision < 0 || c->precision > 5) return LNOCC_EINVAL;
+  if (c->precision < 0 || c->precision > 4) return LNOCC_EINVAL;
   d.prec = (Prec)c->precision;
   d.c_type = 0;
   if (c->tile < 0 || c->tile > 10) return LNOCC_EINVAL;
   d.tile_hint = c->tile;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = gett(d, s);
-  if (e == hipErrorInvalidValue) return LNOCC_EINVAL;
   if (e != hipSuccess) {
     if (!last_error()[0]) note_error("contraction launch failed (%s)", hipGetErrorString(e));
     return LNOCC_EDEVICE;

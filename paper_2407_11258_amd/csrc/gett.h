@@ -18,10 +18,7 @@ namespace lnocc {
 // F32S: FP32 operands whose products run on the bf16 matrix cores as sums of
 // split products (FP32-level accuracy; see the kernel source).  F64S: FP64
 // operands in memory, rounded to FP32 when staged and multiplied as F32S.
-// P3: FP32-class operands given as the three bf16 planes (h, m, l) of the
-// split-product mode (split3_bf16 below), plane p of an operand p * ps elements
-// from its base; products as in F32S, without the split at staging time.
-enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2, F32S = 3, F64S = 4, P3 = 5 };
+enum class Prec : int { F64 = 0, F32 = 1, BF16 = 2, F32S = 3, F64S = 4 };
 
 // What a contraction computes; each class is its own kernel symbol (so
 // profiler statistics separate them) and its own timing bucket.
@@ -59,7 +56,6 @@ struct GOperand {
   int64_t s_ko, s_ki;     // strides of the outer / inner contraction index
   int64_t b0, b1, b2;     // pointer offset per unit of each batch integer
   int64_t bid;            // pointer offset per unit of the batch entry number
-  int64_t ps;             // Prec::P3: elements from one bf16 plane to the next
 };
 
 struct GSegment {
@@ -163,19 +159,6 @@ GemmDesc gemm_desc(int M, int N, int K, double alpha,
                    const double *A, int64_t sam, int64_t sak,
                    const double *B, int64_t sbk, int64_t sbn,
                    double beta, double *C, int64_t scm, int64_t scn);
-
-// x -> (h, m, l): h = bf16(x), m = bf16(x - h), l = bf16(x - h - m), each rounded
-// to nearest even (both differences are exact in FP32); the operand split of the
-// split-bf16 products (Henry, Tang and Heinecke, ARITH 2019).
-__device__ inline uint16_t bf16_rn_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
-__device__ inline float bf16_bits_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-__device__ inline void split3_bf16(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
-  h = bf16_rn_bits(x);
-  const float r1 = x - bf16_bits_to_f32(h);
-  m = bf16_rn_bits(r1);
-  const float r2 = r1 - bf16_bits_to_f32(m);
-  l = bf16_rn_bits(r2);
-}
 
 // Tile of block number `tile` of a tiles_m x tiles_n grid.  Workgroups are
 // dispatched round-robin over the eight XCDs, each with its own L2 (blocks

@@ -100,19 +100,8 @@ struct ModeF64S {
   static constexpr bool kRowMajor = true;
   __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
 };
-// Operands already split into the three bf16 planes (Prec::P3): the products of
-// ModeF32S with the staging reduced to copies.
-struct ModeP3 {
-  using T = uint16_t;
-  using L = uint16_t;
-  static constexpr int kPlanes = 3;
-  using Acc = float4_t;
-  static constexpr int KS = 32, BK = 32;
-  static constexpr bool kRowMajor = true;
-  __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
-};
 
-__device__ inline float bf16_to_f32(uint16_t h) { return bf16_bits_to_f32(h); }
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 // round to nearest even (finite inputs)
 __device__ inline uint16_t f32_to_bf16(float f) {
   const uint32_t u = __float_as_uint(f);
@@ -153,9 +142,8 @@ constexpr int kTileSplit = 6, kTileSq160 = 7, kTileSplit160 = 8, kTileSplitV = 9
 // products with 4 x 4 staging) FP32 and the split modes when split_v4_ok
 inline bool tile_valid(int t, Prec p) {
   if (t < 0 || t > 9) return false;
-  if (t < 4) return p != Prec::P3;
-  if (t == kTileSplitV) return p == Prec::F32 || p == Prec::F32S || p == Prec::F64S || p == Prec::P3;
-  if (p == Prec::P3) return false;   // pre-split planes: the 4 x 4-staged kernel only
+  if (t < 4) return true;
+  if (t == kTileSplitV) return p == Prec::F32 || p == Prec::F32S || p == Prec::F64S;
   return t == kTileSq160 ? p == Prec::F64 : p == Prec::F32;
 }
 
@@ -199,8 +187,15 @@ template <> __device__ inline float scaled<ModeF32>(float x, double s) { return 
 template <> __device__ inline float scaled<ModeF32S>(float x, double s) { return (float)s * x; }
 template <> __device__ inline double scaled<ModeF64S>(double x, double s) { return s * x; }
 
+__device__ inline uint16_t bf16_rn_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 // x -> (h, m, l) of the split-product mode
-__device__ inline void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l) { split3_bf16(x, h, m, l); }
+__device__ inline void split3(float x, uint16_t &h, uint16_t &m, uint16_t &l) {
+  h = bf16_rn_bits(x);
+  const float r1 = x - bf16_to_f32(h);
+  m = bf16_rn_bits(r1);
+  const float r2 = r1 - bf16_to_f32(m);
+  l = bf16_rn_bits(r2);
+}
 // (scale = 1 for the B operand: the multiply folds away after inlining)
 template <> __device__ inline uint16_t scaled<ModeBF16>(uint16_t x, double s) {
   return s == 1.0 ? x : f32_to_bf16((float)s * bf16_to_f32(x));
@@ -716,56 +711,6 @@ struct Block4 {
   }
 };
 
-// Pre-split operands (Prec::P3, k-contiguous only): each thread copies its
-// 4-row x 4-k block of every plane (one 8-byte load and one 8-byte LDS store per
-// row and plane); positions past M, N or K are stored as zeros, as the split of
-// zero would give.
-template <>
-struct Block4<uint16_t> {
-  static constexpr int R = 128, BK = 32;
-  struct Regs { uint2 h0, h1, h2, h3, m0, m1, m2, m3, l0, l1, l2, l3; };
-  int64_t roff0, roff1, roff2, roff3;
-  bool rok;
-  __device__ static int rg(bool) { return threadIdx.x / 8; }
-  __device__ static int kg(bool) { return threadIdx.x % 8; }
-  __device__ void init(const GOperand &op, const FastDiv &rdiv, bool, int nrows, int row0) {
-    const int r0 = row0 + 4 * rg(true);
-    rok = r0 < nrows;   // nrows is a multiple of 4
-    roff0 = rok ? two_index_off(rdiv, (uint32_t)(r0 + 0), op.s_ro, op.s_ri) : 0;
-    roff1 = rok ? two_index_off(rdiv, (uint32_t)(r0 + 1), op.s_ro, op.s_ri) : 0;
-    roff2 = rok ? two_index_off(rdiv, (uint32_t)(r0 + 2), op.s_ro, op.s_ri) : 0;
-    roff3 = rok ? two_index_off(rdiv, (uint32_t)(r0 + 3), op.s_ro, op.s_ri) : 0;
-  }
-  __device__ void load(const uint16_t *__restrict__ base, const GOperand &op, const FastDiv &kdiv,
-                       bool, int K, int k0, Regs &r, bool &ok) const {
-    const int k = k0 + 4 * kg(true);
-    ok = rok && k < K;   // K is a multiple of 4
-    const int64_t ko = ok ? two_index_off(kdiv, (uint32_t)k, op.s_ko, op.s_ki) : 0;
-    const int64_t ps = op.ps;
-    const uint16_t *p0 = base + (ok ? roff0 + ko : 0), *p1 = base + (ok ? roff1 + ko : 0);
-    const uint16_t *p2 = base + (ok ? roff2 + ko : 0), *p3 = base + (ok ? roff3 + ko : 0);
-    r.h0 = *(const uint2 *)p0; r.m0 = *(const uint2 *)(p0 + ps); r.l0 = *(const uint2 *)(p0 + 2 * ps);
-    r.h1 = *(const uint2 *)p1; r.m1 = *(const uint2 *)(p1 + ps); r.l1 = *(const uint2 *)(p1 + 2 * ps);
-    r.h2 = *(const uint2 *)p2; r.m2 = *(const uint2 *)(p2 + ps); r.l2 = *(const uint2 *)(p2 + 2 * ps);
-    r.h3 = *(const uint2 *)p3; r.m3 = *(const uint2 *)(p3 + ps); r.l3 = *(const uint2 *)(p3 + 2 * ps);
-  }
-  template <int LD, int PS>
-  __device__ static void put_row(uint16_t *lds, int o, uint2 h, uint2 m, uint2 l, bool ok) {
-    const uint2 z = make_uint2(0u, 0u);
-    *(uint2 *)(lds + o) = ok ? h : z;
-    *(uint2 *)(lds + PS + o) = ok ? m : z;
-    *(uint2 *)(lds + 2 * PS + o) = ok ? l : z;
-  }
-  template <int LD, int PS>
-  __device__ static void store(uint16_t *lds, bool, const Regs &r, bool ok, double) {
-    const int o = 4 * rg(true) * LD + 4 * kg(true);
-    put_row<LD, PS>(lds, o, r.h0, r.m0, r.l0, ok);
-    put_row<LD, PS>(lds, o + LD, r.h1, r.m1, r.l1, ok);
-    put_row<LD, PS>(lds, o + 2 * LD, r.h2, r.m2, r.l2, ok);
-    put_row<LD, PS>(lds, o + 3 * LD, r.h3, r.m3, r.l3, ok);
-  }
-};
-
 template <class M, int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void gett_split_v4(GemmDesc d, int tiles_m, int slices_per_split) {
@@ -980,9 +925,7 @@ bool operand_ok(const GemmDesc &d, const GOperand &op, int64_t rows, int64_t Ri,
   add_term(s, bmax[1], op.b1);
   add_term(s, bmax[2], op.b2);
   add_term(s, d.batch - 1, op.bid);
-  if (d.prec == Prec::P3) add_term(s, 2, op.ps);   // the third plane
-  const size_t esz = (d.prec == Prec::F64 || d.prec == Prec::F64S) ? 8
-                     : ((d.prec == Prec::BF16 || d.prec == Prec::P3) ? 2 : 4);
+  const size_t esz = (d.prec == Prec::F64 || d.prec == Prec::F64S) ? 8 : (d.prec == Prec::BF16 ? 2 : 4);
   return inside(op.p, s, esz);
 }
 
@@ -1147,18 +1090,15 @@ void launch_split_v4_kind(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hi
 }
 void launch_split_v4(const GemmDesc &d, dim3 grid, int tiles_m, int sps, hipStream_t stream) {
   if (d.prec == Prec::F64S) launch_split_v4_kind<ModeF64S>(d, grid, tiles_m, sps, stream);
-  else if (d.prec == Prec::P3) launch_split_v4_kind<ModeP3>(d, grid, tiles_m, sps, stream);
   else launch_split_v4_kind<ModeF32S>(d, grid, tiles_m, sps, stream);
 }
 // gett_split_v4 stages 4 x 4 operand blocks with 4-element vector loads: every
 // 4-element group (along k for a k-contiguous operand, along its rows
 // otherwise) must be contiguous and aligned, and M, N and every K multiples of 4.
 bool split_v4_ok(const GemmDesc &d) {
-  if (d.prec != Prec::F32 && d.prec != Prec::F32S && d.prec != Prec::F64S && d.prec != Prec::P3)
-    return false;
+  if (d.prec != Prec::F32 && d.prec != Prec::F32S && d.prec != Prec::F64S) return false;
   if (d.M % 4 || d.N % 4) return false;
-  const bool planes = d.prec == Prec::P3;
-  const int64_t esz = d.prec == Prec::F64S ? 8 : (planes ? 2 : 4);
+  const int64_t esz = d.prec == Prec::F64S ? 8 : 4;
   auto al = [](int64_t x) { return x % 4 == 0; };
   auto op_ok = [&](const GOperand &o, int rows_i, int Ki, bool kfast) {
     if (((uintptr_t)o.p) % (4 * esz)) return false;
@@ -1173,12 +1113,8 @@ bool split_v4_ok(const GemmDesc &d) {
   for (int q = 0; q < d.nseg; ++q) {
     const GSegment &S = d.seg[q];
     if (S.K % 4) return false;
-    const bool akf = contiguous_along_k(S.a, S.Ki), bkf = contiguous_along_k(S.b, S.Ki);
-    // pre-split planes: k-contiguous operands, planes 4-element aligned, the
-    // scale already applied
-    if (planes && (!akf || !bkf || !al(S.a.ps) || !al(S.b.ps) || S.scale != 1.0)) return false;
-    if (!op_ok(S.a, d.Mi, S.Ki, akf)) return false;
-    if (!op_ok(S.b, d.Ni, S.Ki, bkf)) return false;
+    if (!op_ok(S.a, d.Mi, S.Ki, contiguous_along_k(S.a, S.Ki))) return false;
+    if (!op_ok(S.b, d.Ni, S.Ki, contiguous_along_k(S.b, S.Ki))) return false;
   }
   return true;
 }
@@ -1342,8 +1278,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   if (d.Mi <= 0 || d.Ni <= 0 || d.nseg <= 0 || d.nseg > kMaxSeg) return hipErrorInvalidValue;
   // k per LDS slice: 32 for the bf16 matrix-core arithmetics, else 16
   auto tile_bk = [&](int t) {
-    return (d.prec == Prec::BF16 || d.prec == Prec::F32S || d.prec == Prec::F64S ||
-            d.prec == Prec::P3 || t == kTileSplit ||
+    return (d.prec == Prec::BF16 || d.prec == Prec::F32S || d.prec == Prec::F64S || t == kTileSplit ||
             t == kTileSplitV ||
             t == kTileSplit160) ? 32 : 16;
   };
@@ -1466,14 +1401,6 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
   if (v4 && tile != 3 &&
       (d.prec == Prec::F32S || d.prec == Prec::F64S || tile == kTileSplit))
     tile = kTileSplitV;
-  if (d.prec == Prec::P3) {   // pre-split planes: only the 4 x 4-staged kernel reads them
-    if (!v4) {
-      note_error("pre-split contraction M=%d N=%d: operands must be k-contiguous, 4-element "
-                 "aligned, with scale 1", d.M, d.N);
-      return hipErrorInvalidValue;
-    }
-    tile = kTileSplitV;
-  }
   // FP64 with 160 x 160 tiles when the cost model (rounds of one workgroup per
   // CU x slices, plus partial sums) prefers them
   auto model = [&](int t, int ns) {
@@ -1613,7 +1540,7 @@ hipError_t gett(const GemmDesc &din, hipStream_t stream) {
     }
     std::lock_guard<std::mutex> lock(g_records_mu);
     // split-bf16 products are timed in a bucket of their own (one arithmetic, one peak)
-    const bool split_products = d.prec == Prec::F32S || d.prec == Prec::F64S || d.prec == Prec::P3 ||
+    const bool split_products = d.prec == Prec::F32S || d.prec == Prec::F64S ||
                                 tile == kTileSplit || tile == kTileSplit160 ||
                                 tile == kTileSplitV;
     g_records.push_back(Record{split_products ? Kind::Split : d.kind, ev[0], ev[1],

@@ -55,11 +55,7 @@ hipError_t scatter_vec(const double *x, int64_t o, int64_t v, double *t1, double
 
 // Particle-particle ladder through (ij)-symmetric / antisymmetric rows.
 // type: 0 double, 1 float, 2 bf16 (round to nearest even)
-// type 0 double, 1 float, 2 bf16, 3 the three bf16 planes of the split products
-// (plane q at q o^2 v^2 elements)
 hipError_t pack_t(const double *t2, int64_t o, int64_t v, void *Tsa, int type, hipStream_t s);
-// plane q of element e of x at P[q ps + e] (the split of the split-bf16 products)
-hipError_t split_planes(const float *x, int64_t n, uint16_t *P, int64_t ps, hipStream_t s);
 hipError_t convert(const double *in, int64_t n, void *out, int type, hipStream_t s);
 // SA rows of ld entries; ca == 0: entry P = a v + b; ca > 0: the stored-ladder
 // order of blocks of ca values of a (see the kernel).

@@ -383,41 +383,6 @@ __global__ void k_pack_t(const double *__restrict__ t2, int64_t o, int64_t v, T 
   }
 }
 
-// The same rows as three bf16 planes of the split products (type 3 of pack_t):
-// plane q of element e at P[q * ps + e], ps = o^2 v^2.
-__global__ void k_pack_t_planes(const double *__restrict__ t2, int64_t o, int64_t v,
-                                uint16_t *P) {
-  const int64_t vv = v * v, total = o * o * vv, op = o * (o + 1) / 2;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t i, j, c, d;
-    split4(e, o, v, i, j, c, d);
-    if (i > j) continue;
-    const int64_t ij = i * o + j, cd = c * v + d;
-    const double x = t2[e], y = t2[ij * vv + d * v + c];
-    uint16_t h, m, l;
-    int64_t r = tri(j, i) * vv + cd;
-    split3_bf16((float)(x + y), h, m, l);
-    P[r] = h; P[total + r] = m; P[2 * total + r] = l;
-    if (i < j) {
-      r = (op + stri(j, i)) * vv + cd;
-      split3_bf16((float)(x - y), h, m, l);
-      P[r] = h; P[total + r] = m; P[2 * total + r] = l;
-    }
-  }
-}
-
-// FP32 values -> the three bf16 planes of the split products, plane q of element
-// e at P[q * ps + e].
-__global__ void k_split_planes(const float *__restrict__ x, int64_t n, uint16_t *P, int64_t ps) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    uint16_t h, m, l;
-    split3_bf16(x[e], h, m, l);
-    P[e] = h; P[ps + e] = m; P[2 * ps + e] = l;
-  }
-}
-
 // R2[i][j][a][b] += (S_ij^ab + A_ij^ab) / 2 from SA[r][P(a, b)] (a >= b), where
 // rows r < o(o+1)/2 hold S (symmetric in ij and ab) and the rest A
 // (antisymmetric in both).  ca == 0: P = a v + b, rows of v^2; ca > 0: the
@@ -787,18 +752,7 @@ hipError_t pack_t(const double *t2, int64_t o, int64_t v, void *Tsa, int type, h
   const dim3 g(ew_blocks(o * o * v * v)), b(kEwThreads);
   if (type == 1) hipLaunchKernelGGL(k_pack_t<float>, g, b, 0, s, t2, o, v, (float *)Tsa);
   else if (type == 2) hipLaunchKernelGGL(k_pack_t<uint16_t>, g, b, 0, s, t2, o, v, (uint16_t *)Tsa);
-  else if (type == 3) hipLaunchKernelGGL(k_pack_t_planes, g, b, 0, s, t2, o, v, (uint16_t *)Tsa);
   else hipLaunchKernelGGL(k_pack_t<double>, g, b, 0, s, t2, o, v, (double *)Tsa);
-  return hipGetLastError();
-}
-hipError_t split_planes(const float *x, int64_t n, uint16_t *P, int64_t ps, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  if (!region_ok(x, (size_t)n * 4) || !region_ok(P, (size_t)(2 * ps + n) * 2)) {
-    note_error("bf16 plane split of %lld values leaves its buffers; not launched", (long long)n);
-    return hipErrorInvalidValue;
-  }
-  if (dry_run()) return hipSuccess;
-  hipLaunchKernelGGL(k_split_planes, dim3(ew_blocks(n)), dim3(kEwThreads), 0, s, x, n, P, ps);
   return hipGetLastError();
 }
 hipError_t convert(const double *in, int64_t n, void *out, int type, hipStream_t s) {

@@ -48,9 +48,6 @@ struct Layout {
   bool lstore = false;
   void *Lst = nullptr;              // (ac|bd) blocks [a in block][b < a1][c][d], ladder precision
   int64_t lrows = 0;                // rows (a, b < a1) of all stored blocks
-  bool lplanes = false;             // FP32 mode: Lst and Tsa held as the three bf16 planes of
-                                    // the split products (formed once per solve / iteration)
-  float *lstage = nullptr;          // lplanes: one block of (ac|bd) in FP32 before its split
   double *Gkc = nullptr;            // (kc|bd) [k][c][b][d]
   double *Zl = nullptr, *Yl = nullptr, *Wl = nullptr;   // [ij][k][b], [ij][k][b], [ij][k][l]
   double *Bvv_lp = nullptr;         // bare B_vv in the ladder precision

@@ -144,19 +144,12 @@ void plan_layout(const Dims &dm, const lnocc_options_t &opt, char *base, Layout 
       blk += na * (a0 + na) * vv;
     }
     L.lrows = blk / vv;
-    // FP32 mode: the stored ladder and the rows as pre-split bf16 planes when the
-    // 4 x 4-staged kernel can read them (every extent a multiple of 4)
-    const bool planes = L.lp == Prec::F32 && vv % 4 == 0 && oo % 4 == 0 && L.lrows % 4 == 0;
-    const size_t lesz = planes ? 6 : esz;
-    const size_t need = (size_t)blk * lesz + (size_t)(o * vvv + 2 * o * oo * v + oo * oo) * 8 +
-                        (L.lp != Prec::F64 ? (size_t)X * vv * esz : 0) +
-                        (planes ? (size_t)L.chunk_a * vvv * 4 : 0);
+    const size_t need = (size_t)blk * esz + (size_t)(o * vvv + 2 * o * oo * v + oo * oo) * 8 +
+                        (L.lp != Prec::F64 ? (size_t)X * vv * esz : 0);
     L.lstore = opt.ladder_mode == LNOCC_LADDER_STORED ||
                (opt.ladder_mode == LNOCC_LADDER_AUTO && need <= ((size_t)32 << 30));
     if (L.lstore) {
-      L.lplanes = planes;
-      L.Lst = A.d((int64_t)(((size_t)blk * lesz + 7) / 8));
-      if (planes) L.lstage = (float *)A.d((int64_t)((L.chunk_a * vvv * 4 + 7) / 8));
+      L.Lst = A.d((int64_t)(((size_t)blk * esz + 7) / 8));
       L.Gkc = A.d(o * vvv);
       L.Zl = A.d(oo * ov);
       L.Yl = A.d(oo * ov);
@@ -256,23 +249,16 @@ int build_stored_ladder(const Layout &L, hipStream_t s) {
     bvv = (const char *)L.Bvv_lp;
   }
   char *dst = (char *)L.Lst;
-  int64_t done = 0;   // elements of the blocks formed so far
   for (int64_t a0 = 0; a0 < v; a0 += L.chunk_a) {
     const int64_t na = std::min<int64_t>(L.chunk_a, v - a0), a1 = a0 + na;
-    // the planes layout forms each block in FP32 first, then splits it
-    double *out = L.lplanes ? (double *)L.lstage : (double *)dst;
-    GemmDesc d = DESC(na * v, v, a1 * v, v, out, a1 * vv, v, vv, 1, 0.0);
+    GemmDesc d = DESC(na * v, v, a1 * v, v, (double *)dst, a1 * vv, v, vv, 1, 0.0);
     SEG(d, X, 1, 1.0, OP((const double *)(bvv + a0 * v * esz), v, 1, vv, 0),
         OP((const double *)bvv, v, 1, vv, 0));
     d.kind = Kind::LadderBuild;
     d.prec = L.lp;
     d.c_type = L.lpt;
     LN_TRY(gett(d, s));
-    if (L.lplanes)
-      LN_TRY(split_planes(L.lstage, na * a1 * vv, (uint16_t *)L.Lst + done, L.lrows * vv, s));
-    else
-      dst += (size_t)na * a1 * vv * esz;
-    done += na * a1 * vv;
+    dst += (size_t)na * a1 * vv * esz;
   }
   {  // Gkc[k][c][b][d] = (kc|bd)
     GemmDesc d = DESC(ov, 1, vv, 1, L.Gkc, vv, 0, 1, 0, 0.0);
@@ -454,7 +440,7 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
   // that precision; products accumulate in FP32 per tile and SA stays FP64.
   const bool lowp = L.lp != Prec::F64;
   const size_t esz = ladder_esz(L);
-  LN_TRY(pack_t(t2, o, v, L.Tsa, L.lplanes ? 3 : L.lpt, s));
+  LN_TRY(pack_t(t2, o, v, L.Tsa, L.lpt, s));
   if (L.lstore) {
     // Bare integrals: B~_ac = B_ac - sum_k t_k^a B_kc makes
     // (ac|bd)~ = (ac|bd) - t_k^a (kc|bd) - t_l^b (ac|ld) + t_k^a t_l^b (kc|ld), so
@@ -465,12 +451,9 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     // SA[r][row] = sum_cd Tsa[r][cd] (ac|bd)[row][cd]
     {
       GemmDesc d = DESC(L.lrows, 1, oo, 1, L.SA, 1, 0, L.lrows, 0, 0.0);
-      GOperand la = OP((const double *)L.Lst, vv, 0, 1, 0), lb = OP(L.Tsa, vv, 0, 1, 0);
-      la.ps = L.lrows * vv;   // plane strides (read only in the planes layout)
-      lb.ps = oo * vv;
-      SEG(d, vv, 1, 1.0, la, lb);
+      SEG(d, vv, 1, 1.0, OP((const double *)L.Lst, vv, 0, 1, 0), OP(L.Tsa, vv, 0, 1, 0));
       d.kind = Kind::LadderContract;
-      d.prec = L.lplanes ? Prec::P3 : L.lp;
+      d.prec = L.lp;
       LN_TRY(run(d));
     }
     LN_TRY(unpack_ladder(L.SA, o, v, L.chunk_a, L.lrows, L.R2, s));

@@ -21,7 +21,7 @@ LNOCC_ENOMEM = -2
 LNOCC_EDEVICE = -3
 LNOCC_ENUMERIC = -4
 
-LNOCC_FP64, LNOCC_FP32, LNOCC_BF16, LNOCC_FP32_SPLIT, LNOCC_FP64_SPLIT, LNOCC_FP32_PLANES = 0, 1, 2, 3, 4, 5
+LNOCC_FP64, LNOCC_FP32, LNOCC_BF16, LNOCC_FP32_SPLIT, LNOCC_FP64_SPLIT = 0, 1, 2, 3, 4
 LNOCC_GUESS_MP2, LNOCC_GUESS_USER, LNOCC_GUESS_MLP = 0, 1, 2
 LNOCC_MLP_FEATURES, LNOCC_MLP_HIDDEN, LNOCC_MLP_HEADER, LNOCC_MLP_PARAMS = 16, 256, 64, 136256
 LNOCC_MLP_BLOB = LNOCC_MLP_HEADER + LNOCC_MLP_PARAMS
@@ -65,7 +65,7 @@ class lnocc_options_t(C.Structure):
 class lnocc_operand_t(C.Structure):
     _fields_ = [("p", C.c_void_p), ("s_ro", C.c_int64), ("s_ri", C.c_int64),
                 ("s_ko", C.c_int64), ("s_ki", C.c_int64), ("b0", C.c_int64),
-                ("b1", C.c_int64), ("bid", C.c_int64), ("ps", C.c_int64)]
+                ("b1", C.c_int64), ("bid", C.c_int64)]
 
 
 class lnocc_contract_t(C.Structure):

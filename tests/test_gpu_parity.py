@@ -323,75 +323,6 @@ def test_contract_split_v4_layouts(precision, tile):
     assert err < 2e-6 * np.sqrt(K1 + K2)
 
 
-def _bf16_rne(x):
-    """float32 -> bf16 bit patterns, round to nearest even (finite inputs)."""
-    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
-
-
-def _bf16_value(h):
-    return (h.astype(np.uint32) << 16).view(np.float32)
-
-
-def _planes(x):
-    """The three bf16 planes of the split products: h = bf16(x), m = bf16(x - h),
-    l = bf16(x - h - m), the differences exact in float32."""
-    x = np.asarray(x, dtype=np.float32)
-    h = _bf16_rne(x)
-    r1 = (x - _bf16_value(h)).astype(np.float32)
-    m = _bf16_rne(r1)
-    r2 = (r1 - _bf16_value(m)).astype(np.float32)
-    return np.stack([h, m, _bf16_rne(r2)])
-
-
-def test_planes_of_the_host_split_are_exact():
-    """h + m + l reproduces x to 2^-24 relative, each part a bf16 value."""
-    x = np.random.default_rng(3).standard_normal(4096).astype(np.float32)
-    P = _planes(x).astype(np.uint32) << 16
-    s = sum(p.view(np.float32).astype(np.float64) for p in P)
-    assert np.abs(s - x).max() <= 2.0 ** -24 * np.abs(x).max()
-
-
-@pytest.mark.parametrize("M,N,K,nb", [(260, 132, 200, 1), (128, 256, 96, 2), (4, 8, 4, 1)])
-def test_contract_presplit_planes_equal_split(M, N, K, nb):
-    """LNOCC_FP32_PLANES on operands split on the host gives the very bits of
-    LNOCC_FP32_SPLIT on the FP32 values (same products, same tiles), with a batch,
-    beta and ragged M, N and K; and the planes layout is refused (EINVAL) where the
-    staged kernel cannot read it."""
-    say(f"contract presplit planes M={M} N={N} K={K} batch {nb}")
-    rng = np.random.default_rng(M + 7 * N + K)
-    A = rng.standard_normal((nb, M, K)).astype(np.float32)
-    B = rng.standard_normal((nb, N, K)).astype(np.float32)
-    C0 = rng.standard_normal((nb, M, N))
-    PA = np.ascontiguousarray(np.stack([_planes(A[e]) for e in range(nb)], axis=1))   # [3][nb][M][K]
-    PB = np.ascontiguousarray(np.stack([_planes(B[e]) for e in range(nb)], axis=1))
-    tA, tB = torch.tensor(A, device=DEV), torch.tensor(B, device=DEV)
-    tPA = torch.tensor(PA.view(np.int16), device=DEV)
-    tPB = torch.tensor(PB.view(np.int16), device=DEV)
-    out = []
-    for prec, a, b in [(3, tA, tB), (5, tPA, tPB)]:
-        c = dev(C0)
-        oa = _operand(a, K, 0, 1, 0, bid=M * K)
-        ob = _operand(b, K, 0, 1, 0, bid=N * K)
-        oa.ps, ob.ps = nb * M * K, nb * N * K
-        _contract(M, 1, N, 1, c, (N, 0, 1, 0), [(K, 1, 1.0, oa, ob)], beta=0.5, batch=nb,
-                  cb=(0, 0, M * N), precision=prec, tile=10)
-        out.append(host(c))
-    assert np.array_equal(out[0], out[1])
-    ref = np.einsum("emk,enk->emn", A.astype(np.float64), B.astype(np.float64)) + 0.5 * C0
-    assert np.abs(out[1] - ref).max() / np.abs(ref).max() < 2e-6 * np.sqrt(K)
-    # K not a multiple of 4: refused, nothing launched
-    d = L.lnocc_contract_t()
-    d.M, d.Mi, d.N, d.Ni, d.nseg = M, 1, N, 1, 1
-    d.K[0], d.Ki[0], d.scale[0] = K - 1, 1, 1.0
-    d.a[0] = L.lnocc_operand_t(tPA.data_ptr(), K, 0, 1, 0, 0, 0, 0, nb * M * K)
-    d.b[0] = L.lnocc_operand_t(tPB.data_ptr(), K, 0, 1, 0, 0, 0, 0, nb * N * K)
-    c = dev(C0[0])
-    d.c, d.c_mo, d.c_no = c.data_ptr(), N, 1
-    d.beta, d.batch, d.nb1, d.precision = 0.0, 1, 1, 5
-    assert L.lnocc_contract(d, torch.cuda.current_stream().cuda_stream) == L.LNOCC_EINVAL
-
-
 @pytest.mark.parametrize("tile", [0, 1, 3])
 def test_contract_fp64_split_accuracy(tile):
     """LNOCC_FP64_SPLIT on full-mantissa FP64 operands (the arithmetic of the
