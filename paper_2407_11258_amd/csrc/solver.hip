@@ -844,6 +844,7 @@ int CcsdRun::after_iteration() {
       count = 0;
       growth = 0;
       prev = best = r_mp2;
+      if (opt.on_iter) opt.on_iter(in.frag, it, out.e_mp2, out.residual, opt.user);
       if (r_mp2 <= in.conv_tol) phase = Phase::Converged;
       else if (it >= opt.max_iter) phase = Phase::Exhausted;
       return LNOCC_OK;
