@@ -422,7 +422,7 @@ def run_batch(args, L, torch, leg: bool = False) -> dict:
 def main() -> int:
     args = parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(fragments would be sharded across GPUs with no exchange but the final "
               "energies); run with --gpus 1.", file=sys.stderr)
         return 2
