@@ -20,6 +20,9 @@ inline int64_t triples_partials_capacity(int64_t) { return kTriplesEnergyGrid; }
 hipError_t split_B(const double *B, int64_t X, int64_t o, int64_t v,
                    double *Boo, double *Bov, double *Bvv, hipStream_t s);
 hipError_t diag_sum(const double *Boo, int64_t X, int64_t o, double *J, hipStream_t s);
+// Bt[Q][a][b] = Bvv[Q][a][b] - sum_k t1[k][a] Bov[Q][k][b] (FP64, k summed in order)
+hipError_t dress_vv(const double *Bvv, const double *Bov, const double *t1, int64_t X, int64_t o,
+                    int64_t v, double *Bt, hipStream_t s);
 hipError_t add_diag(double *M, int64_t n, int64_t ld, const double *eps, hipStream_t s);
 hipError_t transpose2d(const double *in, int64_t rows, int64_t cols, double *out, hipStream_t s);
 hipError_t make_u(const double *t2, int64_t o, int64_t v, double *u, hipStream_t s);

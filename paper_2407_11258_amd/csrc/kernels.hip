@@ -329,6 +329,52 @@ __global__ void k_lincomb(const double *__restrict__ Xs, int64_t stride, int m, 
   }
 }
 
+// T1 dressing of the virtual-virtual DF block: Bt[Q][a][b] = B[Q][a][b] -
+// sum_k t1[k][a] Bov[Q][k][b].  A block takes kDressRows rows a of one Q, with
+// their t1 columns in LDS; a thread owns columns b and subtracts the o terms in
+// order of k (each Bov element is loaded once per block and used for every row).
+constexpr int kDressRows = 16;
+__global__ __launch_bounds__(kEwThreads) void k_dress_vv(const double *__restrict__ Bvv,
+                                                         const double *__restrict__ Bov,
+                                                         const double *__restrict__ t1, int64_t o,
+                                                         int64_t v, double *__restrict__ Bt) {
+  extern __shared__ double tcol[];   // [k][r]
+  const int64_t Q = blockIdx.y, a0 = (int64_t)blockIdx.x * kDressRows;
+  const int nr = (int)min<int64_t>(kDressRows, v - a0);
+  for (int64_t e = threadIdx.x; e < o * kDressRows; e += blockDim.x) {
+    const int64_t k = e / kDressRows, r = e % kDressRows;
+    tcol[e] = r < nr ? t1[k * v + a0 + r] : 0.0;
+  }
+  __syncthreads();
+  const double *B = Bvv + (Q * v + a0) * v, *Bk = Bov + Q * o * v;
+  double *out = Bt + (Q * v + a0) * v;
+  for (int64_t b = threadIdx.x; b < v; b += blockDim.x) {
+    double acc[kDressRows];
+#pragma unroll
+    for (int r = 0; r < kDressRows; ++r) acc[r] = r < nr ? B[r * v + b] : 0.0;
+    // the Bov loads of eight k are issued together (independent of the FMAs)
+    int64_t k = 0;
+    for (; k + 8 <= o; k += 8) {
+      double x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x[q] = Bk[(k + q) * v + b];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int r = 0; r < kDressRows; ++r)
+          acc[r] = fma(-tcol[(k + q) * kDressRows + r], x[q], acc[r]);
+    }
+    for (; k < o; ++k) {
+      const double x = Bk[k * v + b];
+#pragma unroll
+      for (int r = 0; r < kDressRows; ++r) acc[r] = fma(-tcol[k * kDressRows + r], x, acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kDressRows; ++r)
+      if (r < nr) out[r * v + b] = acc[r];
+  }
+}
+
 __global__ void k_scatter(const double *__restrict__ x, int64_t o, int64_t v, double *t1,
                           double *t2) {
   const int64_t n1 = o * v, total = n1 + o * o * v * v;
@@ -633,6 +679,23 @@ hipError_t split_B(const double *B, int64_t X, int64_t o, int64_t v, double *Boo
   const int64_t n = o + v;
   hipLaunchKernelGGL(k_split_B, dim3(ew_blocks(X * n * n)), dim3(kEwThreads), 0, s, B, X, o, v,
                      Boo, Bov, Bvv);
+  return hipGetLastError();
+}
+hipError_t dress_vv(const double *Bvv, const double *Bov, const double *t1, int64_t X, int64_t o,
+                    int64_t v, double *Bt, hipStream_t s) {
+  if (X < 1 || o < 1 || v < 1) return hipErrorInvalidValue;
+  if (!region_ok(Bvv, (size_t)(X * v * v * 8)) || !region_ok(Bt, (size_t)(X * v * v * 8)) ||
+      !region_ok(Bov, (size_t)(X * o * v * 8)) || !region_ok(t1, (size_t)(o * v * 8))) {
+    note_error("T1 dressing of B_vv (nocc %lld, nvir %lld, naux %lld) leaves its buffers",
+               (long long)o, (long long)v, (long long)X);
+    return hipErrorInvalidValue;
+  }
+  if (dry_run()) return hipSuccess;
+  const dim3 g((unsigned)((v + kDressRows - 1) / kDressRows), (unsigned)X);
+  // one thread per column b up to 256 (whole waves), so few lanes idle at small v
+  const unsigned threads = (unsigned)std::min<int64_t>(kEwThreads, (v + 63) / 64 * 64);
+  hipLaunchKernelGGL(k_dress_vv, g, dim3(threads), (size_t)o * kDressRows * 8, s, Bvv, Bov, t1,
+                     o, v, Bt);
   return hipGetLastError();
 }
 hipError_t diag_sum(const double *Boo, int64_t X, int64_t o, double *J, hipStream_t s) {

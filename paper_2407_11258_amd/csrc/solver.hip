@@ -361,13 +361,8 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
     SEG(d, v, 1, 1.0, OPB(OP(L.Bov, v, 0, 1, 0), ov, 0, 0), OP(t1, v, 0, 1, 0));
     LN_TRY(run(d));
   }
-  {  // B~_ab = B_ab - sum_k t_k^a B_kb
-    GemmDesc d = DESC(v, 1, v, 1, L.Btvv, v, 0, 1, 0, 1.0);
-    d.c_src = L.Bvv;
-    BATCH_Q(d, X, vv);
-    SEG(d, o, 1, -1.0, OP(t1, 1, 0, v, 0), OPB(OP(L.Bov, 1, 0, v, 0), ov, 0, 0));
-    LN_TRY(run(d));
-  }
+  // B~_ab = B_ab - sum_k t_k^a B_kb (a rank-nocc update of every B_Q: bandwidth-bound)
+  LN_TRY(dress_vv(L.Bvv, L.Bov, t1, X, o, v, L.Btvv, s));
   {  // B~_ai = B_ai + sum_b B_ab t_i^b - sum_k t_k^a B~_ki, stored [Q][i][a]
     GemmDesc d = DESC(o, 1, v, 1, L.Btai, v, 0, 1, 0, 1.0);
     d.c_src = L.Bov;
