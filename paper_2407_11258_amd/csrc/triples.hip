@@ -98,6 +98,32 @@ struct TripleArgs {
   int tiles_m, tiles_n;
 };
 
+// Output rows of a launch.  Orientation 2 in the blocked layout enumerates its
+// (m1, m2) = (b, c) pairs in 8 x 8 blocks, (b % 8, c % 8) fastest, so that 64
+// consecutive rows at one column a are one contiguous 64-element run of W; pairs
+// with b or c >= v (padding) are computed from clamped rows and never stored.
+__device__ inline bool blocked_rows(const TripleArgs &A) { return A.blocked && A.ori == 2; }
+__device__ inline int64_t row_count(const TripleArgs &A) {
+  const int64_t v = A.v, vt = (v + 7) / 8;
+  return blocked_rows(A) ? vt * vt * 64 : v * v;
+}
+// (m1, m2) of row r; false for a padding row (then clamped into range)
+__device__ inline bool row_pair(const TripleArgs &A, int64_t r, int64_t &m1, int64_t &m2) {
+  const int64_t v = A.v;
+  if (!blocked_rows(A)) {
+    m1 = r / v;
+    m2 = r % v;
+    return true;
+  }
+  const int64_t vt = (v + 7) / 8, blk = r >> 6;
+  m1 = (blk / vt) * 8 + ((r >> 3) & 7);
+  m2 = (blk % vt) * 8 + (r & 7);
+  const bool ok = m1 < v && m2 < v;
+  m1 = min(m1, v - 1);
+  m2 = min(m2, v - 1);
+  return ok;
+}
+
 // Offset within one triple's W of index x in position role (0: a, 1: b, 2: c).
 __device__ inline int64_t w_offset(const TripleArgs &A, int role, int64_t x) {
   const int64_t v = A.v;
@@ -132,7 +158,7 @@ void k_triples_w(TripleArgs A) {
   int tm, tn;
   xcd_tile(blockIdx.x, A.tiles_m, A.tiles_n, tm, tn);
   const int64_t v = A.v, vp = A.vp, o = A.o, vv = v * v;
-  const int64_t nrows = vv;
+  const int64_t nrows = row_count(A);
   const int64_t r0 = (int64_t)tm * BM;
   const int n0 = tn * kBN;
   const int entry = blockIdx.y;
@@ -159,7 +185,8 @@ void k_triples_w(TripleArgs A) {
 #pragma unroll
   for (int s = 0; s < P::PA; ++s) {
     const int64_t gr = min(r0 + t / P::TPR + s * P::RPP, nrows - 1);
-    const int64_t m1 = gr / v, m2 = gr % v;
+    int64_t m1, m2;
+    row_pair(A, gr, m1, m2);
     pa_flat[s] = (uint32_t)(((m1 * v + m2) * vp + kq) * (int64_t)sizeof(E));
     pa_swap[s] = (uint32_t)(((m2 * v + m1) * vp + kq) * (int64_t)sizeof(E));
   }
@@ -174,7 +201,8 @@ void k_triples_w(TripleArgs A) {
   uint32_t ha_flat, ha_swap;
   {
     const int64_t gr = min(r0 + t % BM, nrows - 1);
-    const int64_t m1 = gr / v, m2 = gr % v;
+    int64_t m1, m2;
+    row_pair(A, gr, m1, m2);
     ha_flat = (uint32_t)(m1 * vp + m2);
     ha_swap = (uint32_t)(m2 * vp + m1);
   }
@@ -327,7 +355,9 @@ void k_triples_w(TripleArgs A) {
   else { role1 = 1; role2 = 2; role3 = 0; }
   for (int x = t; x < BM; x += kThreads) {
     const int64_t gr = r0 + x;
-    rowoff[x] = gr < nrows ? w_offset(A, role1, gr / v) + w_offset(A, role2, gr % v) : -1;
+    int64_t m1, m2;
+    const bool ok = gr < nrows && row_pair(A, gr, m1, m2);
+    rowoff[x] = ok ? w_offset(A, role1, m1) + w_offset(A, role2, m2) : -1;
   }
   for (int x = t; x < kBN; x += kThreads) coloff[x] = n0 + x < v ? w_offset(A, role3, n0 + x) : -1;
   E *Cs = smem;
@@ -449,7 +479,9 @@ hipError_t triples_w(const void *G, const void *T, const void *J, void *W, const
   a.nterms = nterms;
   a.blocked = blocked ? 1 : 0;
   constexpr int bm = 128;
-  a.tiles_m = (int)((v * v + bm - 1) / bm);
+  const int64_t vt = (v + 7) / 8;
+  const int64_t rows = (a.blocked && ori == 2) ? vt * vt * 64 : v * v;   // see row_count
+  a.tiles_m = (int)((rows + bm - 1) / bm);
   a.tiles_n = (int)((v + kBN - 1) / kBN);
   if (dry_run()) return hipSuccess;
   const dim3 grid((unsigned)(a.tiles_m * a.tiles_n), (unsigned)nb);
