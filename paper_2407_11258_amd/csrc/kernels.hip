@@ -537,7 +537,7 @@ __device__ inline int pair_index(int u1, int u2) { return 2 * u1 + (u2 > u1 ? u2
 // fetched by one L2.  Each block adds the weighted sums of its items and writes
 // one partial.
 template <typename TW, int SYM>
-__global__ __launch_bounds__(kRedThreads) void k_triples_energy(
+__global__ __launch_bounds__(kRedThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_triples_energy(
     const TW *__restrict__ Wall, const int *__restrict__ table, int nb,
     const double *__restrict__ Kov, const double *__restrict__ t1, const double *__restrict__ eo,
     const double *__restrict__ ev, int o, int v, double *partials) {
@@ -596,13 +596,26 @@ __global__ __launch_bounds__(kRedThreads) void k_triples_energy(
     }
     __syncthreads();   // the previous item's reads of LDS are done
     TileLoad<TW>::run(W, v, vt, mask, c, L);
-    // integral blocks: kind 0 (ia|jb) = Kov[i][a][j][b], 1 (ia|kc), 2 (jb|kc)
-    for (int e = t; e < 3 * 6 * TT * TT; e += kRedThreads) {
-      const int kind = e / (6 * TT * TT), pr = (e / (TT * TT)) % 6, r = (e / TT) % TT, q = e % TT;
-      const int u1 = pr / 2, u2r = pr % 2, u2 = u2r < u1 ? u2r : u2r + 1;
-      const int m1 = kind == 2 ? j : i, m2 = kind == 0 ? j : k;
-      const int x1 = min(8 * c[u1] + r, v - 1), x2 = min(8 * c[u2] + q, v - 1);
-      K[kind][pr][r * TT + q] = Kov[(((int64_t)m1 * v + x1) * o + m2) * v + x2];
+    // integral blocks: kind 0 (ia|jb) = Kov[i][a][j][b], 1 (ia|kc), 2 (jb|kc); every
+    // load of a thread is issued before the first store
+    constexpr int KN = 3 * 6 * TT * TT, KPT = (KN + kRedThreads - 1) / kRedThreads;
+    double kv[KPT];
+#pragma unroll
+    for (int n = 0; n < KPT; ++n) {
+      const int e = t + n * kRedThreads;
+      if (e < KN) {
+        const int kind = e / (6 * TT * TT), pr = (e / (TT * TT)) % 6, r = (e / TT) % TT,
+                  q = e % TT;
+        const int u1 = pr / 2, u2r = pr % 2, u2 = u2r < u1 ? u2r : u2r + 1;
+        const int m1 = kind == 2 ? j : i, m2 = kind == 0 ? j : k;
+        const int x1 = min(8 * c[u1] + r, v - 1), x2 = min(8 * c[u2] + q, v - 1);
+        kv[n] = Kov[(((int64_t)m1 * v + x1) * o + m2) * v + x2];
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < KPT; ++n) {
+      const int e = t + n * kRedThreads;
+      if (e < KN) (&K[0][0][0])[e] = kv[n];
     }
     if (t < 3 * 3 * TT) {
       const int m = t / (3 * TT), u = (t / TT) % 3, r = t % TT;
