@@ -1027,10 +1027,12 @@ int enqueue_triples(const Layout &L, const Inputs &in, hipStream_t s, bool autot
   }
   const int ttype = L.t_f32 ? 1 : 0;
   if (vp > v) LN_TRY(dzero(L.Gt, (size_t)(ov * v * vp * tes), s));
-  {  // Gt[i][a][b][d] = (ai|bd), d padded to vp
+  {  // Gt[i][a][b][d] = (ai|bd), d padded to vp; stored in FP32 in the reduced modes,
+     // so formed there by split-bf16 products (FP32-level accuracy) from the FP64 factors
     GemmDesc d = DESC(ov, 1, vv, v, L.Gt, v * vp, 0, vp, 1, 0.0);
     SEG(d, X, 1, 1.0, OP(L.Bov, 1, 0, ov, 0), OP(L.Bvv, v, 1, vv, 0));
     d.c_type = ttype;
+    if (ttype == 1) d.prec = Prec::F64S;
     LN_TRY(gett(d, s));
   }
   {  // Jt[j][k][c][l] = (ck|jl)
