@@ -14,7 +14,10 @@ further solve, outside the timed region, runs with per-launch HIP events on
 the solve's stream; it gives the per-class kernel times and the roofline
 position of the dominant contraction kernel.
 
-Two further legs are added to the same JSON line (each can be switched off):
+Three further legs are added to the same JSON line (each can be switched off):
+  ladder_on_the_fly  the same fragment with the particle-particle ladder formed
+                 on the fly from the dressed B~_vv in every iteration (the path of
+                 fragments whose stored ladder does not fit in memory);
   large_triples  (T) at the large fragment's full size (nocc=32, nvir=400,
                  naux=1300, seed 4) on the MP1 amplitudes, mixed and FP64, with
                  the algorithmic rate 2 o^3 v^4 + 2 o^4 v^3 over the wall time;
@@ -120,6 +123,10 @@ def parse_args():
                     help="timed repetitions of (T) alone on the converged amplitudes")
     ap.add_argument("--large-triples", type=int, default=1,
                     help="add the large-fragment (T) leg (mixed and FP64, about 90 s)")
+    ap.add_argument("--otf-leg", type=int, default=2, metavar="STEPS",
+                    help="add the on-the-fly ladder leg (the single fragment solved with the "
+                         "ladder formed from B~_vv every iteration) with this many timed steps; "
+                         "0 = off")
     ap.add_argument("--batch-leg", type=int, default=1,
                     help="add the batched-workload leg (mixed batch vs sequential FP64)")
     ap.add_argument("--plans", default="",
@@ -178,10 +185,10 @@ def run_single(args, L, torch) -> dict:
     t2 = torch.empty((o, o, v, v), dtype=torch.float64, device=dev)
     ws = L.Workspace(dev)
 
-    def timed(precision: str, steps: int, warmup: int):
+    def timed(precision: str, steps: int, warmup: int, ladder: str = "auto"):
         opt = L.make_options(precision=precision, level_shift=args.level_shift,
                              diis_start=args.diis_start, diis_space=args.diis_space,
-                             max_iter=args.max_iter,
+                             max_iter=args.max_iter, ladder=ladder,
                              autotune=bool(args.autotune))
         fs = L.make_fragment_struct(B, eo, ev, t1, t2, args.conv_tol)
         ws.attach([fs], opt)
@@ -260,6 +267,19 @@ def run_single(args, L, torch) -> dict:
                                        "d_e_t": ft64.e_t - golden["e_t"]}
         res["fp64"] = cmp
         res["speedup_vs_fp64"] = res["value"] / cmp["value"]
+    if args.otf_leg:
+        # the same solve with the particle-particle ladder formed on the fly from
+        # B~_vv every iteration (the path of fragments whose stored ladder does not fit)
+        fo, _, elo, profo = timed(args.precision, args.otf_leg, 1, ladder="on_the_fly")
+        leg = {"value": args.otf_leg / elo, "unit": "solves/s", "ladder": "on_the_fly",
+               "ms_per_step": 1e3 * elo / args.otf_leg, "precision": args.precision,
+               "ccsd_iterations": fo.n_iter, "e_ccsd": fo.e_ccsd, "e_t": fo.e_t,
+               "kernels": kernel_table(profo),
+               "roofline": roofline(profo, args.precision, args.workload)}
+        if golden:
+            leg["parity_vs_oracle"] = {"d_e_ccsd": fo.e_ccsd - golden["e_ccsd"],
+                                       "d_e_t": fo.e_t - golden["e_t"]}
+        res["ladder_on_the_fly"] = leg
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         res["cpu_baseline"] = cpu_baseline(frag, fs.n_iter)

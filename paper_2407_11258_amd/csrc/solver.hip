@@ -491,7 +491,8 @@ int ccsd_residuals(const Layout &L, const double *t1, const double *t2, hipStrea
       SEG(d, X, 1, 1.0, OP((const double *)(bvv + a0 * v * esz), v, 1, vv, 0),
           OP((const double *)bvv, v, 1, vv, 0));
       d.kind = Kind::LadderBuild;
-      d.prec = L.lp;
+      // FP32 mode: split-bf16 products (FP32-level accuracy at bf16 matrix-core rates)
+      d.prec = L.lp == Prec::F32 ? Prec::F32S : L.lp;
       d.c_type = L.lpt;
       LN_TRY(run(d));
       // SA[r][a][b] = sum_cd Tsa[r][cd] g[a][b][cd], rows (a, b < a1) of the block
