@@ -414,18 +414,37 @@ __global__ void k_convert(const double *__restrict__ in, int64_t n, T *out) {
     out[e] = to_lp<T>(in[e]);
 }
 
+// Ladder rows: S_ij^cd = t_ij^cd + t_ij^dc at row tri(j, i) and, for i < j,
+// A_ij^cd = t_ij^cd - t_ij^dc at row o(o+1)/2 + stri(j, i).  A block takes one
+// pair i <= j and one 32 x 32 (c0, d0) tile; both t_ij[c][d] and t_ij[d][c] of the
+// tile go through LDS so that every read and write runs along the contiguous index.
 template <typename T>
 __global__ void k_pack_t(const double *__restrict__ t2, int64_t o, int64_t v, T *Tsa) {
-  const int64_t vv = v * v, total = o * o * vv, op = o * (o + 1) / 2;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t i, j, c, d;
-    split4(e, o, v, i, j, c, d);
-    if (i > j) continue;
-    const int64_t ij = i * o + j, cd = c * v + d;
-    const double x = t2[e], y = t2[ij * vv + d * v + c];
-    Tsa[tri(j, i) * vv + cd] = to_lp<T>(x + y);
-    if (i < j) Tsa[(op + stri(j, i)) * vv + cd] = to_lp<T>(x - y);
+  __shared__ double Xs[kCT][kCT + 1], Ys[kCT][kCT + 1];   // t[c0 + r][d0 + q], t[d0 + r][c0 + q]
+  const int64_t vv = v * v, op = o * (o + 1) / 2;
+  const int tiles = (int)((v + kCT - 1) / kCT);
+  const int64_t c0 = (int64_t)(blockIdx.x / tiles) * kCT, d0 = (int64_t)(blockIdx.x % tiles) * kCT;
+  for (int64_t p = blockIdx.y; p < op; p += gridDim.y) {
+    // p -> (i, j), i <= j, rows of the upper triangle in order
+    int64_t i = 0, rem = p;
+    while (rem >= o - i) { rem -= o - i; ++i; }
+    const int64_t j = i + rem;
+    const double *X = t2 + (i * o + j) * vv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kCT * kCT; e += blockDim.x) {
+      const int r = e / kCT, q = e % kCT;
+      Xs[r][q] = (c0 + r < v && d0 + q < v) ? X[(c0 + r) * v + d0 + q] : 0.0;
+      Ys[r][q] = (d0 + r < v && c0 + q < v) ? X[(d0 + r) * v + c0 + q] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kCT * kCT; e += blockDim.x) {
+      const int r = e / kCT, q = e % kCT;
+      const int64_t c = c0 + r, d = d0 + q;
+      if (c >= v || d >= v) continue;
+      const double x = Xs[r][q], y = Ys[q][r];   // t_ij^cd, t_ij^dc
+      Tsa[tri(j, i) * vv + c * v + d] = to_lp<T>(x + y);
+      if (i < j) Tsa[(op + stri(j, i)) * vv + c * v + d] = to_lp<T>(x - y);
+    }
   }
 }
 
@@ -825,9 +844,13 @@ hipError_t scatter_vec(const double *x, int64_t o, int64_t v, double *t1, double
 }
 hipError_t pack_t(const double *t2, int64_t o, int64_t v, void *Tsa, int type, hipStream_t s) {
   if (dry_run()) return hipSuccess;
-  const dim3 g(ew_blocks(o * o * v * v)), b(kEwThreads);
+  if (o == 0 || v == 0) return hipSuccess;
+  const int64_t tiles = (v + kCT - 1) / kCT, npairs = o * (o + 1) / 2;
+  const dim3 g((unsigned)(tiles * tiles), (unsigned)std::min<int64_t>(npairs, 65535)),
+      b(kEwThreads);
   if (type == 1) hipLaunchKernelGGL(k_pack_t<float>, g, b, 0, s, t2, o, v, (float *)Tsa);
-  else if (type == 2) hipLaunchKernelGGL(k_pack_t<uint16_t>, g, b, 0, s, t2, o, v, (uint16_t *)Tsa);
+  else if (type == 2)
+    hipLaunchKernelGGL(k_pack_t<uint16_t>, g, b, 0, s, t2, o, v, (uint16_t *)Tsa);
   else hipLaunchKernelGGL(k_pack_t<double>, g, b, 0, s, t2, o, v, (double *)Tsa);
   return hipGetLastError();
 }
