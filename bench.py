@@ -127,6 +127,9 @@ def parse_args():
                     help="add the on-the-fly ladder leg (the single fragment solved with the "
                          "ladder formed from B~_vv every iteration) with this many timed steps; "
                          "0 = off")
+    ap.add_argument("--ladder", default="auto", choices=["auto", "on_the_fly"],
+                    help="ladder path of the single-fragment solves (auto: stored when it "
+                         "fits; on_the_fly: formed from B~_vv every iteration)")
     ap.add_argument("--batch-leg", type=int, default=1,
                     help="add the batched-workload leg (mixed batch vs sequential FP64)")
     ap.add_argument("--plans", default="",
@@ -221,10 +224,13 @@ def run_single(args, L, torch) -> dict:
 
     if args.plans and pathlib.Path(args.plans).exists():
         log(f"loaded {L.lnocc_autotune_load(args.plans)} contraction plans")
-    fs, opt, elapsed, prof = timed(args.precision, args.steps, args.warmup)
+    fs, opt, elapsed, prof = timed(args.precision, args.steps, args.warmup, ladder=args.ladder)
+    # traffic entries are kept per ladder path (different kernels)
+    wkey = args.workload + ("_otf" if args.ladder == "on_the_fly" else "")
     res = {"value": args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
            "config": {"workload": args.workload, "nocc": o, "nvir": v, "naux": X, "seed": seed,
-                      "precision": args.precision, "conv_tol": args.conv_tol,
+                      "precision": args.precision, "ladder": args.ladder,
+                      "conv_tol": args.conv_tol,
                       "level_shift": args.level_shift, "diis_start": args.diis_start,
                       "diis_space": args.diis_space,
                       "autotune": bool(args.autotune), "ccsd_iterations": fs.n_iter,
@@ -241,7 +247,7 @@ def run_single(args, L, torch) -> dict:
     f_t = 2.0 * o ** 3 * v ** 4 + 2.0 * o ** 4 * v ** 3
     log(f"(T): {t_triples * 1e3:.1f} ms, E_(T)={ft.e_t:.12f}")
     res.update(triples_tflops=f_t / t_triples / 1e12, triples_ms=t_triples * 1e3, e_t=ft.e_t,
-               kernels=kernel_table(prof), roofline=roofline(prof, args.precision, args.workload))
+               kernels=kernel_table(prof), roofline=roofline(prof, args.precision, wkey))
     gpath = ROOT / "tests" / "golden" / f"{args.workload}.json"
     golden = json.loads(gpath.read_text()) if gpath.exists() else None
     if golden and golden.get("input_sha256") != frag.sha256():
@@ -250,7 +256,7 @@ def run_single(args, L, torch) -> dict:
         res["parity_vs_oracle"] = {"d_e_ccsd": fs.e_ccsd - golden["e_ccsd"],
                                    "d_e_t": ft.e_t - golden["e_t"]}
     if args.compare_fp64 and args.precision != "fp64":
-        f64, opt64, el64, prof64 = timed("fp64", args.steps, args.warmup)
+        f64, opt64, el64, prof64 = timed("fp64", args.steps, args.warmup, ladder=args.ladder)
     if args.save_plans:
         log(f"saved {L.lnocc_autotune_save(args.save_plans)} contraction plans")
     if args.compare_fp64 and args.precision != "fp64":
@@ -261,7 +267,7 @@ def run_single(args, L, torch) -> dict:
             raise RuntimeError(f"{L.lnocc_status_string(st)}: {L.lnocc_last_error()}")
         cmp = {"value": args.steps / el64, "unit": "solves/s", "ms_per_step": 1e3 * el64 / args.steps,
                "ccsd_iterations": f64.n_iter, "e_ccsd": f64.e_ccsd, "e_t": ft64.e_t,
-               "roofline": roofline(prof64, "fp64", args.workload)}
+               "roofline": roofline(prof64, "fp64", wkey)}
         if golden:
             cmp["parity_vs_oracle"] = {"d_e_ccsd": f64.e_ccsd - golden["e_ccsd"],
                                        "d_e_t": ft64.e_t - golden["e_t"]}
@@ -275,7 +281,7 @@ def run_single(args, L, torch) -> dict:
                "ms_per_step": 1e3 * elo / args.otf_leg, "precision": args.precision,
                "ccsd_iterations": fo.n_iter, "e_ccsd": fo.e_ccsd, "e_t": fo.e_t,
                "kernels": kernel_table(profo),
-               "roofline": roofline(profo, args.precision, args.workload)}
+               "roofline": roofline(profo, args.precision, args.workload + "_otf")}
         if golden:
             leg["parity_vs_oracle"] = {"d_e_ccsd": fo.e_ccsd - golden["e_ccsd"],
                                        "d_e_t": fo.e_t - golden["e_t"]}
